@@ -1,0 +1,307 @@
+/*
+ * mfgemm.h -- C ABI of libmfgemm, a mixed-precision GEMM library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library computes the BLAS GEMM that matrix units express,
+ *     C = alpha * A * B + beta * C                      (paper Sec. IV)
+ * with half-precision (FP16 / BF16) or FP8 operands and FP32 accumulation on
+ * the MFMA units, its batched forms (paper Sec. IV.B), and the residual-based
+ * precision refinement of paper Sec. V (Eq. R, Eq. 1, Eq. 2).
+ *
+ * Conventions shared by every call
+ *   - Matrices are row-major.  A is M x K with leading dimension lda >= K,
+ *     B is K x N with ldb >= N, C is M x N FP32 with ldc >= N.  Leading
+ *     dimensions count elements of the stored type.
+ *   - Data pointers are device pointers (HIP device memory) unless a
+ *     parameter says "host".  The caller owns every buffer it passes and must
+ *     keep it alive until the stream has passed the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls are asynchronous: they validate, enqueue and return.
+ *   - Every call returns an int status (MFG_OK or a negative MFG_ERR_*).
+ *     Arguments are validated before anything is enqueued; on error nothing
+ *     is launched and no output is touched.  No C++ exception crosses this
+ *     ABI and the library never aborts the process.  After MFG_ERR_HIP the
+ *     HIP error code is available from mfg_last_hip_error() (per thread).
+ *   - Edge cases follow BLAS: M == 0 or N == 0 is a no-op; K == 0 or
+ *     alpha == 0 gives C = beta * C; when beta == 0, C is never read (NaN or
+ *     Inf already in C do not propagate).  C must not overlap A or B.
+ *   - Calls are thread-safe.  The library keeps one workspace per
+ *     (device, stream) for the operands it converts, grown on demand with
+ *     hipMalloc and released at process exit.
+ */
+#ifndef MFGEMM_H
+#define MFGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+enum {
+    MFG_OK = 0,
+    MFG_PENDING = 1,              /* mfg_poll: request not finished yet        */
+    MFG_ERR_INVALID_ARG = -1,     /* bad size, leading dimension, pointer, mode */
+    MFG_ERR_UNSUPPORTED = -2,     /* valid request this build does not serve    */
+    MFG_ERR_NO_MEMORY = -3,       /* workspace or descriptor allocation failed  */
+    MFG_ERR_OVER_BUDGET = -4,     /* serving: request larger than the budget    */
+    MFG_ERR_HIP = -5,             /* a HIP runtime call failed                  */
+    MFG_ERR_UNKNOWN_TICKET = -6,  /* serving: ticket never issued or released   */
+    MFG_ERR_INTERNAL = -7
+};
+
+/* -------------------------------------------------------------------- modes
+ * A mode names the operand format fed to the matrix units.  Unless the flag
+ * MFG_IN_PRECONVERTED is or-ed in, A and B are FP32 and the library rounds,
+ * splits or quantises them itself into its workspace (counted in the call).
+ *
+ *   MFG_F32           FP32 operands, FP32 MFMA (the single-precision comparator).
+ *   MFG_F16           rne16(A) rne16(B), FP32 accumulate (paper Sec. V: FP32
+ *                     rounded to half before the matrix-unit GEMM, Sec. VI).
+ *   MFG_BF16          the same with bfloat16 operands.
+ *   MFG_F16_REFINE_A  one-sided refinement, paper Eq. 1:
+ *                     A_h B_h + (R_A B_h) / s, with R_A = rne16(s (A - A_h)).
+ *   MFG_F16_SPLIT3    two-sided refinement, paper Eq. 2 without R_A R_B:
+ *                     A_h B_h + (A_h R_B + R_A B_h) / s.
+ *   MFG_F16_SPLIT4    paper Eq. 2 in full: SPLIT3 + R_A R_B / s^2.
+ *   MFG_FP8_E4M3      OCP E4M3 codes with one power-of-two FP32 scale per
+ *                     128 x 128 tile of A (M x K) and of B (K x N).
+ * The residual scale is s = 2^11 (MFG_RESID_SCALE_LOG2).
+ *
+ * Preconverted storage forms (MFG_IN_PRECONVERTED), as written by
+ * mfg_convert():
+ *   F16 / BF16        16-bit matrix, ld in elements.
+ *   REFINE_A          A: head plane then residual plane at A + rows*lda
+ *                     elements; B: FP16 head plane only.
+ *   SPLIT3 / SPLIT4   A and B: head plane then residual plane.
+ *   FP8_E4M3          byte codes (ld in bytes) followed, at byte offset
+ *                     mfg_fp8_scale_offset(rows, ld), by ceil(rows/128) x
+ *                     ceil(cols/128) FP32 tile scales, row-major.
+ *   F32               ignores the flag.
+ */
+enum {
+    MFG_F32 = 0,
+    MFG_F16 = 1,
+    MFG_BF16 = 2,
+    MFG_F16_REFINE_A = 3,
+    MFG_F16_SPLIT3 = 4,
+    MFG_F16_SPLIT4 = 5,
+    MFG_FP8_E4M3 = 6,
+    MFG_NUM_MODES = 7
+};
+#define MFG_IN_PRECONVERTED 0x100
+#define MFG_MODE_MASK 0xFF
+#define MFG_RESID_SCALE_LOG2 11
+#define MFG_FP8_TILE 128
+
+/* Byte offset of the FP8 tile-scale array behind `rows x ld` code bytes. */
+int64_t mfg_fp8_scale_offset(int64_t rows, int64_t ld);
+
+/* ---------------------------------------------------------------- the GEMM
+ * mfg_gemm -- C = alpha * op(A) * op(B) + beta * C in the given mode
+ * (paper Sec. IV; refinement modes paper Sec. V Eq. 1 / Eq. 2).
+ *   M, N, K    problem sizes (>= 0).
+ *   A, lda     M x K operand, FP32 or the mode's preconverted form.
+ *   B, ldb     K x N operand, likewise.
+ *   C, ldc     M x N FP32, read (beta != 0) and written in place.
+ *   mode       MFG_* mode, optionally | MFG_IN_PRECONVERTED.
+ * Errors: MFG_ERR_INVALID_ARG for negative sizes, lda < max(1,K),
+ * ldb < max(1,N), ldc < max(1,N), a NULL pointer with nonzero extent, or an
+ * unknown mode; MFG_ERR_NO_MEMORY if the workspace cannot grow; MFG_ERR_HIP.
+ */
+int mfg_gemm(int64_t M, int64_t N, int64_t K,
+             const void* A, int64_t lda,
+             const void* B, int64_t ldb,
+             float* C, int64_t ldc,
+             float alpha, float beta, int mode, void* stream);
+
+/* mfg_gemm_config -- mfg_gemm with an explicit tile configuration index
+ * (0 <= config < mfg_num_configs(mode)), or -1 for the tuned choice.  Every
+ * configuration of a mode produces bitwise-identical results: they differ
+ * only in how output tiles are assigned to workgroups, never in the order in
+ * which an output element accumulates its products.  Used by the autotuner. */
+int mfg_gemm_config(int64_t M, int64_t N, int64_t K,
+                    const void* A, int64_t lda,
+                    const void* B, int64_t ldb,
+                    float* C, int64_t ldc,
+                    float alpha, float beta, int mode, int config, void* stream);
+
+/* Number of tile configurations of a mode and a short text description of
+ * one of them (written to `buf`, host, at most `n` bytes incl. the NUL). */
+int mfg_num_configs(int mode);
+int mfg_config_name(int mode, int config, char* buf, int n);
+
+/* --------------------------------------------------------- batched GEMM
+ * mfg_gemm_batched -- for b in [0, count):
+ *     C_b = alpha * A_b * B_b + beta * C_b,
+ * A_b = A + b*strideA, B_b = B + b*strideB, C_b = C + b*strideC (strides in
+ * elements of the stored type), all problems M x N x K (paper Sec. IV.B:
+ * many small GEMMs in one launch).  Modes F16, BF16 and F32 take their
+ * operands directly (F16/BF16 as 16-bit data; the flag is implied); the
+ * refinement modes take FP32 operands and split them into the workspace.
+ * FP8 is not served batched (MFG_ERR_UNSUPPORTED).
+ */
+int mfg_gemm_batched(int64_t count, int64_t M, int64_t N, int64_t K,
+                     const void* A, int64_t lda, int64_t strideA,
+                     const void* B, int64_t ldb, int64_t strideB,
+                     float* C, int64_t ldc, int64_t strideC,
+                     float alpha, float beta, int mode, void* stream);
+
+/* --------------------------------------------------------- grouped GEMM
+ * Thousands of GEMMs of different shapes in one persistent launch.
+ * A problem's operands are 16-bit for F16/BF16 and FP32 for F32; other modes
+ * are MFG_ERR_UNSUPPORTED.  The descriptor array is host memory; the plan
+ * copies it to the device, so it may be freed after mfg_grouped_plan_create.
+ */
+typedef struct mfg_problem {
+    int64_t M, N, K;
+    int64_t lda, ldb, ldc;
+    const void* A;
+    const void* B;
+    float* C;
+} mfg_problem;
+
+typedef struct mfg_grouped_plan mfg_grouped_plan;
+
+/* Build a plan: validates every problem, assigns each a tile class, orders
+ * work items largest first, and uploads descriptors and the work list
+ * (device memory owned by the plan).  `out` receives the plan (host). */
+int mfg_grouped_plan_create(int64_t count, const mfg_problem* problems, int mode,
+                            mfg_grouped_plan** out);
+/* Run the plan once on `stream` (one persistent kernel launch). */
+int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, void* stream);
+/* Run the plan through a HIP graph: captured on first use for (alpha, beta,
+ * stream), replayed afterwards.  The graph holds the plan's launch only. */
+int mfg_grouped_graph_launch(mfg_grouped_plan* plan, float alpha, float beta, void* stream);
+/* Total useful flops 2*sum(M*N*K) and algorithmic bytes of the plan. */
+int mfg_grouped_plan_info(const mfg_grouped_plan* plan, double* flops, double* bytes,
+                          int64_t* work_items);
+int mfg_grouped_plan_destroy(mfg_grouped_plan* plan);
+
+/* ----------------------------------------------------- operand conversion
+ * The paper rounds FP32 inputs to half precision before the matrix-unit
+ * GEMM and leaves that step out of its timings (Sec. VI).  These calls do
+ * that step explicitly.  X is rows x cols FP32 with leading dimension ldx.
+ */
+/* out = rne16(X): IEEE round-to-nearest-even, overflow to +-Inf, gradual
+ * underflow (paper Sec. V, "Limited range"). ldo in 16-bit elements. */
+int mfg_round_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                  void* out, int64_t ldo, void* stream);
+/* out = rnebf16(X), NaN kept quiet. */
+int mfg_round_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                   void* out, int64_t ldo, void* stream);
+/* Residual split (paper Sec. V, Eq. R, scaled): head = rne16(X),
+ * resid = rne16(2^11 * (X - head)).  If norms != NULL (device, 4 doubles)
+ * it receives, in FP64: sum X^2, max|X|, sum r^2, max|r| with r = X - head. */
+int mfg_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                  void* head, void* resid, int64_t ldo, double* norms, void* stream);
+/* FP8-E4M3 with one scale per 128 x 128 tile: scale = 2^E with E the
+ * smallest integer such that 448 * 2^E >= max|tile| (E = 0 for an all-zero
+ * tile, clamped to [-127, 127]); codes = sat_rne_e4m3(X / scale).
+ * codes: rows x ldo bytes; scales: ceil(rows/128) x ceil(cols/128) FP32. */
+int mfg_quantize_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                     void* codes, int64_t ldo, float* scales, void* stream);
+/* Write X in `mode`'s preconverted storage form (see "modes" above); `out`
+ * must hold mfg_convert_bytes(rows, ldo, mode) bytes. */
+int mfg_convert(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                void* out, int64_t ldo, int mode, void* stream);
+int64_t mfg_convert_bytes(int64_t rows, int64_t cols, int64_t ldo, int mode);
+
+/* ----------------------------------------------------- FP64 error norms
+ * Error of a result against an FP64 reference (paper Sec. VI: the max norm
+ * of e = C - C_ref), computed on the GPU in FP64 with a deterministic
+ * two-stage reduction.  out4 (device, 4 doubles) receives
+ *   max|C - Cref|,  ||C - Cref||_F,  ||Cref||_F,  max|Cref|.
+ */
+int mfg_error_norms(int64_t M, int64_t N, const float* C, int64_t ldc,
+                    const double* Cref, int64_t ldr, double* out4, void* stream);
+
+/* ------------------------------------------------------------- autotuner
+ * Time every tile configuration of `mode` on the caller's operands with HIP
+ * events (`reps` timed runs after one warm-up each), keep the fastest whose
+ * output is bitwise equal to configuration 0's, and record it in the tuned
+ * table for the size bucket of (M, N, K).  best_config / best_ms (host) may
+ * be NULL.  C is overwritten. */
+int mfg_autotune(int64_t M, int64_t N, int64_t K,
+                 const void* A, int64_t lda, const void* B, int64_t ldb,
+                 float* C, int64_t ldc, int mode, int reps,
+                 int* best_config, float* best_ms, void* stream);
+/* Save / load the tuned table as text lines "mode mbucket nbucket kbucket config". */
+int mfg_tune_save(const char* path);
+int mfg_tune_load(const char* path);
+int mfg_tune_clear(void);
+/* Configuration mfg_gemm would use for this problem (tuned or heuristic). */
+int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop with continuous batching and HBM admission.  Requests are
+ * GEMMs over caller-owned FP32 A/B and FP32 C device buffers; the server
+ * owns the converted operands.  A request is admitted when its converted-
+ * operand footprint fits in hbm_budget_bytes next to those already admitted
+ * and a slot (one HIP stream each) is free; admitted requests of one mode
+ * that are waiting together are launched as one grouped launch.
+ */
+typedef struct mfg_server mfg_server;
+
+typedef struct mfg_server_config {
+    uint64_t hbm_budget_bytes;  /* bytes of converted operands in flight     */
+    int32_t slots;              /* concurrent launches (streams), >= 1        */
+    int32_t device;             /* HIP device ordinal                         */
+    int32_t max_group;          /* requests per grouped launch, >= 1          */
+    int32_t reserved;
+} mfg_server_config;
+
+typedef struct mfg_request {
+    int64_t M, N, K;
+    int64_t lda, ldb, ldc;
+    const float* A;   /* FP32, device */
+    const float* B;   /* FP32, device */
+    float* C;         /* FP32, device */
+    float alpha, beta;
+    int32_t mode;     /* MFG_F16, MFG_BF16, MFG_F16_SPLIT3, ... (no flag) */
+    int32_t reserved;
+} mfg_request;
+
+typedef struct mfg_result {
+    int32_t status;        /* MFG_OK, MFG_PENDING or an error              */
+    int32_t slot;          /* slot (stream) index that ran it, -1 if none  */
+    int64_t t_submit_ns;   /* steady-clock timestamps                      */
+    int64_t t_admit_ns;
+    int64_t t_start_ns;    /* launch enqueued                              */
+    int64_t t_end_ns;      /* completion observed                          */
+    int64_t group_size;    /* requests in the launch that carried it       */
+    double flops;          /* 2*M*N*K                                      */
+} mfg_result;
+
+typedef struct mfg_server_stats {
+    int64_t submitted, completed, failed, launches;
+    uint64_t bytes_in_use, peak_bytes_in_use;
+    int64_t max_concurrent_slots;
+} mfg_server_stats;
+
+int mfg_server_create(const mfg_server_config* cfg, mfg_server** out);
+/* Submit (host copies *req).  MFG_ERR_OVER_BUDGET if the request alone
+ * exceeds the budget; `ticket` (host) receives the request's id. */
+int mfg_submit(mfg_server* s, const mfg_request* req, uint64_t* ticket);
+/* MFG_PENDING while running; the final status once done (the result is
+ * copied to *out, host, may be NULL), after which the ticket is released. */
+int mfg_poll(mfg_server* s, uint64_t ticket, mfg_result* out);
+/* Block until every submitted request has finished. */
+int mfg_server_drain(mfg_server* s);
+int mfg_server_get_stats(mfg_server* s, mfg_server_stats* out);
+int mfg_server_destroy(mfg_server* s);
+
+/* ------------------------------------------------------------------ misc */
+const char* mfg_status_string(int status);
+int mfg_last_hip_error(void);
+const char* mfg_version(void);
+/* Validation only (host, no HIP call): the status mfg_gemm would return for
+ * these arguments before enqueueing anything. */
+int mfg_validate_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+                      const void* B, int64_t ldb, const float* C, int64_t ldc, int mode);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFGEMM_H */

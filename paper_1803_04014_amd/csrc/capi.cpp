@@ -1,0 +1,568 @@
+// capi.cpp -- the exported C ABI of libmfgemm (see include/mfgemm.h):
+// validation, operand conversion into the per-stream workspace, tile
+// configuration choice and kernel dispatch.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "runtime.h"
+
+namespace mfg {
+
+static bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+static int64_t up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+static int kind_of(int m) {
+    switch (m) {
+        case MFG_F16: return K_F16;
+        case MFG_BF16: return K_BF16;
+        case MFG_F16_REFINE_A: return K_REFINE_A;
+        case MFG_F16_SPLIT3: return K_SPLIT3;
+        case MFG_F16_SPLIT4: return K_SPLIT4;
+        default: return -1;
+    }
+}
+
+static int npa(int m) { return (m == MFG_F16_REFINE_A || m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4) ? 2 : 1; }
+static int npb(int m) { return (m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4) ? 2 : 1; }
+
+// Write the 16-bit planes of `mode` for an FP32 matrix X (rows x cols).
+static int convert16(int m, int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* p0, uint16_t* p1,
+                     int64_t ldo, bool split, hipStream_t s) {
+    if (m == MFG_BF16) return launch_round_bf16(rows, cols, X, ldx, p0, ldo, s);
+    if (split) return launch_split_f16(rows, cols, X, ldx, p0, p1, ldo, nullptr, s);
+    return launch_round_f16(rows, cols, X, ldx, p0, ldo, s);
+}
+
+static int choose16(int m, int config, int64_t M, int64_t N, int64_t K, bool vec) {
+    if (config >= 0) return config;
+    const int t = tuned_lookup(m, M, N, K);
+    if (t >= 0 && t < num_configs16(kind_of(m)) && (vec || t == 0)) return t;
+    return pick_config16(kind_of(m), M, N, K, vec);
+}
+
+static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
+                     float* C, int64_t ldc, float alpha, float beta, int mode, int config, hipStream_t s) {
+    int st = validate_gemm(M, N, K, A, lda, B, ldb, C, ldc, mode);
+    if (st != MFG_OK) return st;
+    const int m = mode & MFG_MODE_MASK;
+    const bool pre = (mode & MFG_IN_PRECONVERTED) != 0;
+    if (M == 0 || N == 0) return MFG_OK;
+    if (K == 0 || alpha == 0.0f) return launch_scale_c(M, N, C, ldc, beta, 1, 0, s);
+
+    if (m == MFG_F32) {
+        GemmF32Args a{};
+        a.M = M, a.N = N, a.K = K;
+        a.A = static_cast<const float*>(A), a.B = static_cast<const float*>(B), a.C = C;
+        a.lda = lda, a.ldb = ldb, a.ldc = ldc, a.alpha = alpha, a.beta = beta;
+        const bool vec = al16(A) && al16(B) && lda % 4 == 0 && ldb % 4 == 0;
+        int cfg = config;
+        if (cfg < 0) {
+            const int t = tuned_lookup(m, M, N, K);
+            cfg = (t >= 0 && t < num_configs_f32() && (vec || t == 0)) ? t : pick_config_f32(M, N, K, vec);
+        }
+        return launch_gemm_f32(cfg, a, 1, vec, s);
+    }
+
+    if (m == MFG_FP8_E4M3) {
+        GemmF8Args a{};
+        a.M = M, a.N = N, a.K = K, a.C = C, a.ldc = ldc, a.alpha = alpha, a.beta = beta;
+        if (pre) {
+            a.A = static_cast<const uint8_t*>(A), a.lda = lda;
+            a.B = static_cast<const uint8_t*>(B), a.ldb = ldb;
+            a.sa = reinterpret_cast<const float*>(a.A + mfg_fp8_scale_offset(M, lda));
+            a.sb = reinterpret_cast<const float*>(a.B + mfg_fp8_scale_offset(K, ldb));
+            const bool vec = al16(A) && lda % 16 == 0;
+            if (config > 0) return MFG_ERR_INVALID_ARG;
+            return launch_gemm_f8(0, a, vec, s);
+        }
+        const int64_t ldk = up(K, 16), ldn = up(N, 16);
+        const int64_t bA = mfg_convert_bytes(M, K, ldk, MFG_FP8_E4M3);
+        const int64_t bB = mfg_convert_bytes(K, N, ldn, MFG_FP8_E4M3);
+        WsLease ws(s, (size_t)(up(bA, 256) + bB));
+        if (!ws.ptr()) return ws.status();
+        uint8_t* qa = static_cast<uint8_t*>(ws.ptr());
+        uint8_t* qb = qa + up(bA, 256);
+        float* sa = reinterpret_cast<float*>(qa + mfg_fp8_scale_offset(M, ldk));
+        float* sb = reinterpret_cast<float*>(qb + mfg_fp8_scale_offset(K, ldn));
+        if ((st = launch_quantize_fp8(M, K, static_cast<const float*>(A), lda, qa, ldk, sa, s)) != MFG_OK) return st;
+        if ((st = launch_quantize_fp8(K, N, static_cast<const float*>(B), ldb, qb, ldn, sb, s)) != MFG_OK) return st;
+        a.A = qa, a.lda = ldk, a.B = qb, a.ldb = ldn, a.sa = sa, a.sb = sb;
+        if (config > 0) return MFG_ERR_INVALID_ARG;
+        return launch_gemm_f8(0, a, true, s);
+    }
+
+    // 16-bit modes
+    const int kind = kind_of(m);
+    Gemm16Args a{};
+    a.M = M, a.N = N, a.K = K, a.C = C, a.ldc = ldc, a.alpha = alpha, a.beta = beta;
+    if (pre) {
+        const uint16_t* pa = static_cast<const uint16_t*>(A);
+        const uint16_t* pb = static_cast<const uint16_t*>(B);
+        a.A[0] = pa, a.A[1] = npa(m) == 2 ? pa + M * lda : nullptr;
+        a.B[0] = pb, a.B[1] = npb(m) == 2 ? pb + K * ldb : nullptr;
+        a.lda = lda, a.ldb = ldb;
+        const bool vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0;
+        return launch_gemm16(kind, choose16(m, config, M, N, K, vec), a, 1, vec, s);
+    }
+    const int64_t ldk = up(K, 8), ldn = up(N, 8);
+    const int64_t pa_elems = M * ldk, pb_elems = K * ldn;
+    const size_t bytes = (size_t)(npa(m) * up(pa_elems, 128) + npb(m) * up(pb_elems, 128)) * 2;
+    WsLease ws(s, bytes);
+    if (!ws.ptr()) return ws.status();
+    uint16_t* w = static_cast<uint16_t*>(ws.ptr());
+    uint16_t* a0 = w;
+    uint16_t* a1 = npa(m) == 2 ? a0 + up(pa_elems, 128) : nullptr;
+    uint16_t* b0 = (a1 ? a1 : a0) + up(pa_elems, 128);
+    uint16_t* b1 = npb(m) == 2 ? b0 + up(pb_elems, 128) : nullptr;
+    if ((st = convert16(m, M, K, static_cast<const float*>(A), lda, a0, a1, ldk, npa(m) == 2, s)) != MFG_OK) return st;
+    if ((st = convert16(m, K, N, static_cast<const float*>(B), ldb, b0, b1, ldn, npb(m) == 2, s)) != MFG_OK) return st;
+    a.A[0] = a0, a.A[1] = a1, a.B[0] = b0, a.B[1] = b1, a.lda = ldk, a.ldb = ldn;
+    return launch_gemm16(kind, choose16(m, config, M, N, K, true), a, 1, true, s);
+}
+
+}  // namespace mfg
+
+using namespace mfg;
+
+#define MFG_GUARD(expr)                      \
+    try {                                    \
+        return (expr);                       \
+    } catch (const std::bad_alloc&) {        \
+        return MFG_ERR_NO_MEMORY;            \
+    } catch (...) {                          \
+        return MFG_ERR_INTERNAL;             \
+    }
+
+extern "C" int mfg_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
+                        float* C, int64_t ldc, float alpha, float beta, int mode, void* stream) {
+    MFG_GUARD(gemm_impl(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, mode, -1, (hipStream_t)stream));
+}
+
+extern "C" int mfg_gemm_config(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
+                               int64_t ldb, float* C, int64_t ldc, float alpha, float beta, int mode, int config,
+                               void* stream) {
+    if (config < -1) return MFG_ERR_INVALID_ARG;
+    MFG_GUARD(gemm_impl(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, mode, config, (hipStream_t)stream));
+}
+
+extern "C" int mfg_num_configs(int mode) {
+    const int m = mode & MFG_MODE_MASK;
+    if (m == MFG_F32) return num_configs_f32();
+    if (m == MFG_FP8_E4M3) return num_configs_f8();
+    const int k = kind_of(m);
+    return k < 0 ? MFG_ERR_INVALID_ARG : num_configs16(k);
+}
+
+extern "C" int mfg_config_name(int mode, int config, char* buf, int n) {
+    const int m = mode & MFG_MODE_MASK;
+    const char* name = nullptr;
+    if (m == MFG_F32) name = config_f32_name(config);
+    else if (m == MFG_FP8_E4M3) name = config_f8_name(config);
+    else if (kind_of(m) >= 0) name = config16_name(kind_of(m), config);
+    if (!name || !buf || n <= 0) return MFG_ERR_INVALID_ARG;
+    std::strncpy(buf, name, (size_t)n - 1);
+    buf[n - 1] = '\0';
+    return MFG_OK;
+}
+
+extern "C" int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode) {
+    const int m = mode & MFG_MODE_MASK;
+    if (m < 0 || m >= MFG_NUM_MODES || M < 0 || N < 0 || K < 0) return MFG_ERR_INVALID_ARG;
+    if (m == MFG_F32) {
+        const int t = tuned_lookup(m, M, N, K);
+        return t >= 0 ? t : pick_config_f32(M, N, K, true);
+    }
+    if (m == MFG_FP8_E4M3) return 0;
+    return choose16(m, -1, M, N, K, true);
+}
+
+// -------------------------------------------------------------------- batched
+static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+                        int64_t strideA, const void* B, int64_t ldb, int64_t strideB, float* C, int64_t ldc,
+                        int64_t strideC, float alpha, float beta, int mode, hipStream_t s) {
+    const int m = mode & MFG_MODE_MASK;
+    if (count < 0 || strideA < 0 || strideB < 0 || strideC < 0) return MFG_ERR_INVALID_ARG;
+    int st = validate_gemm(M, N, K, A, lda, B, ldb, C, ldc, m);
+    if (st != MFG_OK) return st;
+    if (count > 1 && M > 0 && N > 0 && strideC < (M - 1) * ldc + N) return MFG_ERR_INVALID_ARG;  // outputs overlap
+    if (m == MFG_FP8_E4M3) return MFG_ERR_UNSUPPORTED;
+    if (count == 0 || M == 0 || N == 0) return MFG_OK;
+    if (K == 0 || alpha == 0.0f) return launch_scale_c(M, N, C, ldc, beta, count, strideC, s);
+
+    if (m == MFG_F32) {
+        GemmF32Args a{};
+        a.M = M, a.N = N, a.K = K, a.ldc = ldc, a.alpha = alpha, a.beta = beta;
+        a.lda = lda, a.ldb = ldb, a.sA = strideA, a.sB = strideB, a.sC = strideC;
+        const bool vec = al16(A) && al16(B) && lda % 4 == 0 && ldb % 4 == 0 && strideA % 4 == 0 && strideB % 4 == 0;
+        const int cfg = (M >= 128 && N >= 128 && vec) ? 1 : 0;
+        for (int64_t b0 = 0; b0 < count; b0 += 65535) {
+            a.A = static_cast<const float*>(A) + b0 * strideA;
+            a.B = static_cast<const float*>(B) + b0 * strideB;
+            a.C = C + b0 * strideC;
+            if ((st = launch_gemm_f32(cfg, a, std::min<int64_t>(65535, count - b0), vec, s)) != MFG_OK) return st;
+        }
+        return MFG_OK;
+    }
+
+    const int kind = kind_of(m);
+    Gemm16Args a{};
+    a.M = M, a.N = N, a.K = K, a.ldc = ldc, a.sC = strideC, a.alpha = alpha, a.beta = beta;
+    bool vec;
+    const bool split_mode = (m == MFG_F16_REFINE_A || m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4);
+    std::unique_ptr<WsLease> ws;
+    if (!split_mode) {
+        a.A[0] = static_cast<const uint16_t*>(A), a.B[0] = static_cast<const uint16_t*>(B);
+        a.lda = lda, a.ldb = ldb, a.sA = strideA, a.sB = strideB;
+        vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && strideA % 8 == 0 && strideB % 8 == 0;
+    } else {
+        // FP32 operands split into the workspace, packed per batch entry.
+        const int64_t ldk = up(K, 8), ldn = up(N, 8);
+        const int64_t pa = up(M * ldk, 8), pb = up(K * ldn, 8);
+        const size_t bytes = (size_t)(npa(m) * count * pa + npb(m) * count * pb) * 2 + 1024;
+        ws.reset(new WsLease(s, bytes));
+        if (!ws->ptr()) return ws->status();
+        uint16_t* w = static_cast<uint16_t*>(ws->ptr());
+        uint16_t* a0 = w;
+        uint16_t* a1 = a0 + count * pa;
+        uint16_t* b0 = a1 + count * pa;
+        uint16_t* b1 = npb(m) == 2 ? b0 + count * pb : nullptr;
+        const float* Af = static_cast<const float*>(A);
+        const float* Bf = static_cast<const float*>(B);
+        // A contiguous batch (stride == rows * ld) is one tall matrix.
+        if (strideA == M * lda && pa == M * ldk) {
+            if ((st = launch_split_f16(count * M, K, Af, lda, a0, a1, ldk, nullptr, s)) != MFG_OK) return st;
+        } else {
+            for (int64_t b = 0; b < count; ++b)
+                if ((st = launch_split_f16(M, K, Af + b * strideA, lda, a0 + b * pa, a1 + b * pa, ldk, nullptr, s)) !=
+                    MFG_OK)
+                    return st;
+        }
+        const bool bsplit = npb(m) == 2;
+        for (int64_t b = 0; b < count; ++b) {
+            if (strideB == K * ldb && pb == K * ldn) {
+                st = bsplit ? launch_split_f16(count * K, N, Bf, ldb, b0, b1, ldn, nullptr, s)
+                            : launch_round_f16(count * K, N, Bf, ldb, b0, ldn, s);
+                if (st != MFG_OK) return st;
+                break;
+            }
+            st = bsplit ? launch_split_f16(K, N, Bf + b * strideB, ldb, b0 + b * pb, b1 + b * pb, ldn, nullptr, s)
+                        : launch_round_f16(K, N, Bf + b * strideB, ldb, b0 + b * pb, ldn, s);
+            if (st != MFG_OK) return st;
+        }
+        a.A[0] = a0, a.A[1] = a1, a.B[0] = b0, a.B[1] = b1;
+        a.lda = ldk, a.ldb = ldn, a.sA = pa, a.sB = pb;
+        vec = true;
+    }
+    if (M <= 32 && N <= 32) return launch_batched_small(kind, a, count, vec, device_cu_count(), s);
+    const int cfg = vec ? pick_config16(kind, M, N, K, vec) : 0;
+    for (int64_t b0 = 0; b0 < count; b0 += 65535) {
+        Gemm16Args c = a;
+        for (int q = 0; q < 2; ++q) {
+            if (c.A[q]) c.A[q] += b0 * a.sA;
+            if (c.B[q]) c.B[q] += b0 * a.sB;
+        }
+        c.C = C + b0 * strideC;
+        if ((st = launch_gemm16(kind, cfg, c, std::min<int64_t>(65535, count - b0), vec, s)) != MFG_OK) return st;
+    }
+    return MFG_OK;
+}
+
+extern "C" int mfg_gemm_batched(int64_t count, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+                                int64_t strideA, const void* B, int64_t ldb, int64_t strideB, float* C, int64_t ldc,
+                                int64_t strideC, float alpha, float beta, int mode, void* stream) {
+    MFG_GUARD(batched_impl(count, M, N, K, A, lda, strideA, B, ldb, strideB, C, ldc, strideC, alpha, beta, mode,
+                           (hipStream_t)stream));
+}
+
+// -------------------------------------------------------------------- grouped
+struct mfg_grouped_plan {
+    int mode = 0, kind = 0, device = 0;
+    int64_t count = 0, nwork = 0;
+    int grid = 0;
+    GroupedDesc* d_desc = nullptr;
+    GroupedWork* d_work = nullptr;
+    double flops = 0.0, bytes = 0.0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float g_alpha = 0.f, g_beta = 0.f;
+    hipStream_t g_stream = nullptr;
+};
+
+static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, mfg_grouped_plan** out) {
+    if (!out || count < 0 || (count > 0 && !probs)) return MFG_ERR_INVALID_ARG;
+    *out = nullptr;
+    const int m = mode & MFG_MODE_MASK;
+    if ((mode & ~(MFG_MODE_MASK | MFG_IN_PRECONVERTED)) != 0 || m < 0 || m >= MFG_NUM_MODES) return MFG_ERR_INVALID_ARG;
+    if (m != MFG_F16 && m != MFG_BF16) return MFG_ERR_UNSUPPORTED;
+    if (count > ((int64_t)1 << 31) - 1) return MFG_ERR_UNSUPPORTED;
+    std::vector<GroupedDesc> descs((size_t)count);
+    std::vector<GroupedWork> work;
+    double flops = 0.0, bytes = 0.0;
+    for (int64_t i = 0; i < count; ++i) {
+        const mfg_problem& p = probs[i];
+        int st = validate_gemm(p.M, p.N, p.K, p.A, p.lda, p.B, p.ldb, p.C, p.ldc, m);
+        if (st != MFG_OK) return st;
+        if (p.M > ((int64_t)1 << 24) || p.N > ((int64_t)1 << 24)) return MFG_ERR_UNSUPPORTED;
+        GroupedDesc& d = descs[(size_t)i];
+        d.M = p.M, d.N = p.N, d.K = p.K, d.lda = p.lda, d.ldb = p.ldb, d.ldc = p.ldc;
+        d.A = static_cast<const uint16_t*>(p.A), d.B = static_cast<const uint16_t*>(p.B), d.C = p.C;
+        d.vec = (al16(p.A) && al16(p.B) && p.lda % 8 == 0 && p.ldb % 8 == 0) ? 1 : 0;
+        d.pad = 0;
+        flops += 2.0 * (double)p.M * (double)p.N * (double)p.K;
+        bytes += 2.0 * (double)(p.M * p.K + p.K * p.N) + 4.0 * (double)(p.M * p.N);
+        const int64_t tm = cdiv(p.M, 64), tn = cdiv(p.N, 64);
+        for (int64_t a = 0; a < tm; ++a)
+            for (int64_t b = 0; b < tn; ++b) work.push_back(GroupedWork{(int32_t)i, (int32_t)a, (int32_t)b, 0});
+    }
+    // Largest cost (K) first, stable, so the static stride balances like LPT.
+    std::stable_sort(work.begin(), work.end(), [&](const GroupedWork& x, const GroupedWork& y) {
+        return descs[(size_t)x.prob].K > descs[(size_t)y.prob].K;
+    });
+    std::unique_ptr<mfg_grouped_plan> plan(new mfg_grouped_plan());
+    plan->mode = m, plan->kind = kind_of(m), plan->count = count, plan->nwork = (int64_t)work.size();
+    plan->flops = flops, plan->bytes = bytes;
+    MFG_HIP_CHECK(hipGetDevice(&plan->device));
+    // Persistent grid: four 256-thread workgroups per CU (LDS 32 KB each).
+    const int64_t g = (int64_t)device_cu_count() * 4;
+    plan->grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, plan->nwork));
+    if (count > 0) {
+        if (hipMalloc(&plan->d_desc, descs.size() * sizeof(GroupedDesc)) != hipSuccess) return MFG_ERR_NO_MEMORY;
+        MFG_HIP_CHECK(hipMemcpy(plan->d_desc, descs.data(), descs.size() * sizeof(GroupedDesc), hipMemcpyHostToDevice));
+    }
+    if (!work.empty()) {
+        if (hipMalloc(&plan->d_work, work.size() * sizeof(GroupedWork)) != hipSuccess) {
+            (void)hipFree(plan->d_desc);
+            return MFG_ERR_NO_MEMORY;
+        }
+        MFG_HIP_CHECK(hipMemcpy(plan->d_work, work.data(), work.size() * sizeof(GroupedWork), hipMemcpyHostToDevice));
+    }
+    // Set kernel attributes now, outside any stream capture.
+    int st = grouped_launch(plan->kind, nullptr, nullptr, 0, 1, 1.f, 0.f, nullptr);
+    if (st != MFG_OK) return st;
+    *out = plan.release();
+    return MFG_OK;
+}
+
+extern "C" int mfg_grouped_plan_create(int64_t count, const mfg_problem* problems, int mode,
+                                       mfg_grouped_plan** out) {
+    MFG_GUARD(plan_create_impl(count, problems, mode, out));
+}
+
+extern "C" int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, void* stream) {
+    if (!plan) return MFG_ERR_INVALID_ARG;
+    MFG_GUARD(grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->nwork, plan->grid, alpha, beta,
+                             (hipStream_t)stream));
+}
+
+static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hipStream_t s) {
+    if (!plan) return MFG_ERR_INVALID_ARG;
+    if (plan->exec && (plan->g_alpha != alpha || plan->g_beta != beta || plan->g_stream != s)) {
+        MFG_HIP_CHECK(hipGraphExecDestroy(plan->exec));
+        MFG_HIP_CHECK(hipGraphDestroy(plan->graph));
+        plan->exec = nullptr, plan->graph = nullptr;
+    }
+    if (!plan->exec) {
+        MFG_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int st = grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->nwork, plan->grid, alpha, beta, s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (st != MFG_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e);
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e);
+        }
+        plan->graph = g, plan->exec = x, plan->g_alpha = alpha, plan->g_beta = beta, plan->g_stream = s;
+    }
+    MFG_HIP_CHECK(hipGraphLaunch(plan->exec, s));
+    return MFG_OK;
+}
+
+extern "C" int mfg_grouped_graph_launch(mfg_grouped_plan* plan, float alpha, float beta, void* stream) {
+    MFG_GUARD(graph_launch_impl(plan, alpha, beta, (hipStream_t)stream));
+}
+
+extern "C" int mfg_grouped_plan_info(const mfg_grouped_plan* plan, double* flops, double* bytes,
+                                     int64_t* work_items) {
+    if (!plan) return MFG_ERR_INVALID_ARG;
+    if (flops) *flops = plan->flops;
+    if (bytes) *bytes = plan->bytes;
+    if (work_items) *work_items = plan->nwork;
+    return MFG_OK;
+}
+
+extern "C" int mfg_grouped_plan_destroy(mfg_grouped_plan* plan) {
+    if (!plan) return MFG_ERR_INVALID_ARG;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->d_desc) (void)hipFree(plan->d_desc);
+    if (plan->d_work) (void)hipFree(plan->d_work);
+    delete plan;
+    return MFG_OK;
+}
+
+// ----------------------------------------------------------------- converts
+extern "C" int mfg_round_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, void* out, int64_t ldo,
+                             void* stream) {
+    int st = validate_matrix(rows, cols, X, ldx);
+    if (st == MFG_OK) st = validate_matrix(rows, cols, out, ldo);
+    if (st != MFG_OK) return st;
+    MFG_GUARD(launch_round_f16(rows, cols, X, ldx, static_cast<uint16_t*>(out), ldo, (hipStream_t)stream));
+}
+
+extern "C" int mfg_round_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, void* out, int64_t ldo,
+                              void* stream) {
+    int st = validate_matrix(rows, cols, X, ldx);
+    if (st == MFG_OK) st = validate_matrix(rows, cols, out, ldo);
+    if (st != MFG_OK) return st;
+    MFG_GUARD(launch_round_bf16(rows, cols, X, ldx, static_cast<uint16_t*>(out), ldo, (hipStream_t)stream));
+}
+
+extern "C" int mfg_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, void* head, void* resid,
+                             int64_t ldo, double* norms, void* stream) {
+    int st = validate_matrix(rows, cols, X, ldx);
+    if (st == MFG_OK) st = validate_matrix(rows, cols, head, ldo);
+    if (st == MFG_OK) st = validate_matrix(rows, cols, resid, ldo);
+    if (st != MFG_OK) return st;
+    MFG_GUARD(launch_split_f16(rows, cols, X, ldx, static_cast<uint16_t*>(head), static_cast<uint16_t*>(resid), ldo,
+                               norms, (hipStream_t)stream));
+}
+
+extern "C" int mfg_quantize_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx, void* codes, int64_t ldo,
+                                float* scales, void* stream) {
+    int st = validate_matrix(rows, cols, X, ldx);
+    if (st == MFG_OK) st = validate_matrix(rows, cols, codes, ldo);
+    if (st != MFG_OK) return st;
+    if (rows > 0 && cols > 0 && !scales) return MFG_ERR_INVALID_ARG;
+    MFG_GUARD(launch_quantize_fp8(rows, cols, X, ldx, static_cast<uint8_t*>(codes), ldo, scales, (hipStream_t)stream));
+}
+
+static int convert_impl(int64_t rows, int64_t cols, const float* X, int64_t ldx, void* out, int64_t ldo, int mode,
+                        hipStream_t s) {
+    int st = validate_matrix(rows, cols, X, ldx);
+    if (st == MFG_OK) st = validate_matrix(rows, cols, out, ldo);
+    if (st != MFG_OK) return st;
+    const int m = mode & MFG_MODE_MASK;
+    uint16_t* o16 = static_cast<uint16_t*>(out);
+    switch (m) {
+        case MFG_F32:
+            if (rows == 0 || cols == 0) return MFG_OK;
+            MFG_HIP_CHECK(hipMemcpy2DAsync(out, (size_t)ldo * 4, X, (size_t)ldx * 4, (size_t)cols * 4, (size_t)rows,
+                                           hipMemcpyDeviceToDevice, s));
+            return MFG_OK;
+        case MFG_F16: return launch_round_f16(rows, cols, X, ldx, o16, ldo, s);
+        case MFG_BF16: return launch_round_bf16(rows, cols, X, ldx, o16, ldo, s);
+        case MFG_F16_REFINE_A:
+        case MFG_F16_SPLIT3:
+        case MFG_F16_SPLIT4: return launch_split_f16(rows, cols, X, ldx, o16, o16 + rows * ldo, ldo, nullptr, s);
+        case MFG_FP8_E4M3: {
+            uint8_t* c = static_cast<uint8_t*>(out);
+            return launch_quantize_fp8(rows, cols, X, ldx, c, ldo,
+                                       reinterpret_cast<float*>(c + mfg_fp8_scale_offset(rows, ldo)), s);
+        }
+        default: return MFG_ERR_INVALID_ARG;
+    }
+}
+
+extern "C" int mfg_convert(int64_t rows, int64_t cols, const float* X, int64_t ldx, void* out, int64_t ldo, int mode,
+                           void* stream) {
+    MFG_GUARD(convert_impl(rows, cols, X, ldx, out, ldo, mode, (hipStream_t)stream));
+}
+
+extern "C" int mfg_error_norms(int64_t M, int64_t N, const float* C, int64_t ldc, const double* Cref, int64_t ldr,
+                               double* out4, void* stream) {
+    int st = validate_matrix(M, N, C, ldc);
+    if (st == MFG_OK) st = validate_matrix(M, N, Cref, ldr);
+    if (st != MFG_OK) return st;
+    if (!out4) return MFG_ERR_INVALID_ARG;
+    MFG_GUARD(launch_error_norms(M, N, C, ldc, Cref, ldr, out4, (hipStream_t)stream));
+}
+
+// ------------------------------------------------------------------ autotune
+static int autotune_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
+                         float* C, int64_t ldc, int mode, int reps, int* best_config, float* best_ms, hipStream_t s) {
+    int st = validate_gemm(M, N, K, A, lda, B, ldb, C, ldc, mode);
+    if (st != MFG_OK) return st;
+    if (reps < 1 || M == 0 || N == 0) return MFG_ERR_INVALID_ARG;
+    const int m = mode & MFG_MODE_MASK;
+    const int ncfg = mfg_num_configs(m);
+    if (ncfg <= 0) return MFG_ERR_INVALID_ARG;
+    float* ref = nullptr;
+    unsigned long long* cnt = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = 0;
+    float bms = 0.f;
+    auto cleanup = [&]() {
+        if (ref) (void)hipFree(ref);
+        if (cnt) (void)hipFree(cnt);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&ref, (size_t)M * N * sizeof(float)) != hipSuccess ||
+        hipMalloc(&cnt, sizeof(unsigned long long)) != hipSuccess) {
+        cleanup();
+        return MFG_ERR_NO_MEMORY;
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return MFG_ERR_HIP;
+    }
+    // beta = 0: C is output only, so every run starts from the same state.
+    st = gemm_impl(M, N, K, A, lda, B, ldb, C, ldc, 1.f, 0.f, mode, 0, s);
+    if (st == MFG_OK &&
+        hipMemcpy2DAsync(ref, (size_t)N * 4, C, (size_t)ldc * 4, (size_t)N * 4, (size_t)M, hipMemcpyDeviceToDevice,
+                         s) != hipSuccess)
+        st = MFG_ERR_HIP;
+    bms = 3.4e38f;
+    for (int c = 0; st == MFG_OK && c < ncfg; ++c) {
+        int r = gemm_impl(M, N, K, A, lda, B, ldb, C, ldc, 1.f, 0.f, mode, c, s);  // warm-up
+        if (r == MFG_ERR_UNSUPPORTED) continue;
+        if (r != MFG_OK) {
+            st = r;
+            break;
+        }
+        float total = 0.f;
+        for (int i = 0; i < reps && st == MFG_OK; ++i) {
+            if (hipEventRecord(e0, s) != hipSuccess) st = MFG_ERR_HIP;
+            r = gemm_impl(M, N, K, A, lda, B, ldb, C, ldc, 1.f, 0.f, mode, c, s);
+            if (r != MFG_OK) st = r;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = MFG_ERR_HIP;
+            float ms = 0.f;
+            if (st == MFG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MFG_ERR_HIP;
+            total += ms;
+        }
+        if (st != MFG_OK) break;
+        if ((st = launch_count_mismatch(M, N, C, ldc, ref, N, cnt, s)) != MFG_OK) break;
+        unsigned long long bad = 1;
+        if (hipMemcpyAsync(&bad, cnt, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            st = MFG_ERR_HIP;
+            break;
+        }
+        const float avg = total / reps;
+        if (bad == 0 && avg < bms) bms = avg, best = c;
+    }
+    cleanup();
+    if (st != MFG_OK) return st;
+    tuned_store(m, M, N, K, best);
+    if (best_config) *best_config = best;
+    if (best_ms) *best_ms = bms;
+    return MFG_OK;
+}
+
+extern "C" int mfg_autotune(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
+                            float* C, int64_t ldc, int mode, int reps, int* best_config, float* best_ms,
+                            void* stream) {
+    MFG_GUARD(autotune_impl(M, N, K, A, lda, B, ldb, C, ldc, mode, reps, best_config, best_ms, (hipStream_t)stream));
+}

@@ -1,0 +1,156 @@
+// gemm16.hip -- GEMM on 16-bit operand planes with FP32 accumulation on the
+// gfx950 matrix cores (v_mfma_f32_32x32x16_{f16,bf16}).
+//
+// Paper Sec. IV: C = alpha*A*B + beta*C on matrix units, FP16 inputs and FP32
+// accumulation.  Paper Sec. V, Eq. 1 and Eq. 2: the refined products
+//   REFINE_A : A_h B_h + (R_A B_h) / s
+//   SPLIT3   : A_h B_h + (A_h R_B + R_A B_h) / s
+//   SPLIT4   : SPLIT3 + (R_A R_B) / s^2
+// fused into one K loop.  A_h B_h accumulates in `hi`, the residual products
+// in `lo` (and R_A R_B in `rr`), each in FP32; the epilogue folds them with
+// the exact scale 2^-11.  One launch replaces the paper's chain of four GEMM
+// calls, so C is written once.
+//
+// Every kernel here accumulates an output element over K in the same order
+// (16-wide chunks k0 = 0, 16, 32, ...; within a chunk, products in the
+// order fixed above) and applies the same epilogue, so all tile
+// configurations of a kind give bitwise-identical results.
+#include "tile16.h"
+
+namespace mfg {
+
+// ---------------------------------------------------------------------------
+// Configuration tables and launch.
+// ---------------------------------------------------------------------------
+struct Cfg16 {
+    const char* name;
+    int bm, bn;  // 0, 0 = simple kernel
+    int group_m;
+};
+
+template <int KIND, int BM, int BN, int BK, int WM, int WN>
+static int launch_tiled(const Gemm16Args& a, int64_t batch, int group_m, hipStream_t s) {
+    using G = TileCfg<KIND, BM, BN, BK, WM, WN>;
+    auto kern = gemm16_tiled<KIND, BM, BN, BK, WM, WN>;
+    static bool attr_set = false;  // benign race: the attribute call is idempotent
+    if (!attr_set) {
+        MFG_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          G::LDS_BYTES));
+        attr_set = true;
+    }
+    const int tiles_m = (int)cdiv(a.M, BM), tiles_n = (int)cdiv(a.N, BN);
+    dim3 grid(tiles_m * tiles_n, (unsigned)batch, 1);
+    hipLaunchKernelGGL(kern, grid, dim3(G::NT), G::LDS_BYTES, s, a, tiles_m, tiles_n, group_m);
+    MFG_LAUNCH_CHECK();
+    return MFG_OK;
+}
+
+template <int KIND>
+static int launch_simple(const Gemm16Args& a, int64_t batch, bool vec_ok, hipStream_t s) {
+    dim3 grid((unsigned)cdiv(a.N, 32), (unsigned)cdiv(a.M, 32), (unsigned)batch);
+    hipLaunchKernelGGL(gemm16_simple<KIND>, grid, dim3(64), 0, s, a, vec_ok ? 1 : 0);
+    MFG_LAUNCH_CHECK();
+    return MFG_OK;
+}
+
+// Tile menus per kind.  Index 0 is the simple kernel.
+static const Cfg16 kCfgPlain[] = {
+    {"simple32", 0, 0, 0},          {"t256x256k64w2x2g8", 256, 256, 8}, {"t256x256k64w2x2g4", 256, 256, 4},
+    {"t128x128k64w2x2g8", 128, 128, 8}, {"t256x128k64w2x2g8", 256, 128, 8}, {"t128x256k64w2x2g8", 128, 256, 8},
+    {"t64x64k64w2x2g8", 64, 64, 8},
+};
+static const Cfg16 kCfgSplit[] = {
+    {"simple32", 0, 0, 0},
+    {"t256x128k32w2x2g8", 256, 128, 8},
+    {"t128x128k32w2x2g8", 128, 128, 8},
+    {"t64x64k32w2x2g8", 64, 64, 8},
+};
+static const Cfg16 kCfgSplit4[] = {
+    {"simple32", 0, 0, 0},
+    {"t128x128k32w2x2g8", 128, 128, 8},
+    {"t64x64k32w2x2g8", 64, 64, 8},
+};
+
+static const Cfg16* menu(int kind, int* n) {
+    if (kind == K_F16 || kind == K_BF16) {
+        *n = (int)(sizeof(kCfgPlain) / sizeof(kCfgPlain[0]));
+        return kCfgPlain;
+    }
+    if (kind == K_SPLIT4) {
+        *n = (int)(sizeof(kCfgSplit4) / sizeof(kCfgSplit4[0]));
+        return kCfgSplit4;
+    }
+    *n = (int)(sizeof(kCfgSplit) / sizeof(kCfgSplit[0]));
+    return kCfgSplit;
+}
+
+int num_configs16(int kind) {
+    int n;
+    menu(kind, &n);
+    return n;
+}
+
+const char* config16_name(int kind, int cfg) {
+    int n;
+    const Cfg16* m = menu(kind, &n);
+    return (cfg >= 0 && cfg < n) ? m[cfg].name : nullptr;
+}
+
+int pick_config16(int kind, int64_t M, int64_t N, int64_t K, bool vec_ok) {
+    (void)K;
+    if (!vec_ok) return 0;
+    const int64_t mn = M * N;
+    if (kind == K_F16 || kind == K_BF16) {
+        if (M >= 2048 && N >= 2048) return 1;
+        if (mn >= 512 * 512) return 3;
+        if (M >= 64 && N >= 64) return 6;
+        return 0;
+    }
+    if (kind == K_SPLIT4) {
+        if (mn >= 512 * 512) return 1;
+        if (M >= 64 && N >= 64) return 2;
+        return 0;
+    }
+    if (M >= 2048 && N >= 2048) return 1;
+    if (mn >= 512 * 512) return 2;
+    if (M >= 64 && N >= 64) return 3;
+    return 0;
+}
+
+template <int KIND>
+static int launch_kind(int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok, hipStream_t s) {
+    int n;
+    const Cfg16* m = menu(KIND, &n);
+    if (cfg < 0 || cfg >= n) return MFG_ERR_INVALID_ARG;
+    if (cfg != 0 && !vec_ok) return MFG_ERR_UNSUPPORTED;
+    const Cfg16& c = m[cfg];
+    if (c.bm == 0) return launch_simple<KIND>(a, batch, vec_ok, s);
+    if constexpr (KIND == K_F16 || KIND == K_BF16) {
+        if (c.bm == 256 && c.bn == 256) return launch_tiled<KIND, 256, 256, 64, 2, 2>(a, batch, c.group_m, s);
+        if (c.bm == 128 && c.bn == 128) return launch_tiled<KIND, 128, 128, 64, 2, 2>(a, batch, c.group_m, s);
+        if (c.bm == 256 && c.bn == 128) return launch_tiled<KIND, 256, 128, 64, 2, 2>(a, batch, c.group_m, s);
+        if (c.bm == 128 && c.bn == 256) return launch_tiled<KIND, 128, 256, 64, 2, 2>(a, batch, c.group_m, s);
+        if (c.bm == 64 && c.bn == 64) return launch_tiled<KIND, 64, 64, 64, 2, 2>(a, batch, c.group_m, s);
+    } else if constexpr (KIND == K_SPLIT4) {
+        if (c.bm == 128 && c.bn == 128) return launch_tiled<KIND, 128, 128, 32, 2, 2>(a, batch, c.group_m, s);
+        if (c.bm == 64 && c.bn == 64) return launch_tiled<KIND, 64, 64, 32, 2, 2>(a, batch, c.group_m, s);
+    } else {
+        if (c.bm == 256 && c.bn == 128) return launch_tiled<KIND, 256, 128, 32, 2, 2>(a, batch, c.group_m, s);
+        if (c.bm == 128 && c.bn == 128) return launch_tiled<KIND, 128, 128, 32, 2, 2>(a, batch, c.group_m, s);
+        if (c.bm == 64 && c.bn == 64) return launch_tiled<KIND, 64, 64, 32, 2, 2>(a, batch, c.group_m, s);
+    }
+    return MFG_ERR_INTERNAL;
+}
+
+int launch_gemm16(int kind, int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok, hipStream_t s) {
+    switch (kind) {
+        case K_F16: return launch_kind<K_F16>(cfg, a, batch, vec_ok, s);
+        case K_BF16: return launch_kind<K_BF16>(cfg, a, batch, vec_ok, s);
+        case K_REFINE_A: return launch_kind<K_REFINE_A>(cfg, a, batch, vec_ok, s);
+        case K_SPLIT3: return launch_kind<K_SPLIT3>(cfg, a, batch, vec_ok, s);
+        case K_SPLIT4: return launch_kind<K_SPLIT4>(cfg, a, batch, vec_ok, s);
+        default: return MFG_ERR_INVALID_ARG;
+    }
+}
+
+}  // namespace mfg

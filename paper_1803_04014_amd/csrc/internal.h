@@ -1,0 +1,130 @@
+// internal.h -- private declarations shared by libmfgemm's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mfgemm.h"
+
+namespace mfg {
+
+// Records a failed HIP call for mfg_last_hip_error() (per thread) and
+// returns MFG_ERR_HIP.
+int hip_fail(hipError_t e);
+
+#define MFG_HIP_CHECK(call)                                    \
+    do {                                                       \
+        hipError_t mfg_e_ = (call);                            \
+        if (mfg_e_ != hipSuccess) return ::mfg::hip_fail(mfg_e_); \
+    } while (0)
+
+// After a kernel launch: report a launch error.
+#define MFG_LAUNCH_CHECK() MFG_HIP_CHECK(hipGetLastError())
+
+// Per-(device, stream) workspace.  Returns a device pointer holding at least
+// `bytes`, or nullptr with *status set.  The region stays valid until the
+// next workspace() call on the same stream; growing it synchronises the
+// stream before freeing the old region.
+void* workspace(hipStream_t s, size_t bytes, int* status);
+// A second, independent per-stream region for reduction partials.
+void* scratch(hipStream_t s, size_t bytes, int* status);
+// Number of compute units of the current device (cached).
+int device_cu_count();
+
+// -------------------------------------------------------------- arguments
+// One GEMM (or a strided batch of them) on 16-bit planes.  A[p] / B[p] are
+// the head (p = 0) and scaled-residual (p = 1) planes.
+struct Gemm16Args {
+    int64_t M, N, K;
+    const uint16_t* A[2];
+    const uint16_t* B[2];
+    float* C;
+    int64_t lda, ldb, ldc;
+    int64_t sA, sB, sC;  // batch strides (elements)
+    float alpha, beta;
+};
+
+struct GemmF32Args {
+    int64_t M, N, K;
+    const float* A;
+    const float* B;
+    float* C;
+    int64_t lda, ldb, ldc;
+    int64_t sA, sB, sC;
+    float alpha, beta;
+};
+
+struct GemmF8Args {
+    int64_t M, N, K;
+    const uint8_t* A;    // codes
+    const uint8_t* B;
+    const float* sa;     // ceil(M/128) x ceil(K/128)
+    const float* sb;     // ceil(K/128) x ceil(N/128)
+    float* C;
+    int64_t lda, ldb, ldc;
+    float alpha, beta;
+};
+
+// Kernel families.  `kind` selects the operand format and products:
+enum Kind16 { K_F16 = 0, K_BF16 = 1, K_REFINE_A = 2, K_SPLIT3 = 3, K_SPLIT4 = 4 };
+
+// Tile configurations (index 0 is always the simple one-wave-per-32x32 kernel).
+int num_configs16(int kind);
+const char* config16_name(int kind, int cfg);
+int pick_config16(int kind, int64_t M, int64_t N, int64_t K, bool vec_ok);
+int launch_gemm16(int kind, int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok, hipStream_t s);
+
+int num_configs_f32();
+const char* config_f32_name(int cfg);
+int pick_config_f32(int64_t M, int64_t N, int64_t K, bool vec_ok);
+int launch_gemm_f32(int cfg, const GemmF32Args& a, int64_t batch, bool vec_ok, hipStream_t s);
+
+int num_configs_f8();
+const char* config_f8_name(int cfg);
+int pick_config_f8(int64_t M, int64_t N, int64_t K, bool vec_ok);
+int launch_gemm_f8(int cfg, const GemmF8Args& a, bool vec_ok, hipStream_t s);
+
+// Conversions (convert.hip).
+int launch_round_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* out,
+                     int64_t ldo, hipStream_t s);
+int launch_round_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* out,
+                      int64_t ldo, hipStream_t s);
+int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head,
+                     uint16_t* resid, int64_t ldo, double* norms, hipStream_t s);
+int launch_quantize_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint8_t* codes,
+                        int64_t ldo, float* scales, hipStream_t s);
+int launch_error_norms(int64_t M, int64_t N, const float* C, int64_t ldc, const double* R,
+                       int64_t ldr, double* out4, hipStream_t s);
+int launch_count_mismatch(int64_t M, int64_t N, const float* C, int64_t ldc, const float* R,
+                          int64_t ldr, unsigned long long* out, hipStream_t s);
+int launch_scale_c(int64_t M, int64_t N, float* C, int64_t ldc, float beta, int64_t batch,
+                   int64_t sC, hipStream_t s);
+
+// Batched and grouped launches (batched.hip).
+struct GroupedDesc {  // one problem, device resident
+    int64_t M, N, K, lda, ldb, ldc;
+    const uint16_t* A;
+    const uint16_t* B;
+    float* C;
+    int32_t vec;  // 1: 16-byte aligned rows (LDS-staged tile), 0: per-wave tile
+    int32_t pad;
+};
+struct GroupedWork {  // one 64 x 64 output tile of one problem
+    int32_t prob, tm, tn, pad;
+};
+int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_ok, int num_cu,
+                         hipStream_t s);
+int grouped_launch(int kind, const GroupedDesc* descs, const GroupedWork* work, int64_t nwork,
+                   int grid, float alpha, float beta, hipStream_t s);
+int grouped_lds_bytes();
+
+// Validation (validate.cpp; pure host code).
+int validate_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
+                  int64_t ldb, const void* C, int64_t ldc, int mode);
+int validate_matrix(int64_t rows, int64_t cols, const void* X, int64_t ld);
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace mfg
