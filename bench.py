@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of libmfgemm on one MI355X.
+
+Headline step: one FP16-in / FP32-accumulate GEMM  C = A B + C  at
+M = N = K = 8192 (alpha = beta = 1, row-major), the size at which the paper
+reports its best matrix-unit GEMM (Sec. VII.A).  A and B are FP32 uniform in
+[-1, 1] rounded to FP16 before timing (the paper leaves the rounding out of
+its timings, Sec. VI); C0 is uniform in [-1, 1].  Inputs are resident in HBM
+when the timed region starts.
+
+Prints ONE JSON line.  Besides the headline it carries:
+  roofline      the GEMM kernel's average launch time (HIP events on the
+                stream it runs on) against the dense FP16 MFMA peak;
+  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of rows of the
+                same GEMM (the rows it computes also give the FP64 reference
+                for the error figures);
+  errors        max and Frobenius relative error vs FP64 on those rows, for
+                FP16, the split-refined mode and FP32 (reduced on the GPU);
+  extras        BF16 / FP32 / refined / FP8 rates at 8192, an N sweep, the
+                batched and grouped workloads (GEMM/s, % of HBM roofline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TFLOP/s and % MFMA peak at max-rel-err vs FP64; batched GEMM/s; p50/p99 latency"
+PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
+HBM_GBS = 8000.0
+PAPER_V100_TFLOPS = 83.0   # best mixed-precision GEMM on V100, N=8192 (context)
+KERNEL_SOURCES = ["paper_1803_04014_amd/csrc/tile16.h", "paper_1803_04014_amd/csrc/gemm16.hip",
+                  "paper_1803_04014_amd/csrc/device.h"]
+PMC_FILE = os.path.join(ROOT, "profiles", "gemm_f16_n8192_pmc.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(fn, reps, warm=2):
+    """Average milliseconds of fn() over reps launches, HIP events on the current stream."""
+    import torch
+
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle time for cpu_baseline")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build is single-GPU)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1803_04014_amd as mfg
+    import workloads
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    N = args.n
+    log(f"bench: generating inputs N={N}")
+    A32, B32, C0 = workloads.uniform(2, [(N, N), (N, N), (N, N)])
+    dA32 = torch.from_numpy(A32).to(dev)
+    dB32 = torch.from_numpy(B32).to(dev)
+    dC0 = torch.from_numpy(C0).to(dev)
+    dA = torch.empty((N, N), dtype=torch.float16, device=dev)
+    dB = torch.empty((N, N), dtype=torch.float16, device=dev)
+    mfg.round_f16(dA32, dA)   # untimed rounding (paper Sec. VI)
+    mfg.round_f16(dB32, dB)
+    dC = dC0.clone()
+    flops = 2.0 * N * N * N
+
+    def step():
+        mfg.gemm(dA, dB, dC, 1.0, 1.0, mode="f16", preconverted=True)
+
+    log("bench: warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    log("bench: timed steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record()
+        step()
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    value = flops * args.steps / wall / 1e12
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+
+    traffic = None
+    if os.path.exists(PMC_FILE):
+        with open(PMC_FILE) as f:
+            pmc = json.load(f)
+        if pmc.get("kernel_hash") == kernel_hash() and pmc.get("n") == N:
+            traffic = pmc.get("hbm_bytes_per_launch")
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": round(value / PAPER_V100_TFLOPS, 2), "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": f"square GEMM C=A*B+C, M=N=K={N}, FP16 inputs (FP32 uniform[-1,1] rounded, "
+                               "untimed), FP32 accumulate and output, alpha=beta=1, row-major",
+                   "M": N, "N": N, "K": N, "mode": "f16", "seed": 2},
+        "pct_mfma_peak": round(100.0 * value / PEAK_TFLOPS["f16"], 2),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["f16"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f16"], 4), "traffic": traffic,
+                     "kernel_ms": round(kernel_ms, 4), "kernel_hash": kernel_hash()},
+    }
+    log(f"bench: f16 N={N}: {value:.1f} TFLOP/s wall, kernel {kernel_ms:.3f} ms -> {achieved:.1f} TFLOP/s")
+
+    # fresh result for the error figures: C = A B + C0 once
+    results = {}
+    dC.copy_(dC0)
+    step()
+    results["f16"] = dC
+    if not args.no_extras:
+        dCs = dC0.clone()
+        mfg.gemm(dA32, dB32, dCs, 1.0, 1.0, mode="split3")
+        results["split3"] = dCs
+        dCf = dC0.clone()
+        mfg.gemm(dA32, dB32, dCf, 1.0, 1.0, mode="f32")
+        results["f32"] = dCf
+    torch.cuda.synchronize()
+
+    # ----------------------------------------------------- CPU oracle leg
+    if not args.no_cpu:
+        import oracle  # the FP64 CPU oracle: only this leg of the benchmark uses it
+
+        rows_probe = np.arange(0, N, max(1, N // 8))[:8]
+        t = time.perf_counter()
+        oracle.exact(A32, B32, 1.0, 1.0, C0, rows=rows_probe)
+        per_row = (time.perf_counter() - t) / len(rows_probe)
+        nrows = int(max(8, min(N, args.cpu_seconds / max(per_row, 1e-6))))
+        rows = np.unique(np.linspace(0, N - 1, nrows).astype(np.int64))
+        log(f"bench: cpu oracle on {len(rows)} rows")
+        t = time.perf_counter()
+        ref = oracle.exact(A32, B32, 1.0, 1.0, C0, rows=rows)
+        cpu_s = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(2.0 * len(rows) * N * N / cpu_s / 1e12, 5), "unit": "TFLOP/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"FP64 GEMM of {len(rows)} of {N} rows (x {N} x {N}), {cpu_s:.1f} s"}
+        # FP64 error reductions on the GPU (rows of C against the oracle's rows)
+        dref = torch.from_numpy(ref).to(dev)
+        ridx = torch.from_numpy(rows).to(dev)
+        errs = {}
+        for name, t_c in results.items():
+            sub = t_c.index_select(0, ridx).contiguous()
+            o4 = torch.zeros(4, dtype=torch.float64, device=dev)
+            mfg.error_norms(sub, dref, o4)
+            o = o4.cpu().numpy()
+            errs[name] = {"max_rel": float(o[0] / o[3]), "fro_rel": float(o[1] / o[2])}
+        out["errors_vs_fp64"] = errs
+        out["max_rel_err_vs_fp64"] = errs["f16"]["max_rel"]
+
+    # ------------------------------------------------------------- extras
+    if not args.no_extras:
+        ex = {}
+        reps = 10
+        dAb = torch.empty((N, N), dtype=torch.bfloat16, device=dev)
+        dBb = torch.empty((N, N), dtype=torch.bfloat16, device=dev)
+        mfg.round_bf16(dA32, dAb)
+        mfg.round_bf16(dB32, dBb)
+        dCx = dC0.clone()
+        ms = timed(lambda: mfg.gemm(dAb, dBb, dCx, 1.0, 1.0, mode="bf16", preconverted=True), reps)
+        ex["bf16_n8192"] = {"tflops": round(flops / ms / 1e9, 1), "pct_peak": round(flops / ms / 1e9 / 25.0, 1)}
+        ms = timed(lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode="f32"), 3, warm=1)
+        ex["f32_n8192"] = {"tflops": round(flops / ms / 1e9, 1), "pct_peak": round(flops / ms / 1e9 / 1.573, 1)}
+        for mode in ("refine_a", "split3", "split4", "fp8"):
+            ms = timed(lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode=mode), 3, warm=1)
+            ex[f"{mode}_n8192_fp32_in"] = {"useful_tflops": round(flops / ms / 1e9, 1), "ms": round(ms, 3)}
+        # N sweep (FP16, preconverted)
+        sweep = {}
+        for n in (1024, 2048, 4096):
+            a = dA[:n, :n].contiguous()
+            b = dB[:n, :n].contiguous()
+            c = dC0[:n, :n].contiguous()
+            ms = timed(lambda: mfg.gemm(a, b, c, 1.0, 1.0, mode="f16", preconverted=True), 20)
+            sweep[str(n)] = round(2.0 * n ** 3 / ms / 1e9, 1)
+        ex["f16_sweep_tflops"] = sweep
+        # batched 65536 x 16^3 and 16384 x 64^3 (FP16 in, FP32 out, alpha=1, beta=0)
+        for cnt, s in ((65536, 16), (16384, 64)):
+            a16, b16 = (torch.empty((cnt, s, s), dtype=torch.float16, device=dev).uniform_(-1, 1) for _ in range(2))
+            c = torch.empty((cnt, s, s), dtype=torch.float32, device=dev)
+            ms = timed(lambda: mfg.gemm_batched(a16, b16, c, 1.0, 0.0, mode="f16"), 20)
+            byts = cnt * (2 * 2 * s * s + 4 * s * s)
+            ex[f"batched_{cnt}x{s}^3"] = {"gemm_per_s": round(cnt / ms * 1e3, 1), "tflops": round(2 * cnt * s ** 3 / ms / 1e9, 2),
+                                          "hbm_gbs": round(byts / ms / 1e6, 1),
+                                          "pct_hbm": round(100 * byts / ms / 1e6 / HBM_GBS, 1), "us": round(ms * 1e3, 2)}
+            del a16, b16, c
+        # grouped: 4096 problems, M, N, K log-uniform in [16, 512]
+        dims = workloads.loguniform_dims(6, 4096, 16, 512)
+        probs = []
+        for (m_, n_, k_) in dims:
+            lda, ldb = -(-int(k_) // 8) * 8, -(-int(n_) // 8) * 8
+            a = torch.empty((m_, lda), dtype=torch.float16, device=dev).uniform_(-1, 1)[:, :k_]
+            b = torch.empty((k_, ldb), dtype=torch.float16, device=dev).uniform_(-1, 1)[:, :n_]
+            probs.append((a, b, torch.empty((m_, n_), dtype=torch.float32, device=dev)))
+        plan = mfg.GroupedPlan(probs, "f16")
+        info = plan.info()
+        ms = timed(lambda: plan.graph_launch(1.0, 0.0), 20)
+        ex["grouped_4096"] = {"gemm_per_s": round(4096 / ms * 1e3, 1), "tflops": round(info["flops"] / ms / 1e9, 2),
+                              "hbm_gbs": round(info["bytes"] / ms / 1e6, 1),
+                              "pct_hbm": round(100 * info["bytes"] / ms / 1e6 / HBM_GBS, 1), "us": round(ms * 1e3, 1),
+                              "work_items": info["work_items"]}
+        plan.close()
+        out["extras"] = ex
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

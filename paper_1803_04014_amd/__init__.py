@@ -42,6 +42,8 @@ def _ptr(t):
 
 
 def _ld(t) -> int:
+    if t.dim() == 2 and t.numel() == 0:
+        return max(1, t.shape[1])
     if t.dim() != 2 or t.stride(1) != 1:
         raise ValueError("expected a 2-D row-major tensor with unit column stride")
     return max(1, t.stride(0))

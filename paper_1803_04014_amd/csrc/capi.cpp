@@ -212,7 +212,7 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
 
     const int kind = kind_of(m);
     Gemm16Args a{};
-    a.M = M, a.N = N, a.K = K, a.ldc = ldc, a.sC = strideC, a.alpha = alpha, a.beta = beta;
+    a.M = M, a.N = N, a.K = K, a.C = C, a.ldc = ldc, a.sC = strideC, a.alpha = alpha, a.beta = beta;
     bool vec;
     const bool split_mode = (m == MFG_F16_REFINE_A || m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4);
     std::unique_ptr<WsLease> ws;

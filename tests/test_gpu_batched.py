@@ -1,0 +1,119 @@
+"""GPU tests of the batched forms (paper Sec. IV.B: many small GEMMs at once).
+
+Each problem of a batched or grouped launch must be bitwise identical to the
+same problem run alone through mfg_gemm (all kernels share one accumulation
+order), and within the parity tolerance of the oracle on sampled problems.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1803_04014_amd as mfg
+import workloads
+from gpu_util import DEV, assert_parity, dev, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _solo(mode, A, B, C0, alpha, beta, preconverted):
+    C = C0.clone()
+    mfg.gemm(A, B, C, alpha, beta, mode=mode, preconverted=preconverted)
+    return C
+
+
+@pytest.mark.parametrize("mode,shape,count", [
+    ("f16", (16, 16, 16), 1000), ("bf16", (16, 16, 16), 333), ("f16", (17, 9, 100), 257),
+    ("f16", (64, 64, 64), 300), ("f16", (33, 70, 48), 65), ("f32", (16, 16, 16), 200), ("f32", (64, 64, 64), 50),
+])
+def test_batched_equals_solo_and_oracle(mode, shape, count):
+    M, N, K = shape
+    A32, B32, C0 = workloads.uniform(21, [(count, M, K), (count, K, N), (count, M, N)])
+    if mode in ("f16", "bf16"):
+        dt = torch.float16 if mode == "f16" else torch.bfloat16
+        dA, dB = dev(A32).to(dt), dev(B32).to(dt)
+    else:
+        dA, dB = dev(A32), dev(B32)
+    dC = dev(C0)
+    mfg.gemm_batched(dA, dB, dC, 1.5, 0.5, mode=mode)
+    got = host(dC)
+    pre = mode != "f32"
+    for b in list(range(0, count, max(1, count // 12))) + [count - 1]:
+        solo = host(_solo(mode, dA[b], dB[b], dev(C0[b]), 1.5, 0.5, pre))
+        assert np.array_equal(got[b].view(np.uint32), solo.view(np.uint32)), f"problem {b} differs from solo"
+        Ab = host(dA[b].float()).astype(np.float32)
+        Bb = host(dB[b].float()).astype(np.float32)
+        ref = oracle.reference("f32", Ab, Bb, 1.5, 0.5, C0[b])  # operands already rounded
+        assert_parity(got[b], ref, f"{mode} problem {b}")
+
+
+@pytest.mark.parametrize("mode", ["split3", "refine_a", "split4"])
+def test_batched_refined_equals_solo(mode):
+    count, M, N, K = 96, 16, 16, 40
+    A, B, C0 = workloads.normal(22, [(count, M, K), (count, K, N), (count, M, N)])
+    dC = dev(C0)
+    mfg.gemm_batched(dev(A), dev(B), dC, 1.0, 1.0, mode=mode)
+    got = host(dC)
+    for b in (0, 1, 47, 95):
+        solo = np.copy(C0[b])
+        d = dev(solo)
+        mfg.gemm(dev(A[b]), dev(B[b]), d, 1.0, 1.0, mode=mode)
+        assert np.array_equal(got[b].view(np.uint32), host(d).view(np.uint32))
+        assert_parity(got[b], oracle.reference(mode, A[b], B[b], 1.0, 1.0, C0[b]), f"{mode} problem {b}")
+
+
+def _grouped_problems(count, lo, hi, seed, unaligned_every=0):
+    dims = workloads.loguniform_dims(seed, count, lo, hi)
+    probs, host_ops = [], []
+    for i, (m, n, k) in enumerate(dims):
+        m, n, k = int(m), int(n), int(k)
+        if unaligned_every and i % unaligned_every == 0:
+            lda, ldb = k, n  # unaligned leading dimensions -> per-wave tile path
+        else:
+            lda, ldb = -(-k // 8) * 8, -(-n // 8) * 8
+        A, B = workloads.uniform(1000 + i, [(m, lda), (k, ldb)])
+        dA = dev(A).half()[:, :k]
+        dB = dev(B).half()[:, :n]
+        dC = torch.zeros((m, n), dtype=torch.float32, device=DEV)
+        probs.append((dA, dB, dC))
+        host_ops.append((A[:, :k], B[:, :n]))
+    return probs, host_ops
+
+
+def test_grouped_equals_solo_and_graph_replays():
+    probs, host_ops = _grouped_problems(300, 16, 200, 6, unaligned_every=7)
+    plan = mfg.GroupedPlan(probs, "f16")
+    info = plan.info()
+    assert info["work_items"] == sum(-(-p[0].shape[0] // 64) * -(-p[1].shape[1] // 64) for p in probs)
+    plan.run(1.0, 0.0)
+    first = [host(p[2]).copy() for p in probs]
+    for i in range(0, 300, 23):
+        A, B, C = probs[i]
+        solo = torch.zeros_like(C)
+        mfg.gemm(A, B, solo, 1.0, 0.0, mode="f16", preconverted=True)
+        assert np.array_equal(first[i].view(np.uint32), host(solo).view(np.uint32)), f"problem {i}"
+        a16 = oracle.f16_round(host_ops[i][0]).astype(np.float32)
+        b16 = oracle.f16_round(host_ops[i][1]).astype(np.float32)
+        assert_parity(first[i], oracle.reference("f32", a16, b16), f"grouped problem {i}")
+    # graph replays with eager work in between; every replay must equal the eager result
+    for rep in range(3):
+        for p in probs:
+            p[2].fill_(float("nan"))
+        plan.graph_launch(1.0, 0.0)
+        junk = torch.randn(512, 512, device=DEV) @ torch.randn(512, 512, device=DEV)  # unrelated eager work
+        torch.cuda.synchronize()
+        del junk
+        for i in range(0, 300, 11):
+            assert np.array_equal(host(probs[i][2]).view(np.uint32), first[i].view(np.uint32)), f"replay {rep} problem {i}"
+    plan.close()
+
+
+def test_grouped_rejects_unsupported_mode():
+    probs, _ = _grouped_problems(4, 16, 64, 9)
+    with pytest.raises(mfg.MfgError):
+        mfg.GroupedPlan(probs, "split3")

@@ -50,7 +50,12 @@ def test_mode_parity_all_configs(mode, shape):
     bound = oracle.representation_bound(mode, A, B, 1.25)
     outs = []
     for cfg in range(mfg.num_configs(mode)):
-        C = run_gemm(mode, A, B, C0, 1.25, -0.5, config=cfg)
+        try:
+            C = run_gemm(mode, A, B, C0, 1.25, -0.5, config=cfg)
+        except mfg.MfgError as e:
+            # tiled FP32 kernels need 16-byte aligned rows (lda % 4 == 0); others report it
+            assert mode == "f32" and cfg > 0 and e.status == mfg.capi.MFG_ERR_UNSUPPORTED and K % 4 != 0
+            continue
         err, tol = assert_parity(C, ref, f"{mode} cfg {cfg} {mfg.config_name(mode, cfg)}")
         # a-priori accuracy against the exact product
         assert np.all(np.abs(C - ex) <= bound + tol), f"{mode} cfg {cfg}: beyond the accuracy bound"
