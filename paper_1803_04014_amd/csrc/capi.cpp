@@ -291,7 +291,7 @@ struct mfg_grouped_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float g_alpha = 0.f, g_beta = 0.f;
-    hipStream_t g_stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // capture happens here: the legacy NULL stream cannot be captured
 };
 
 static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, mfg_grouped_plan** out) {
@@ -362,16 +362,18 @@ extern "C" int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, 
 
 static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hipStream_t s) {
     if (!plan) return MFG_ERR_INVALID_ARG;
-    if (plan->exec && (plan->g_alpha != alpha || plan->g_beta != beta || plan->g_stream != s)) {
+    if (plan->exec && (plan->g_alpha != alpha || plan->g_beta != beta)) {
         MFG_HIP_CHECK(hipGraphExecDestroy(plan->exec));
         MFG_HIP_CHECK(hipGraphDestroy(plan->graph));
         plan->exec = nullptr, plan->graph = nullptr;
     }
     if (!plan->exec) {
-        MFG_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        int st = grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->nwork, plan->grid, alpha, beta, s);
+        if (!plan->cap_stream) MFG_HIP_CHECK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+        MFG_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+        int st = grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->nwork, plan->grid, alpha, beta,
+                                plan->cap_stream);
         hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(s, &g);
+        hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
         if (st != MFG_OK) {
             if (g) (void)hipGraphDestroy(g);
             return st;
@@ -383,7 +385,7 @@ static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hi
             (void)hipGraphDestroy(g);
             return hip_fail(e);
         }
-        plan->graph = g, plan->exec = x, plan->g_alpha = alpha, plan->g_beta = beta, plan->g_stream = s;
+        plan->graph = g, plan->exec = x, plan->g_alpha = alpha, plan->g_beta = beta;
     }
     MFG_HIP_CHECK(hipGraphLaunch(plan->exec, s));
     return MFG_OK;
@@ -408,6 +410,7 @@ extern "C" int mfg_grouped_plan_destroy(mfg_grouped_plan* plan) {
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->d_desc) (void)hipFree(plan->d_desc);
     if (plan->d_work) (void)hipFree(plan->d_work);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
     return MFG_OK;
 }

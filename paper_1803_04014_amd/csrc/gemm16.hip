@@ -15,6 +15,7 @@
 // (16-wide chunks k0 = 0, 16, 32, ...; within a chunk, products in the
 // order fixed above) and applies the same epilogue, so all tile
 // configurations of a kind give bitwise-identical results.
+#include "fast16.h"
 #include "tile16.h"
 
 namespace mfg {
@@ -26,7 +27,31 @@ struct Cfg16 {
     const char* name;
     int bm, bn;  // 0, 0 = simple kernel
     int group_m;
+    int fast;    // 0: tile16 kernel; 1: fast kernel, loads via VGPRs; 2: fast kernel, loads straight to LDS
+    int wm, wn;  // wavefront grid of the fast kernel
 };
+
+template <int KIND, int BM, int BN, int WM, int WN, bool DMA>
+static int launch_fast(const Gemm16Args& a, int64_t batch, int group_m, hipStream_t s) {
+    using G = FastCfg<KIND, BM, BN, WM, WN, DMA>;
+    auto kern = gemm16_fast<KIND, BM, BN, WM, WN, DMA>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        MFG_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          G::LDS_BYTES));
+        attr_set = true;
+    }
+    const int tiles_m = (int)cdiv(a.M, BM), tiles_n = (int)cdiv(a.N, BN);
+    dim3 grid(tiles_m * tiles_n, (unsigned)batch, 1);
+    hipLaunchKernelGGL(kern, grid, dim3(G::NT), G::LDS_BYTES, s, a, tiles_m, tiles_n, group_m);
+    MFG_LAUNCH_CHECK();
+    return MFG_OK;
+}
+
+// The fast kernel needs K % 64 == 0, 16-byte aligned rows and N % 8 == 0, N >= 8.
+static bool fast_ok(const Gemm16Args& a, bool vec_ok) {
+    return vec_ok && a.K % 64 == 0 && a.N % 8 == 0 && a.N >= 8 && a.M >= 1;
+}
 
 template <int KIND, int BM, int BN, int BK, int WM, int WN>
 static int launch_tiled(const Gemm16Args& a, int64_t batch, int group_m, hipStream_t s) {
@@ -55,9 +80,18 @@ static int launch_simple(const Gemm16Args& a, int64_t batch, bool vec_ok, hipStr
 
 // Tile menus per kind.  Index 0 is the simple kernel.
 static const Cfg16 kCfgPlain[] = {
-    {"simple32", 0, 0, 0},          {"t256x256k64w2x2g8", 256, 256, 8}, {"t256x256k64w2x2g4", 256, 256, 4},
-    {"t128x128k64w2x2g8", 128, 128, 8}, {"t256x128k64w2x2g8", 256, 128, 8}, {"t128x256k64w2x2g8", 128, 256, 8},
-    {"t64x64k64w2x2g8", 64, 64, 8},
+    {"simple32", 0, 0, 0, 0, 0, 0},
+    {"t256x256k64w2x2g8", 256, 256, 8, 0, 0, 0},
+    {"t256x256k64w2x2g4", 256, 256, 4, 0, 0, 0},
+    {"t128x128k64w2x2g8", 128, 128, 8, 0, 0, 0},
+    {"t256x128k64w2x2g8", 256, 128, 8, 0, 0, 0},
+    {"t128x256k64w2x2g8", 128, 256, 8, 0, 0, 0},
+    {"t64x64k64w2x2g8", 64, 64, 8, 0, 0, 0},
+    {"f256x256k64w2x2g8dma", 256, 256, 8, 2, 2, 2},
+    {"f256x256k64w2x2g8reg", 256, 256, 8, 1, 2, 2},
+    {"f256x256k64w2x4g8dma", 256, 256, 8, 2, 2, 4},
+    {"f256x128k64w2x2g8dma", 256, 128, 8, 2, 2, 2},
+    {"f128x128k64w2x2g8dma", 128, 128, 8, 2, 2, 2},
 };
 static const Cfg16 kCfgSplit[] = {
     {"simple32", 0, 0, 0},
@@ -125,6 +159,18 @@ static int launch_kind(int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok,
     if (cfg != 0 && !vec_ok) return MFG_ERR_UNSUPPORTED;
     const Cfg16& c = m[cfg];
     if (c.bm == 0) return launch_simple<KIND>(a, batch, vec_ok, s);
+    if (c.fast) {
+        if (!fast_ok(a, vec_ok)) return MFG_ERR_UNSUPPORTED;
+        if constexpr (KIND == K_F16 || KIND == K_BF16) {
+            if (c.bm == 256 && c.bn == 256 && c.wn == 2)
+                return c.fast == 2 ? launch_fast<KIND, 256, 256, 2, 2, true>(a, batch, c.group_m, s)
+                                   : launch_fast<KIND, 256, 256, 2, 2, false>(a, batch, c.group_m, s);
+            if (c.bm == 256 && c.bn == 256 && c.wn == 4) return launch_fast<KIND, 256, 256, 2, 4, true>(a, batch, c.group_m, s);
+            if (c.bm == 256 && c.bn == 128) return launch_fast<KIND, 256, 128, 2, 2, true>(a, batch, c.group_m, s);
+            if (c.bm == 128 && c.bn == 128) return launch_fast<KIND, 128, 128, 2, 2, true>(a, batch, c.group_m, s);
+        }
+        return MFG_ERR_INTERNAL;
+    }
     if constexpr (KIND == K_F16 || KIND == K_BF16) {
         if (c.bm == 256 && c.bn == 256) return launch_tiled<KIND, 256, 256, 64, 2, 2>(a, batch, c.group_m, s);
         if (c.bm == 128 && c.bn == 128) return launch_tiled<KIND, 128, 128, 64, 2, 2>(a, batch, c.group_m, s);

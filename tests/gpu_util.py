@@ -38,8 +38,23 @@ def run_gemm(mode, A, B, C0=None, alpha=1.0, beta=0.0, config=-1):
     return host(dC)
 
 
-def assert_parity(C, ref: oracle.Reference, what=""):
+# The gfx950 E4M3 matrix instruction does not add its 64 products exactly in
+# FP32: measured, its error is at most 2^-12 of the sum of |products| of one
+# instruction (tests/test_gpu_fp8_model.py pins this).  Summed over the
+# instructions of a dot product that is <= 2^-12 * (|A~||B~|)_ij; the FP8
+# parity bar takes twice that on top of the FP32 accumulation term.
+FP8_MFMA_REL = 2.0 ** -11
+
+
+def parity_tolerance(ref: oracle.Reference, mode: str = "") -> float:
     tol = oracle.parity_tol(ref)
+    if mode == "fp8" and ref.absval.size:
+        tol += FP8_MFMA_REL * float(np.max(ref.absval))
+    return tol
+
+
+def assert_parity(C, ref: oracle.Reference, what="", mode=""):
+    tol = parity_tolerance(ref, mode or what.split(" ")[0])
     err = float(np.max(np.abs(C.astype(np.float64) - ref.value))) if C.size else 0.0
     assert np.all(np.isfinite(C)), f"{what}: non-finite output"
     assert err <= tol, f"{what}: |C - R_mode|_max = {err:.3e} > tol {tol:.3e}"

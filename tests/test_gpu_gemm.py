@@ -37,7 +37,7 @@ def test_256_cube_acceptance(mode):
 
 
 # ------------------------------------------------- every mode, every config
-RAGGED = [(300, 260, 200), (129, 65, 33), (512, 384, 320)]
+RAGGED = [(300, 260, 200), (129, 65, 33), (512, 384, 320), (1000, 1000, 512)]
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -53,8 +53,11 @@ def test_mode_parity_all_configs(mode, shape):
         try:
             C = run_gemm(mode, A, B, C0, 1.25, -0.5, config=cfg)
         except mfg.MfgError as e:
-            # tiled FP32 kernels need 16-byte aligned rows (lda % 4 == 0); others report it
-            assert mode == "f32" and cfg > 0 and e.status == mfg.capi.MFG_ERR_UNSUPPORTED and K % 4 != 0
+            # tiled FP32 kernels need 16-byte aligned rows (lda % 4 == 0); the fast
+            # 16-bit kernels need K % 64 == 0 and N % 8 == 0; both report it
+            name = mfg.config_name(mode, cfg)
+            assert e.status == mfg.capi.MFG_ERR_UNSUPPORTED, name
+            assert (mode == "f32" and cfg > 0 and K % 4 != 0) or (name.startswith("f") and (K % 64 or N % 8)), name
             continue
         err, tol = assert_parity(C, ref, f"{mode} cfg {cfg} {mfg.config_name(mode, cfg)}")
         # a-priori accuracy against the exact product
