@@ -13,9 +13,10 @@
 //     values of one column) comes from two ds_read_b64_tr_b16: in each group
 //     of 16 lanes, lane 4j+q points at 4 columns of row j and lane i receives
 //     column i of the 4 rows, i.e. the transpose happens in the LDS read.
-//   - LDS swizzles (16-byte chunks): A row r stores chunk c at c ^ S(r) with
-//     S(r) = (r ^ (r >> 3)) & 7; B row k stores chunk c at c ^ F[k & 3] with
-//     F = {0, 6, 12, 10}.  Both make the operand reads bank-conflict free for
+//   - LDS swizzles (16-byte chunks): an A row of BK = 64 halfs stores chunk
+//     c at c ^ ((r ^ (r >> 3)) & 7), a row of BK = 32 at
+//     c ^ (((r >> 1) ^ (r >> 3)) & 3); B row k stores chunk c at c ^ F[k & 3]
+//     with F = {0, 6, 12, 10}.  Both make the operand reads bank-conflict free for
 //     a 32-bank (128 B) and a 64-bank (256 B) LDS.
 //   - Two LDS stages.  A K step first reads all of its operand fragments
 //     from LDS, then issues the loads of step t+1 into the other stage, then
@@ -39,9 +40,11 @@ __device__ __forceinline__ int swzB(int k) {
     return (int)((0xA0C0600u >> ((k & 3) * 8)) & 0xFu);
 }
 
-template <int KIND, int BM, int BN, int WM, int WN, bool DMA>
+template <int KIND, int BM, int BN, int WM, int WN, bool DMA, int BK_ = 64>
 struct FastCfg {
-    static constexpr int BK = 64;
+    static constexpr int BK = BK_;
+    static constexpr int CPR = BK / 8;            // 16-byte chunks per A row
+    static constexpr int A_ROWS_PER_INSTR = 512 / BK;
     static constexpr int NT = 64 * WM * WN;
     static constexpr int NW = WM * WN;
     static constexpr int TMW = BM / WM, TNW = BN / WN;
@@ -58,33 +61,34 @@ struct FastCfg {
     static constexpr int B_CPR = BN / 8;                // 16-byte chunks per B row
     static_assert(A_PLANE % (512 * NW) == 0 && B_PLANE % (512 * NW) == 0, "tile must split into 1 KB loads");
     static_assert(BN == 128 || BN == 256, "B rows of 256 or 512 bytes");
+    static_assert(BK == 32 || BK == 64, "BK of 32 or 64");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
 
 // Staging registers of the VGPR path (unused when loads go straight to LDS).
-template <int KIND, int BM, int BN, int WM, int WN, bool DMA>
+template <int KIND, int BM, int BN, int WM, int WN, bool DMA, int BK>
 struct FastRegs {
-    using G = FastCfg<KIND, BM, BN, WM, WN, DMA>;
+    using G = FastCfg<KIND, BM, BN, WM, WN, DMA, BK>;
     u32x4 a[DMA ? 1 : G::NPA][DMA ? 1 : G::A_INSTR];
     u32x4 b[DMA ? 1 : G::NPB][DMA ? 1 : G::B_INSTR];
 };
 
 // Issue the loads of one K step (all planes) for LDS stage `dst`: straight
 // into LDS (DMA) or into `regs`, written by fast_store after the MFMAs.
-template <int KIND, int BM, int BN, int WM, int WN, bool DMA>
+template <int KIND, int BM, int BN, int WM, int WN, bool DMA, int BK>
 __device__ __forceinline__ void fast_load(const uint16_t* const (&Ap)[2], const uint16_t* const (&Bp)[2],
                                           int64_t lda, int64_t ldb, int64_t M, int64_t N, int64_t m0,
                                           int64_t n0, int64_t k0, uint16_t* dst, int wid, int lane,
-                                          FastRegs<KIND, BM, BN, WM, WN, DMA>& regs) {
-    using G = FastCfg<KIND, BM, BN, WM, WN, DMA>;
+                                          FastRegs<KIND, BM, BN, WM, WN, DMA, BK>& regs) {
+    using G = FastCfg<KIND, BM, BN, WM, WN, DMA, BK>;
 #pragma unroll
     for (int q = 0; q < G::NPA; ++q) {
         uint16_t* As = dst + q * G::A_PLANE;
 #pragma unroll
         for (int i = 0; i < G::A_INSTR; ++i) {
-            const int blk = wid * G::A_INSTR + i;       // 1 KB block = 8 rows of 64 halfs
-            const int row = blk * 8 + (lane >> 3);
-            const int c = (lane & 7) ^ swz<8>(row);     // logical chunk stored at physical lane & 7
+            const int blk = wid * G::A_INSTR + i;       // 1 KB block = 512/BK rows of BK halfs
+            const int row = blk * G::A_ROWS_PER_INSTR + lane / G::CPR;
+            const int c = (lane % G::CPR) ^ swz<G::CPR>(row);  // logical chunk stored at physical lane % CPR
             int64_t gm = m0 + row;
             gm = gm < M ? gm : M - 1;
             const uint16_t* src = Ap[q] + gm * lda + k0 + c * 8;
@@ -118,10 +122,10 @@ __device__ __forceinline__ void fast_load(const uint16_t* const (&Ap)[2], const 
 }
 
 // VGPR path: write the staged K step into LDS stage `dst` (same layout as DMA).
-template <int KIND, int BM, int BN, int WM, int WN, bool DMA>
+template <int KIND, int BM, int BN, int WM, int WN, bool DMA, int BK>
 __device__ __forceinline__ void fast_store(uint16_t* dst, int wid, int lane,
-                                           const FastRegs<KIND, BM, BN, WM, WN, DMA>& regs) {
-    using G = FastCfg<KIND, BM, BN, WM, WN, DMA>;
+                                           const FastRegs<KIND, BM, BN, WM, WN, DMA, BK>& regs) {
+    using G = FastCfg<KIND, BM, BN, WM, WN, DMA, BK>;
     if constexpr (!DMA) {
 #pragma unroll
         for (int q = 0; q < G::NPA; ++q)
@@ -142,31 +146,33 @@ __device__ __forceinline__ void wait_vm0() {
     __builtin_amdgcn_s_waitcnt(0x0F70);
 }
 
-// B operand of one 32x32x16 MFMA from a row-major B tile: rows kb..kb+7 of
-// columns nb..nb+31 (lane l: column l % 32, rows kb + 8 (l/32) + 0..7).
+// B operand of one 32x32x16 MFMA from a row-major B tile that starts
+// `boff` halfs into the LDS array `st`: rows kb..kb+15 of columns nb..nb+31
+// (lane l: column l % 32, rows kb + 8 (l/32) + 0..7).  Both reads are formed
+// as one offset from the array base so the compiler can tell which array
+// (pipeline stage) they touch.
 template <int BN>
-__device__ __forceinline__ u32x4 read_b_tr(const uint16_t* Bs, int kb, int nb, int lane) {
+__device__ __forceinline__ u32x4 read_b_tr(const uint16_t* st, int boff, int kb, int nb, int lane) {
     const int w = lane & 15, j = w >> 2, q = w & 3;
     const int h = (lane >> 4) & 1, g = lane >> 5;
     const int n = nb + h * 16 + q * 4;
     const int c = n >> 3, off = n & 7;
     const int k1 = kb + g * 8 + j;  // k1 and k1 + 4 share k % 4
-    const int phys = ((c ^ swzB(k1)) << 3) + off;
-    const uint16_t* p1 = Bs + k1 * BN + phys;
-    const uint16_t* p2 = p1 + 4 * BN;
-    i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) i16x4*)p1);
-    i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) i16x4*)p2);
+    const int o1 = boff + k1 * BN + ((c ^ swzB(k1)) << 3) + off;
+    const int o2 = o1 + 4 * BN;
+    i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) i16x4*)(st + o1));
+    i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) i16x4*)(st + o2));
     u32x2 a = __builtin_bit_cast(u32x2, lo), b = __builtin_bit_cast(u32x2, hi);
     return u32x4{a[0], a[1], b[0], b[1]};
 }
 
-template <int KIND, int BM, int BN, int WM, int WN, bool DMA>
+template <int KIND, int BM, int BN, int WM, int WN, bool DMA, int BK_>
 __device__ __forceinline__ void fast_tile(const uint16_t* const (&Ap)[2], const uint16_t* const (&Bp)[2], float* C,
                                           int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, int64_t ldc,
                                           float alpha, float beta, int64_t m0, int64_t n0, uint16_t* lds) {
     using T = KT<KIND>;
-    using G = FastCfg<KIND, BM, BN, WM, WN, DMA>;
-    constexpr int FM = G::FM, FN = G::FN, BK = G::BK;
+    using G = FastCfg<KIND, BM, BN, WM, WN, DMA, BK_>;
+    constexpr int FM = G::FM, FN = G::FN, BK = G::BK, CPR = G::CPR;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
 
@@ -181,9 +187,9 @@ __device__ __forceinline__ void fast_tile(const uint16_t* const (&Ap)[2], const 
         }
 
     const int64_t KTN = K / BK;
-    FastRegs<KIND, BM, BN, WM, WN, DMA> regs;
-    fast_load<KIND, BM, BN, WM, WN, DMA>(Ap, Bp, lda, ldb, M, N, m0, n0, 0, lds, wid, lane, regs);
-    fast_store<KIND, BM, BN, WM, WN, DMA>(lds, wid, lane, regs);
+    FastRegs<KIND, BM, BN, WM, WN, DMA, BK> regs;
+    fast_load<KIND, BM, BN, WM, WN, DMA, BK>(Ap, Bp, lda, ldb, M, N, m0, n0, 0, lds, wid, lane, regs);
+    fast_store<KIND, BM, BN, WM, WN, DMA, BK>(lds, wid, lane, regs);
     if constexpr (DMA) wait_vm0();
     __syncthreads();
     for (int64_t kt = 0; kt < KTN; ++kt) {
@@ -199,14 +205,14 @@ __device__ __forceinline__ void fast_tile(const uint16_t* const (&Ap)[2], const 
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
                     af[kk][fm][q] = (q < T::NPA) ? *reinterpret_cast<const u32x4*>(cur + q * G::A_PLANE + row * BK +
-                                                                                   ((c ^ swz<8>(row)) * 8))
+                                                                                   ((c ^ swz<CPR>(row)) * 8))
                                                  : zero4();
             }
 #pragma unroll
             for (int fn = 0; fn < FN; ++fn) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
-                    bf[kk][fn][q] = (q < T::NPB) ? read_b_tr<BN>(cur + T::NPA * G::A_PLANE + q * G::B_PLANE, kk * 16,
+                    bf[kk][fn][q] = (q < T::NPB) ? read_b_tr<BN>(cur, T::NPA * G::A_PLANE + q * G::B_PLANE, kk * 16,
                                                                  wn * G::TNW + fn * 32, lane)
                                                  : zero4();
             }
@@ -214,7 +220,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t* const (&Ap)[2], const 
         // 2. the next K step's loads into the other stage (after the reads in
         //    program order, so no wait on them is needed before those reads)
         if (kt + 1 < KTN)
-            fast_load<KIND, BM, BN, WM, WN, DMA>(Ap, Bp, lda, ldb, M, N, m0, n0, (kt + 1) * BK,
+            fast_load<KIND, BM, BN, WM, WN, DMA, BK>(Ap, Bp, lda, ldb, M, N, m0, n0, (kt + 1) * BK,
                                                  lds + ((kt + 1) & 1) * G::STAGE, wid, lane, regs);
         // 3. the MFMAs, while those loads are in flight
 #pragma unroll
@@ -229,7 +235,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t* const (&Ap)[2], const 
         if constexpr (DMA) {
             wait_vm0();
         } else {
-            if (kt + 1 < KTN) fast_store<KIND, BM, BN, WM, WN, DMA>(lds + ((kt + 1) & 1) * G::STAGE, wid, lane, regs);
+            if (kt + 1 < KTN) fast_store<KIND, BM, BN, WM, WN, DMA, BK>(lds + ((kt + 1) & 1) * G::STAGE, wid, lane, regs);
         }
         __syncthreads();
     }
@@ -253,8 +259,8 @@ __device__ __forceinline__ void fast_tile(const uint16_t* const (&Ap)[2], const 
         }
 }
 
-template <int KIND, int BM, int BN, int WM, int WN, bool DMA>
-__global__ __launch_bounds__(64 * WM * WN) void gemm16_fast(Gemm16Args p, int tiles_m, int tiles_n, int group_m) {
+template <int KIND, int BM, int BN, int WM, int WN, bool DMA, int BK, int OCC = 1>
+__global__ __launch_bounds__(64 * WM * WN, OCC) void gemm16_fast(Gemm16Args p, int tiles_m, int tiles_n, int group_m) {
     using T = KT<KIND>;
     extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
     int tm, tn;
@@ -267,7 +273,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm16_fast(Gemm16Args p, int ti
         Ap[q] = (q < T::NPA) ? p.A[q] + bz * p.sA : nullptr;
         Bp[q] = (q < T::NPB) ? p.B[q] + bz * p.sB : nullptr;
     }
-    fast_tile<KIND, BM, BN, WM, WN, DMA>(Ap, Bp, p.C + bz * p.sC, p.M, p.N, p.K, p.lda, p.ldb, p.ldc, p.alpha,
+    fast_tile<KIND, BM, BN, WM, WN, DMA, BK>(Ap, Bp, p.C + bz * p.sC, p.M, p.N, p.K, p.lda, p.ldb, p.ldc, p.alpha,
                                          p.beta, (int64_t)tm * BM, (int64_t)tn * BN, lds);
 }
 

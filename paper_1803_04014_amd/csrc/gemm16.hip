@@ -16,6 +16,7 @@
 // order fixed above) and applies the same epilogue, so all tile
 // configurations of a kind give bitwise-identical results.
 #include "fast16.h"
+#include "pipe16.h"
 #include "tile16.h"
 
 namespace mfg {
@@ -27,14 +28,16 @@ struct Cfg16 {
     const char* name;
     int bm, bn;  // 0, 0 = simple kernel
     int group_m;
-    int fast;    // 0: tile16 kernel; 1: fast kernel, loads via VGPRs; 2: fast kernel, loads straight to LDS
+    int fast;    // 0: tile16 kernel; 1: fast kernel, loads via VGPRs; 2: fast kernel, loads straight to LDS;
+                 // 3: pipelined kernel, 4 stages; 5: fast kernel with BK = 32, loads straight to LDS;
+                 // 6: as 5 with a register budget for 2 (or 4) wavefronts per SIMD
     int wm, wn;  // wavefront grid of the fast kernel
 };
 
-template <int KIND, int BM, int BN, int WM, int WN, bool DMA>
+template <int KIND, int BM, int BN, int WM, int WN, bool DMA, int BK = 64, int OCC = 1>
 static int launch_fast(const Gemm16Args& a, int64_t batch, int group_m, hipStream_t s) {
-    using G = FastCfg<KIND, BM, BN, WM, WN, DMA>;
-    auto kern = gemm16_fast<KIND, BM, BN, WM, WN, DMA>;
+    using G = FastCfg<KIND, BM, BN, WM, WN, DMA, BK>;
+    auto kern = gemm16_fast<KIND, BM, BN, WM, WN, DMA, BK, OCC>;
     static bool attr_set = false;
     if (!attr_set) {
         MFG_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -44,6 +47,16 @@ static int launch_fast(const Gemm16Args& a, int64_t batch, int group_m, hipStrea
     const int tiles_m = (int)cdiv(a.M, BM), tiles_n = (int)cdiv(a.N, BN);
     dim3 grid(tiles_m * tiles_n, (unsigned)batch, 1);
     hipLaunchKernelGGL(kern, grid, dim3(G::NT), G::LDS_BYTES, s, a, tiles_m, tiles_n, group_m);
+    MFG_LAUNCH_CHECK();
+    return MFG_OK;
+}
+
+template <int KIND, int BM, int BN, int WM, int WN, int S>
+static int launch_pipe(const Gemm16Args& a, int64_t batch, int group_m, hipStream_t s) {
+    using G = PipeCfg<KIND, BM, BN, WM, WN, S>;
+    const int tiles_m = (int)cdiv(a.M, BM), tiles_n = (int)cdiv(a.N, BN);
+    dim3 grid(tiles_m * tiles_n, (unsigned)batch, 1);
+    hipLaunchKernelGGL((gemm16_pipe<KIND, BM, BN, WM, WN, S>), grid, dim3(G::NT), 0, s, a, tiles_m, tiles_n, group_m);
     MFG_LAUNCH_CHECK();
     return MFG_OK;
 }
@@ -92,6 +105,18 @@ static const Cfg16 kCfgPlain[] = {
     {"f256x256k64w2x4g8dma", 256, 256, 8, 2, 2, 4},
     {"f256x128k64w2x2g8dma", 256, 128, 8, 2, 2, 2},
     {"f128x128k64w2x2g8dma", 128, 128, 8, 2, 2, 2},
+    {"f128x128k32w2x2g8dma", 128, 128, 8, 5, 2, 2},
+    {"f256x128k32w2x2g8dma", 256, 128, 8, 5, 2, 2},
+    {"f128x256k32w2x2g8dma", 128, 256, 8, 5, 2, 2},
+    {"f256x128k32w2x2g8o2", 256, 128, 8, 6, 2, 2},
+    {"f128x256k32w2x2g8o2", 128, 256, 8, 6, 2, 2},
+    {"f128x128k32w2x2g8o4", 128, 128, 8, 6, 2, 2},
+    {"f256x256k32w2x4g8dma", 256, 256, 8, 5, 2, 4},
+    {"f256x256k32w2x2g8dma", 256, 256, 8, 5, 2, 2},
+    {"p256x256k32s4w2x2g8", 256, 256, 8, 3, 2, 2},
+    {"p256x128k32s4w2x2g8", 256, 128, 8, 3, 2, 2},
+    {"p256x256k32s4w2x2g4", 256, 256, 4, 3, 2, 2},
+    {"p256x256k32s4w2x2g16", 256, 256, 16, 3, 2, 2},
 };
 static const Cfg16 kCfgSplit[] = {
     {"simple32", 0, 0, 0},
@@ -159,6 +184,35 @@ static int launch_kind(int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok,
     if (cfg != 0 && !vec_ok) return MFG_ERR_UNSUPPORTED;
     const Cfg16& c = m[cfg];
     if (c.bm == 0) return launch_simple<KIND>(a, batch, vec_ok, s);
+    if (c.fast == 6) {  // BK = 32 with a higher occupancy target
+        if (!fast_ok(a, vec_ok)) return MFG_ERR_UNSUPPORTED;
+        if constexpr (KIND == K_F16 || KIND == K_BF16) {
+            if (c.bm == 256 && c.bn == 128) return launch_fast<KIND, 256, 128, 2, 2, true, 32, 2>(a, batch, c.group_m, s);
+            if (c.bm == 128 && c.bn == 256) return launch_fast<KIND, 128, 256, 2, 2, true, 32, 2>(a, batch, c.group_m, s);
+            if (c.bm == 128 && c.bn == 128) return launch_fast<KIND, 128, 128, 2, 2, true, 32, 4>(a, batch, c.group_m, s);
+        }
+        return MFG_ERR_INTERNAL;
+    }
+    if (c.fast == 5) {
+        if (!fast_ok(a, vec_ok)) return MFG_ERR_UNSUPPORTED;
+        if constexpr (KIND == K_F16 || KIND == K_BF16) {
+            if (c.bm == 128 && c.bn == 128) return launch_fast<KIND, 128, 128, 2, 2, true, 32>(a, batch, c.group_m, s);
+            if (c.bm == 256 && c.bn == 128) return launch_fast<KIND, 256, 128, 2, 2, true, 32>(a, batch, c.group_m, s);
+            if (c.bm == 128 && c.bn == 256) return launch_fast<KIND, 128, 256, 2, 2, true, 32>(a, batch, c.group_m, s);
+            if (c.bm == 256 && c.bn == 256 && c.wn == 4)
+                return launch_fast<KIND, 256, 256, 2, 4, true, 32>(a, batch, c.group_m, s);
+            if (c.bm == 256 && c.bn == 256) return launch_fast<KIND, 256, 256, 2, 2, true, 32>(a, batch, c.group_m, s);
+        }
+        return MFG_ERR_INTERNAL;
+    }
+    if (c.fast == 3) {
+        if (!fast_ok(a, vec_ok)) return MFG_ERR_UNSUPPORTED;  // K % 64 == 0 implies K % 32 == 0
+        if constexpr (KIND == K_F16 || KIND == K_BF16) {
+            if (c.bm == 256 && c.bn == 256) return launch_pipe<KIND, 256, 256, 2, 2, 4>(a, batch, c.group_m, s);
+            if (c.bm == 256 && c.bn == 128) return launch_pipe<KIND, 256, 128, 2, 2, 4>(a, batch, c.group_m, s);
+        }
+        return MFG_ERR_INTERNAL;
+    }
     if (c.fast) {
         if (!fast_ok(a, vec_ok)) return MFG_ERR_UNSUPPORTED;
         if constexpr (KIND == K_F16 || KIND == K_BF16) {

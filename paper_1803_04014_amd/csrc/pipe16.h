@@ -1,0 +1,269 @@
+// pipe16.h -- multi-stage pipelined GEMM kernel for 16-bit operand planes.
+//
+// Same arithmetic and LDS layout as fast16.h (bitwise-identical results),
+// with a deeper pipeline for the one-wavefront-per-SIMD regime of large
+// tiles:
+//   - S LDS stages of BK = 32, each its own __shared__ array.  Distinct
+//     arrays let the compiler see that a read of stage s does not alias the
+//     global->LDS loads still in flight into the other stages, so its own
+//     wait insertion stays precise; loads run S-1 steps ahead.
+//   - Operand fragments are double-buffered in VGPRs: while the MFMAs of
+//     step t run, the fragments of step t+1 are read from LDS, interleaved
+//     one read per MFMA (sched_group_barrier), so LDS latency hides under
+//     the matrix cores.
+//   - One barrier per step, a bare s_barrier (__syncthreads() would also
+//     wait for the loads that must stay in flight).  At the top of step t:
+//     wait for this wave's loads of step t+1 and its LDS reads, barrier
+//     (everyone's loads landed; everyone's reads of step t's array, done
+//     during step t-1, completed), then refill that array with step t+S.  Past the last step the refill fetches the last
+//     step again (valid addresses, never read), so wait counts are fixed.
+#pragma once
+
+#include <type_traits>
+
+#include "fast16.h"
+
+namespace mfg {
+
+template <int KIND, int BM, int BN, int WM, int WN, int S>
+struct PipeCfg {
+    static constexpr int BK = 32;
+    static constexpr int NT = 64 * WM * WN, NW = WM * WN;
+    static constexpr int TMW = BM / WM, TNW = BN / WN;
+    static constexpr int FM = TMW / 32, FN = TNW / 32;
+    static constexpr int NPA = KT<KIND>::NPA, NPB = KT<KIND>::NPB;
+    static constexpr int A_PLANE = BM * BK, B_PLANE = BK * BN;  // halfs
+    static constexpr int STAGE = NPA * A_PLANE + NPB * B_PLANE;
+    static constexpr int LDS_BYTES = S * STAGE * 2;
+    static constexpr int A_INSTR = A_PLANE / 512 / NW;  // 1 KB loads per wave per plane
+    static constexpr int B_INSTR = B_PLANE / 512 / NW;
+    static constexpr int LOADS = NPA * A_INSTR + NPB * B_INSTR;  // per wave per stage
+    static constexpr int B_ROWS_PER_INSTR = 512 / BN, B_CPR = BN / 8;
+    static constexpr int READS = 2 * (FM * NPA + 2 * FN * NPB);  // LDS reads per wave per step
+    static constexpr int PRODUCTS = KIND == K_REFINE_A ? 2 : KIND == K_SPLIT3 ? 3 : KIND == K_SPLIT4 ? 4 : 1;
+    static constexpr int MFMAS = 2 * FM * FN * PRODUCTS;  // per wave per step
+    static_assert(A_PLANE % (512 * NW) == 0 && B_PLANE % (512 * NW) == 0, "tile must split into 1 KB loads");
+    static_assert(BN == 128 || BN == 256, "B rows of 256 or 512 bytes");
+    static_assert(S == 4, "4 stages: the fragment double buffer alternates with the step parity only for an even unroll");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+    static_assert(LOADS * (S - 1) <= 63, "vmcnt range");
+};
+
+// Global -> LDS loads of one BK = 32 step into stage array `st`.  The A tile
+// row has 4 chunks of 16 bytes (64 B); a 1 KB load fills 16 rows.  Chunk c of
+// row r sits at c ^ ((r >> 1 ^ r >> 3) & 3): conflict-free A operand reads.
+template <int KIND, int BM, int BN, int WM, int WN, int S>
+__device__ __forceinline__ void pipe_load(const uint16_t* const (&Ap)[2], const uint16_t* const (&Bp)[2],
+                                          int64_t lda, int64_t ldb, int64_t M, int64_t N, int64_t m0, int64_t n0,
+                                          int64_t k0, uint16_t* st, int wid, int lane) {
+    using G = PipeCfg<KIND, BM, BN, WM, WN, S>;
+#pragma unroll
+    for (int q = 0; q < G::NPA; ++q) {
+#pragma unroll
+        for (int i = 0; i < G::A_INSTR; ++i) {
+            const int blk = wid * G::A_INSTR + i;  // 16 rows of 32 halfs
+            const int row = blk * 16 + (lane >> 2);
+            const int c = (lane & 3) ^ swz<4>(row);
+            int64_t gm = m0 + row;
+            gm = gm < M ? gm : M - 1;
+            const int loff = q * G::A_PLANE + blk * 512;
+            __builtin_amdgcn_global_load_lds((const void*)(Ap[q] + gm * lda + k0 + c * 8), (lds_void*)(st + loff), 16,
+                                             0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < G::NPB; ++q) {
+#pragma unroll
+        for (int i = 0; i < G::B_INSTR; ++i) {
+            const int blk = wid * G::B_INSTR + i;
+            const int krow = blk * G::B_ROWS_PER_INSTR + lane / G::B_CPR;
+            const int c = (lane % G::B_CPR) ^ swzB(krow);
+            int64_t gn = n0 + c * 8;
+            gn = gn + 8 <= N ? gn : N - 8;
+            const int loff = G::NPA * G::A_PLANE + q * G::B_PLANE + blk * 512;
+            __builtin_amdgcn_global_load_lds((const void*)(Bp[q] + (k0 + krow) * ldb + gn), (lds_void*)(st + loff), 16,
+                                             0, 0);
+        }
+    }
+}
+
+template <int KIND, int BM, int BN, int WM, int WN, int S>
+struct PipeFrags {
+    using G = PipeCfg<KIND, BM, BN, WM, WN, S>;
+    u32x4 a[2][G::FM][2];
+    u32x4 b[2][G::FN][2];
+};
+
+template <int KIND, int BM, int BN, int WM, int WN, int S>
+__device__ __forceinline__ void pipe_read(const uint16_t* st, int wm, int wn, int lane,
+                                          PipeFrags<KIND, BM, BN, WM, WN, S>& f) {
+    using G = PipeCfg<KIND, BM, BN, WM, WN, S>;
+    using T = KT<KIND>;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+        const int c = kk * 2 + (lane >> 5);
+#pragma unroll
+        for (int fm = 0; fm < G::FM; ++fm) {
+            const int row = wm * G::TMW + fm * 32 + (lane & 31);
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                f.a[kk][fm][q] = (q < T::NPA) ? *reinterpret_cast<const u32x4*>(
+                                                    st + (q * G::A_PLANE + row * 32 + ((c ^ swz<4>(row)) * 8)))
+                                              : zero4();
+        }
+#pragma unroll
+        for (int fn = 0; fn < G::FN; ++fn) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                f.b[kk][fn][q] = (q < T::NPB) ? read_b_tr<BN>(st, G::NPA * G::A_PLANE + q * G::B_PLANE, kk * 16,
+                                                              wn * G::TNW + fn * 32, lane)
+                                              : zero4();
+        }
+    }
+}
+
+template <int KIND, int BM, int BN, int WM, int WN, int S>
+__device__ __forceinline__ void pipe_mma(const PipeFrags<KIND, BM, BN, WM, WN, S>& f,
+                                         f32x16 (&hi)[PipeCfg<KIND, BM, BN, WM, WN, S>::FM][PipeCfg<KIND, BM, BN, WM, WN, S>::FN],
+                                         f32x16 (&lo)[PipeCfg<KIND, BM, BN, WM, WN, S>::FM][PipeCfg<KIND, BM, BN, WM, WN, S>::FN],
+                                         f32x16 (&rr)[PipeCfg<KIND, BM, BN, WM, WN, S>::FM][PipeCfg<KIND, BM, BN, WM, WN, S>::FN]) {
+    using G = PipeCfg<KIND, BM, BN, WM, WN, S>;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int fm = 0; fm < G::FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < G::FN; ++fn) mma_step<KIND>(f.a[kk][fm], f.b[kk][fn], hi[fm][fn], lo[fm][fn], rr[fm][fn]);
+}
+
+// s_waitcnt vmcnt(n) (gfx9 encoding: vmcnt bits [3:0] and [15:14]; expcnt
+// and lgkmcnt left at their no-wait maxima).
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(n >= 0 && n < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// s_waitcnt lgkmcnt(0): this wave's LDS reads have returned their data.
+__device__ __forceinline__ void wait_lgkm0() {
+    __builtin_amdgcn_s_waitcnt(0xF | (0x3 << 14) | (0x7 << 4));
+}
+
+// Workgroup barrier without __syncthreads()'s release fence: that fence
+// waits for every outstanding memory operation of the wave, including the
+// global->LDS loads of later stages that must stay in flight.  The caller
+// waits for exactly what the other wavefronts need first; the compiler-only
+// fences keep LDS accesses on their side of the barrier.
+__device__ __forceinline__ void bare_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Interleave: one LDS read after each MFMA until the reads run out.
+template <int READS, int MFMAS>
+__device__ __forceinline__ void pipe_interleave() {
+#pragma unroll
+    for (int i = 0; i < (READS < MFMAS ? READS : MFMAS); ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+    }
+}
+
+template <int KIND, int BM, int BN, int WM, int WN, int S>
+__global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe(Gemm16Args p, int tiles_m, int tiles_n, int group_m) {
+    using T = KT<KIND>;
+    using G = PipeCfg<KIND, BM, BN, WM, WN, S>;
+    constexpr int FM = G::FM, FN = G::FN, BK = G::BK;
+    __shared__ __attribute__((aligned(16))) uint16_t st0[G::STAGE];
+    __shared__ __attribute__((aligned(16))) uint16_t st1[G::STAGE];
+    __shared__ __attribute__((aligned(16))) uint16_t st2[G::STAGE];
+    __shared__ __attribute__((aligned(16))) uint16_t st3[G::STAGE];
+
+    int tm, tn;
+    raster(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, group_m, tm, tn);
+    const int64_t bz = blockIdx.y;
+    const uint16_t* Ap[2];
+    const uint16_t* Bp[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        Ap[q] = (q < T::NPA) ? p.A[q] + bz * p.sA : nullptr;
+        Bp[q] = (q < T::NPB) ? p.B[q] + bz * p.sB : nullptr;
+    }
+    float* C = p.C + bz * p.sC;
+    const int64_t M = p.M, N = p.N, K = p.K, lda = p.lda, ldb = p.ldb;
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid / WN, wn = wid % WN;
+    const int64_t KTN = K / BK;  // >= 1
+    auto kclamp = [&](int64_t t) { return (t < KTN ? t : KTN - 1) * BK; };
+    auto stage = [&](int s) -> uint16_t* { return s == 0 ? st0 : s == 1 ? st1 : s == 2 ? st2 : st3; };
+
+
+    f32x16 hi[FM][FN], lo[FM][FN], rr[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            hi[i][j] = f32x16{};
+            if constexpr (T::LO) lo[i][j] = f32x16{};
+            if constexpr (T::RR) rr[i][j] = f32x16{};
+        }
+
+    // prologue: steps 0 .. S-1 in flight; wait for step 0 and read its fragments
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        pipe_load<KIND, BM, BN, WM, WN, S>(Ap, Bp, lda, ldb, M, N, m0, n0, kclamp(s), stage(s), wid, lane);
+    PipeFrags<KIND, BM, BN, WM, WN, S> f[2];
+    wait_vmcnt<G::LOADS * (S - 1)>();
+    bare_barrier();
+    pipe_read<KIND, BM, BN, WM, WN, S>(st0, wm, wn, lane, f[0]);
+
+    // One step: wait + barrier, refill the freed array, read the next
+    // step's fragments (always: past the end they are simply unused),
+    // MFMAs of this step interleaved with those reads.
+    auto step = [&](auto ucst, int64_t t) {
+        constexpr int u = decltype(ucst)::value;
+        wait_vmcnt<G::LOADS * (S - 2)>();  // this wave's loads of step t+1 landed
+        wait_lgkm0();                      // this wave's reads of step t's array returned
+        bare_barrier();
+        pipe_load<KIND, BM, BN, WM, WN, S>(Ap, Bp, lda, ldb, M, N, m0, n0, kclamp(t + S), stage(u), wid, lane);
+        pipe_read<KIND, BM, BN, WM, WN, S>(stage((u + 1) % S), wm, wn, lane, f[(u + 1) & 1]);
+        pipe_mma<KIND, BM, BN, WM, WN, S>(f[u & 1], hi, lo, rr);
+        pipe_interleave<G::READS, G::MFMAS>();
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // main loop over whole groups of S steps (stage arrays named statically, no branches)
+    const int64_t KFULL = KTN - KTN % S;
+    for (int64_t t0 = 0; t0 < KFULL; t0 += S) {
+        step(std::integral_constant<int, 0>{}, t0);
+        step(std::integral_constant<int, 1>{}, t0 + 1);
+        step(std::integral_constant<int, 2>{}, t0 + 2);
+        step(std::integral_constant<int, 3>{}, t0 + 3);
+    }
+    // remaining KTN % S steps
+    if (KFULL < KTN) step(std::integral_constant<int, 0>{}, KFULL);
+    if (KFULL + 1 < KTN) step(std::integral_constant<int, 1>{}, KFULL + 1);
+    if (KFULL + 2 < KTN) step(std::integral_constant<int, 2>{}, KFULL + 2);
+
+    wait_vmcnt<0>();  // no global->LDS load may outlive the workgroup's LDS
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+            const int64_t col = n0 + wn * G::TNW + fn * 32 + (lane & 31);
+            const int64_t rbase = m0 + wm * G::TMW + fm * 32;
+            if (col < N) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int64_t row = rbase + mfma_out_row(i, lane);
+                    float l = 0.0f, x = 0.0f;
+                    if constexpr (T::LO) l = lo[fm][fn][i];
+                    if constexpr (T::RR) x = rr[fm][fn][i];
+                    if (row < M) store_out(C, row * p.ldc + col, combine<KIND>(hi[fm][fn][i], l, x), p.alpha, p.beta);
+                }
+            }
+        }
+}
+
+}  // namespace mfg
