@@ -35,7 +35,8 @@ METRIC = "TFLOP/s and % MFMA peak at max-rel-err vs FP64; batched GEMM/s; p50/p9
 PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
 HBM_GBS = 8000.0
 PAPER_V100_TFLOPS = 83.0   # best mixed-precision GEMM on V100, N=8192 (context)
-KERNEL_SOURCES = ["paper_1803_04014_amd/csrc/tile16.h", "paper_1803_04014_amd/csrc/gemm16.hip",
+KERNEL_SOURCES = ["paper_1803_04014_amd/csrc/tile16.h", "paper_1803_04014_amd/csrc/fast16.h",
+                  "paper_1803_04014_amd/csrc/pipe16.h", "paper_1803_04014_amd/csrc/gemm16.hip",
                   "paper_1803_04014_amd/csrc/device.h"]
 PMC_FILE = os.path.join(ROOT, "profiles", "gemm_f16_n8192_pmc.json")
 
@@ -68,6 +69,63 @@ def timed(fn, reps, warm=2):
     return s.elapsed_time(e) / reps
 
 
+def _csv_rows(d: str, suffix: str):
+    import csv
+    import glob
+
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            yield from csv.DictReader(fh)
+
+
+def _per_dispatch(d: str, counter: str, name_part: str) -> float:
+    """Mean of `counter` over the dispatches whose kernel name contains name_part."""
+    vals = [float(r["Counter_Value"]) for r in _csv_rows(d, "counter_collection.csv")
+            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for kernels matching {name_part!r} under {d}")
+    return sum(vals) / len(vals)
+
+
+def pmc_summarize(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, n) -> int:
+    """HBM bytes per launch of the headline GEMM kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for a plain copy of copy_bytes (torch's elementwise copy)."""
+    kern = "gemm16_fast"
+    copy = "copy"
+    f_k = _per_dispatch(fetch_dir, "FETCH_SIZE", kern)
+    w_k = _per_dispatch(write_dir, "WRITE_SIZE", kern)
+    f_c = _per_dispatch(copy_fetch_dir, "FETCH_SIZE", copy)
+    w_c = _per_dispatch(copy_write_dir, "WRITE_SIZE", copy)
+    f_scale, w_scale = copy_bytes / (f_c * 1024.0), copy_bytes / (w_c * 1024.0)
+    fetch, write = f_k * 1024.0 * f_scale, w_k * 1024.0 * w_scale
+    algo = 2 * n * n * 2 + 2 * n * n * 4   # A, B in FP16 once; C read and written in FP32
+    out = {"kernel_hash": kernel_hash(), "n": n, "kernel_match": kern,
+           "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
+           "copy_bytes": copy_bytes, "copy_fetch_kib": f_c, "copy_write_kib": w_c,
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "hbm_bytes_per_launch": fetch + write, "algorithmic_bytes_per_launch": algo,
+           "traffic_over_algorithmic": (fetch + write) / algo}
+    with open(PMC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+    return 0
+
+
+def copy_probe(nbytes: int) -> int:
+    """A plain device copy of nbytes, three times: the calibration kernel for
+    the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {nbytes} bytes x 3", flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,7 +135,15 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle time for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, metavar="BYTES", help="only run the counter-calibration copy")
+    ap.add_argument("--pmc-summarize", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="only turn four rocprofv3 --pmc output folders into the traffic record")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     args = ap.parse_args()
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
+    if args.pmc_summarize:
+        return pmc_summarize(*args.pmc_summarize, args.copy_bytes, args.n)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build is single-GPU)",
               file=sys.stderr)
@@ -166,11 +232,17 @@ def main() -> int:
     if not args.no_cpu:
         import oracle  # the FP64 CPU oracle: only this leg of the benchmark uses it
 
-        rows_probe = np.arange(0, N, max(1, N // 8))[:8]
-        t = time.perf_counter()
-        oracle.exact(A32, B32, 1.0, 1.0, C0, rows=rows_probe)
-        per_row = (time.perf_counter() - t) / len(rows_probe)
-        nrows = int(max(8, min(N, args.cpu_seconds / max(per_row, 1e-6))))
+        # per-row cost from two probes (the difference removes the fixed cost
+        # of widening the operands to FP64)
+        probe_t = []
+        for n_probe in (32, 160):
+            rows_probe = np.arange(n_probe, dtype=np.int64) * max(1, N // n_probe)
+            t = time.perf_counter()
+            oracle.exact(A32, B32, 1.0, 1.0, C0, rows=rows_probe)
+            probe_t.append(time.perf_counter() - t)
+        per_row = max((probe_t[1] - probe_t[0]) / 128, 1e-6)
+        fixed = max(probe_t[0] - 32 * per_row, 0.0)
+        nrows = int(max(8, min(N, (args.cpu_seconds - fixed) / per_row)))
         rows = np.unique(np.linspace(0, N - 1, nrows).astype(np.int64))
         log(f"bench: cpu oracle on {len(rows)} rows")
         t = time.perf_counter()
