@@ -126,6 +126,74 @@ def copy_probe(nbytes: int) -> int:
     return 0
 
 
+def served_errors(trace, views, per_mode: int = 3, max_flops: float = 2 * 512.0 ** 3):
+    """Part of the CPU oracle leg: max relative error vs FP64 of a few served
+    requests per mode (the oracle computes their exact products)."""
+    import numpy as np
+
+    import oracle
+
+    errs = {}
+    for mode in sorted({r["mode"] for r in trace}):
+        picked = [i for i, r in enumerate(trace) if r["mode"] == mode and 2.0 * r["M"] * r["N"] * r["K"] <= max_flops]
+        worst = 0.0
+        for i in picked[:per_mode]:
+            a, b, c = views[i]
+            A = a.cpu().numpy()
+            B = b.cpu().numpy()
+            ref = oracle.exact(A, B, 1.0, 0.0, None)
+            err = np.max(np.abs(c.cpu().numpy().astype(np.float64) - ref)) / max(np.max(np.abs(ref)), 1e-300)
+            worst = max(worst, float(err))
+        errs[mode] = {"max_rel": worst, "sampled": min(per_mode, len(picked))}
+    return errs
+
+
+def serving_leg(rate: float, seconds: float, seed: int, pools, budget: float = 200e9, slots: int = 4,
+                max_group: int = 16):
+    """Replay a Poisson trace of GEMM requests (M, N, K log-uniform in [32, 4096],
+    modes F16 / BF16 / SPLIT3 / FP8, operands sub-blocks of resident 4096 x 4096
+    FP32 pools, a distinct C per request, alpha = 1, beta = 0) into mfg_server.
+    Latency = completion observed - submit, per request."""
+    import numpy as np
+    import torch
+
+    import paper_1803_04014_amd as mfg
+    import workloads
+
+    dA, dB = pools
+    n = max(1, int(rate * seconds))
+    trace = workloads.serving_trace(seed, rate, n)
+    sizes = [r["M"] * r["N"] for r in trace]
+    arena = torch.empty(int(sum(sizes)), dtype=torch.float32, device=dA.device)
+    views, off = [], 0
+    for r, sz in zip(trace, sizes):
+        (ar, ac), (br, bc) = r["a_off"], r["b_off"]
+        views.append((dA[ar:ar + r["M"], ac:ac + r["K"]], dB[br:br + r["K"], bc:bc + r["N"]],
+                      arena[off:off + sz].view(r["M"], r["N"])))
+        off += sz
+    torch.cuda.synchronize()
+    server = mfg.Server(int(budget), slots=slots, max_group=max_group)
+    tickets = []
+    t0 = time.perf_counter()
+    for r, (a, b, c) in zip(trace, views):
+        while time.perf_counter() - t0 < r["t"]:
+            pass
+        tickets.append(server.submit(a, b, c, r["mode"], 1.0, 0.0))
+    server.drain()
+    res = [server.poll(t)[1] for t in tickets]
+    stats = server.stats()
+    server.close()
+    lat = np.array([(x["t_end_ns"] - x["t_submit_ns"]) * 1e-6 for x in res])
+    span = (max(x["t_end_ns"] for x in res) - min(x["t_submit_ns"] for x in res)) * 1e-9
+    flops = sum(x["flops"] for x in res)
+    out = {"rate_per_s": rate, "requests": n, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
+           "useful_tflops": round(flops / span / 1e12, 2), "launches": stats["launches"],
+           "mean_group": round(float(np.mean([x["group_size"] for x in res])), 2),
+           "failed": stats["failed"], "peak_converted_gb": round(stats["peak_bytes_in_use"] / 1e9, 3)}
+    return out, trace, views
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +383,19 @@ def main() -> int:
                               "pct_hbm": round(100 * info["bytes"] / ms / 1e6 / HBM_GBS, 1), "us": round(ms * 1e3, 1),
                               "work_items": info["work_items"]}
         plan.close()
+        # serving: Poisson arrivals at two rates
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(7)
+        pools = (torch.randn((4096, 4096), device=dev, generator=gen), torch.randn((4096, 4096), device=dev, generator=gen))
+        serving = {}
+        for rate, secs in ((1000.0, 2.0), (5000.0, 1.0)):
+            log(f"bench: serving at {rate:.0f} requests/s")
+            srv, trace, views = serving_leg(rate, secs, 7, pools)
+            if not args.no_cpu:
+                srv["errors_vs_fp64"] = served_errors(trace, views)
+            serving[f"lambda_{int(rate)}"] = srv
+            del views
+        ex["serving"] = serving
         out["extras"] = ex
     print(json.dumps(out), flush=True)
     return 0

@@ -237,17 +237,35 @@ int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode);
 /* ---------------------------------------------------------------- serving
  * A request loop with continuous batching and HBM admission.  Requests are
  * GEMMs over caller-owned FP32 A/B and FP32 C device buffers; the server
- * owns the converted operands.  A request is admitted when its converted-
- * operand footprint fits in hbm_budget_bytes next to those already admitted
- * and a slot (one HIP stream each) is free; admitted requests of one mode
- * that are waiting together are launched as one grouped launch.
+ * owns the converted operands (paper Sec. V-VI: FP32 data rounded, split
+ * or quantised before the matrix-unit GEMM).  A request is admitted, first
+ * come first served, when its converted-operand footprint fits in
+ * hbm_budget_bytes next to those already admitted (a request that does not
+ * fit waits, and so do the ones behind it).  When a slot (one HIP stream) is
+ * free, the oldest admitted request takes up to max_group admitted requests
+ * of its mode, alpha and beta into one group: operands are converted on the
+ * slot's stream, small FP16/BF16 problems (M*N < 512*512, at most 64 tiles of
+ * 64 x 64) run as one persistent grouped launch, the others one by one; one
+ * completion event per group.  Footprint: the mode's converted A (ld = K
+ * rounded up to 8, or to 16 for FP8) and B (ld = N rounded likewise), each
+ * rounded up to 256 bytes; 0 for MFG_F32 and for empty problems.  The fixed
+ * per-slot descriptor staging is not counted.  Results are bitwise those of
+ * mfg_gemm on the same FP32 operands, whatever a request is grouped with.
+ * Config limits: 1 <= slots <= 64, 1 <= max_group <= 4096, reserved = 0.
+ * Request limits: mode without flags, reserved = 0, mfg_gemm's validation.
+ * Caller's A, B, C must stay valid until mfg_poll returns a final status.
  */
 typedef struct mfg_server mfg_server;
 
 typedef struct mfg_server_config {
     uint64_t hbm_budget_bytes;  /* bytes of converted operands in flight     */
     int32_t slots;              /* concurrent launches (streams), >= 1        */
-    int32_t device;             /* HIP device ordinal                         */
+    int32_t device;             /* HIP device ordinal; -1 = dry run: requests
+                                   are validated, admitted, grouped and
+                                   accounted, but no HIP call is made, nothing
+                                   is computed and A, B, C are never touched
+                                   (a group "runs" for flops / 1e14 s); for
+                                   testing the scheduler without a GPU        */
     int32_t max_group;          /* requests per grouped launch, >= 1          */
     int32_t reserved;
 } mfg_server_config;

@@ -1,0 +1,132 @@
+"""The C-ABI boundary on the CPU: the built libmfgemm exports every function
+include/mfgemm.h declares, the Python binding declares the same names, the
+numeric constants and struct layouts agree with the header, and the host-only
+entry points (validation, sizes, names, tuned table) behave as documented.
+No call here touches a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1803_04014_amd as mfg
+from paper_1803_04014_amd import capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mfgemm.h")
+
+
+def header_text():
+    with open(HEADER) as f:
+        return f.read()
+
+
+def declared_functions():
+    src = re.sub(r"/\*.*?\*/", "", header_text(), flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(mfg_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_documented_calls():
+    names = declared_functions()
+    for must in ("mfg_gemm", "mfg_gemm_batched", "mfg_submit", "mfg_poll", "mfg_error_norms", "mfg_split_f16",
+                 "mfg_quantize_fp8", "mfg_grouped_graph_launch", "mfg_autotune", "mfg_server_create"):
+        assert must in names
+    assert len(names) >= 30
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mfg.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+    out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r"\sT\s+(mfg_[a-z_0-9]+)$", out.stdout, flags=re.M))
+    assert set(declared_functions()) <= exported
+    # nothing else of the C ABI leaks out under the mfg_ prefix
+    assert exported - set(declared_functions()) == set()
+
+
+def test_binding_declares_exactly_the_header():
+    assert set(capi.SIGNATURES) == set(declared_functions())
+
+
+def test_constants_match_header():
+    src = header_text()
+    values = {k: int(v, 0) for k, v in re.findall(r"#define\s+(MFG_[A-Z0-9_]+)\s+(0x[0-9A-Fa-f]+|-?\d+)", src)}
+    values.update({k: int(v) for k, v in re.findall(r"\b(MFG_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)})
+    assert len(values) >= 20
+    for k, v in values.items():
+        assert getattr(capi, k) == v, k
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(capi.mfg_problem) == 6 * 8 + 3 * 8
+    assert ctypes.sizeof(capi.mfg_server_config) == 8 + 4 * 4
+    assert ctypes.sizeof(capi.mfg_request) == 6 * 8 + 3 * 8 + 4 * 4
+    assert ctypes.sizeof(capi.mfg_result) == 4 + 4 + 5 * 8 + 8
+    assert ctypes.sizeof(capi.mfg_server_stats) == 7 * 8
+
+
+def test_version_and_status_strings():
+    assert mfg.lib().mfg_version().decode().startswith("libmfgemm")
+    for st in range(-7, 2):
+        assert mfg.lib().mfg_status_string(st)
+    assert b"unknown" in mfg.lib().mfg_status_string(-99).lower()
+
+
+P = 0x7F0000000000  # a non-null address: validation never dereferences
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((8, 8, 8, P, 8, P, 8, P, 8, 1), 0),
+    ((0, 8, 8, None, 8, P, 8, None, 8, 1), 0),              # M = 0: A and C have no extent
+    ((8, 8, 0, None, 1, None, 8, P, 8, 1), 0),              # K = 0: A, B unused
+    ((-1, 8, 8, P, 8, P, 8, P, 8, 1), -1),
+    ((8, 8, 8, P, 7, P, 8, P, 8, 1), -1),                   # lda < K
+    ((8, 8, 8, P, 8, P, 7, P, 8, 1), -1),                   # ldb < N
+    ((8, 8, 8, P, 8, P, 8, P, 7, 1), -1),                   # ldc < N
+    ((8, 8, 8, None, 8, P, 8, P, 8, 1), -1),
+    ((8, 8, 8, P, 8, P, 8, None, 8, 1), -1),
+    ((8, 8, 8, P, 8, P, 8, P, 8, 7), -1),                   # no such mode
+    ((8, 8, 8, P, 8, P, 8, P, 8, 0x201), -1),               # unknown flag
+    ((8, 8, 8, P, 8, P, 8, P, 8, 0x101), 0),
+])
+def test_validation_rules(args, expect):
+    assert mfg.lib().mfg_validate_gemm(*args) == expect
+
+
+def test_convert_bytes_and_fp8_scale_offset():
+    L = mfg.lib()
+    assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_F16) == 10 * 8 * 2
+    assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_F16_SPLIT3) == 2 * 10 * 8 * 2
+    assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_F32) == 10 * 8 * 4
+    off = L.mfg_fp8_scale_offset(300, 272)
+    assert off >= 300 * 272 and off % 16 == 0
+    assert L.mfg_convert_bytes(300, 260, 272, capi.MFG_FP8_E4M3) == off + 4 * 3 * 3
+
+
+def test_config_menus_and_names():
+    for mode in mfg.capi.MODE_BY_NAME:
+        n = mfg.num_configs(mode)
+        assert n >= 1
+        names = [mfg.config_name(mode, i) for i in range(n)]
+        assert len(set(names)) == n and all(names)
+        assert mfg.lib().mfg_config_name(capi.MODE_BY_NAME[mode], n, ctypes.create_string_buffer(64), 64) != 0
+
+
+def test_tuned_table_round_trip(tmp_path):
+    L = mfg.lib()
+    L.mfg_tune_clear()
+    base = L.mfg_tune_lookup(4096, 4096, 4096, capi.MFG_F16)
+    assert 0 <= base < mfg.num_configs("f16")
+    path = tmp_path / "tuned.txt"
+    path.write_text(f"{capi.MFG_F16} 12 12 12 3\n")
+    assert L.mfg_tune_load(str(path).encode()) == 0
+    got = [L.mfg_tune_lookup(n, n, n, capi.MFG_F16) for n in (4096, 8192)]
+    assert 3 in got
+    out = tmp_path / "saved.txt"
+    assert L.mfg_tune_save(str(out).encode()) == 0
+    rows = [ln.split() for ln in out.read_text().splitlines() if ln.strip() and not ln.startswith("#")]
+    assert rows == [f"{capi.MFG_F16} 12 12 12 3".split()]
+    L.mfg_tune_clear()
+    assert L.mfg_tune_lookup(4096, 4096, 4096, capi.MFG_F16) == base
