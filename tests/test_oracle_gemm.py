@@ -104,3 +104,23 @@ def test_parity_tol_formula():
     # 4*(K+2)*2^-24*max(|A~||B~|): for uniform[-1,1] at K=256, max(|A||B|) is ~80
     assert tol == 4 * 258 * 2.0 ** -24 * float(np.max(ref.absval))
     assert 3e-3 < tol < 6e-3
+
+
+def test_error_norms_closed_forms():
+    # all-ones n x n error: max 1, Frobenius exactly n; a single spike sets the max norm
+    n = 37
+    ref = np.zeros((n, n))
+    e = oracle.error_norms(np.ones((n, n), np.float32), ref)
+    assert e["max_abs"] == 1.0 and e["fro"] == float(n) and e["ref_fro"] == 0.0 and e["ref_max"] == 0.0
+    C = np.zeros((5, 4), np.float32)
+    C[3, 2] = -2.5
+    R = np.full((5, 4), 3.0)
+    e = oracle.error_norms(C, R)
+    assert e["max_abs"] == 5.5 and e["ref_max"] == 3.0 and e["ref_fro"] == np.sqrt(20 * 9.0)
+    assert oracle.error_norms(np.zeros((0, 3)), np.zeros((0, 3)))["fro"] == 0.0
+
+
+def test_sample_rows_cover_edges():
+    rows = oracle.sample_rows(1000, n=40, seed=1)
+    assert rows[0] == 0 and rows[-1] == 999 and len(rows) <= 40
+    assert np.all(np.diff(rows) > 0)
