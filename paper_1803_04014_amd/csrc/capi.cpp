@@ -72,19 +72,39 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     if (m == MFG_FP8_E4M3) {
         GemmF8Args a{};
         a.M = M, a.N = N, a.K = K, a.C = C, a.ldc = ldc, a.alpha = alpha, a.beta = beta;
+        auto choose = [&](bool vec) {
+            if (config >= 0) return config;
+            const int t = tuned_lookup(m, M, N, K);
+            if (t >= 0 && t < num_configs_f8() && (vec || t == 0)) return t;
+            return pick_config_f8(M, N, K, vec);
+        };
+        const int64_t ldt = up(K, 16);                      // ld of the transposed B codes
+        const int64_t bT = up(N * ldt, 256);
         if (pre) {
             a.A = static_cast<const uint8_t*>(A), a.lda = lda;
             a.B = static_cast<const uint8_t*>(B), a.ldb = ldb;
             a.sa = reinterpret_cast<const float*>(a.A + mfg_fp8_scale_offset(M, lda));
             a.sb = reinterpret_cast<const float*>(a.B + mfg_fp8_scale_offset(K, ldb));
             const bool vec = al16(A) && lda % 16 == 0;
-            if (config > 0) return MFG_ERR_INVALID_ARG;
-            return launch_gemm_f8(0, a, vec, s);
+            const int cfg = choose(vec);
+            if (cfg < 0 || cfg >= num_configs_f8()) return MFG_ERR_INVALID_ARG;
+            if (!f8_config_needs_bt(cfg)) return launch_gemm_f8(cfg, a, vec, s);
+            if (!vec || K % 128 != 0) return MFG_ERR_UNSUPPORTED;
+            WsLease ws(s, (size_t)bT);
+            if (!ws.ptr()) return ws.status();
+            uint8_t* bt = static_cast<uint8_t*>(ws.ptr());
+            if ((st = launch_transpose_b8(K, N, a.B, ldb, bt, ldt, s)) != MFG_OK) return st;
+            a.Bt = bt, a.ldbt = ldt;
+            return launch_gemm_f8(cfg, a, vec, s);
         }
+        const int cfg = choose(true);
+        if (cfg < 0 || cfg >= num_configs_f8()) return MFG_ERR_INVALID_ARG;
+        const bool need_bt = f8_config_needs_bt(cfg);
+        if (need_bt && K % 128 != 0) return MFG_ERR_UNSUPPORTED;
         const int64_t ldk = up(K, 16), ldn = up(N, 16);
         const int64_t bA = mfg_convert_bytes(M, K, ldk, MFG_FP8_E4M3);
         const int64_t bB = mfg_convert_bytes(K, N, ldn, MFG_FP8_E4M3);
-        WsLease ws(s, (size_t)(up(bA, 256) + bB));
+        WsLease ws(s, (size_t)(up(bA, 256) + up(bB, 256) + (need_bt ? bT : 0)));
         if (!ws.ptr()) return ws.status();
         uint8_t* qa = static_cast<uint8_t*>(ws.ptr());
         uint8_t* qb = qa + up(bA, 256);
@@ -93,8 +113,12 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         if ((st = launch_quantize_fp8(M, K, static_cast<const float*>(A), lda, qa, ldk, sa, s)) != MFG_OK) return st;
         if ((st = launch_quantize_fp8(K, N, static_cast<const float*>(B), ldb, qb, ldn, sb, s)) != MFG_OK) return st;
         a.A = qa, a.lda = ldk, a.B = qb, a.ldb = ldn, a.sa = sa, a.sb = sb;
-        if (config > 0) return MFG_ERR_INVALID_ARG;
-        return launch_gemm_f8(0, a, true, s);
+        if (need_bt) {
+            uint8_t* bt = qb + up(bB, 256);
+            if ((st = launch_transpose_b8(K, N, qb, ldn, bt, ldt, s)) != MFG_OK) return st;
+            a.Bt = bt, a.ldbt = ldt;
+        }
+        return launch_gemm_f8(cfg, a, true, s);
     }
 
     // 16-bit modes
@@ -178,7 +202,10 @@ extern "C" int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode) {
         const int t = tuned_lookup(m, M, N, K);
         return t >= 0 ? t : pick_config_f32(M, N, K, true);
     }
-    if (m == MFG_FP8_E4M3) return 0;
+    if (m == MFG_FP8_E4M3) {
+        const int t = tuned_lookup(m, M, N, K);
+        return (t >= 0 && t < num_configs_f8()) ? t : pick_config_f8(M, N, K, true);
+    }
     return choose16(m, -1, M, N, K, true);
 }
 

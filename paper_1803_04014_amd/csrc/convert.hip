@@ -301,6 +301,58 @@ int launch_quantize_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx,
     return MFG_OK;
 }
 
+// ------------------------------------------------------------ byte transpose
+// dst (cols x rows, ld ldd) = src^T (src rows x cols, ld lds), bytes.  One
+// workgroup per 64 x 64 tile through LDS: each thread reads 16 bytes of a
+// source row and writes 16 bytes of a destination row (vector path when the
+// tile is whole and both matrices have 16-byte rows), bytewise otherwise.
+__global__ __launch_bounds__(256) void transpose_b8_kernel(int64_t rows, int64_t cols, const uint8_t* src,
+                                                           int64_t lds, uint8_t* dst, int64_t ldd, int vec) {
+    __shared__ uint8_t tile[64][64 + 4];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int t = threadIdx.x, tr = t >> 2, tc = (t & 3) * 16;
+    const bool whole = vec && r0 + 64 <= rows && c0 + 64 <= cols;
+    if (whole) {
+        const u32x4 v = *reinterpret_cast<const u32x4*>(src + (r0 + tr) * lds + c0 + tc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) tile[tr][tc + 4 * j + b] = (uint8_t)(v[j] >> (8 * b));
+    } else {
+        for (int j = 0; j < 16; ++j) {
+            const int64_t r = r0 + tr, c = c0 + tc + j;
+            tile[tr][tc + j] = (r < rows && c < cols) ? src[r * lds + c] : (uint8_t)0;
+        }
+    }
+    __syncthreads();
+    // thread t writes destination row c0 + tr (= source column), bytes tc .. tc+15 (source rows)
+    if (whole) {
+        u32x4 w;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            w[j] = (uint32_t)tile[tc + 4 * j][tr] | ((uint32_t)tile[tc + 4 * j + 1][tr] << 8) |
+                   ((uint32_t)tile[tc + 4 * j + 2][tr] << 16) | ((uint32_t)tile[tc + 4 * j + 3][tr] << 24);
+        *reinterpret_cast<u32x4*>(dst + (c0 + tr) * ldd + r0 + tc) = w;
+    } else {
+        for (int j = 0; j < 16; ++j) {
+            const int64_t c = c0 + tr, r = r0 + tc + j;
+            if (c < cols && r < rows) dst[c * ldd + r] = tile[tc + j][tr];
+        }
+    }
+}
+
+int launch_transpose_b8(int64_t rows, int64_t cols, const uint8_t* src, int64_t lds, uint8_t* dst, int64_t ldd,
+                        hipStream_t s) {
+    if (rows == 0 || cols == 0) return MFG_OK;
+    const int64_t gr = cdiv(rows, 64), gc = cdiv(cols, 64);
+    if (gr > 65535) return MFG_ERR_UNSUPPORTED;
+    const int vec = aligned(src, lds, 16, 16) && aligned(dst, ldd, 16, 16);
+    hipLaunchKernelGGL(transpose_b8_kernel, dim3((unsigned)gc, (unsigned)gr), dim3(256), 0, s, rows, cols, src, lds,
+                       dst, ldd, vec);
+    MFG_LAUNCH_CHECK();
+    return MFG_OK;
+}
+
 // ------------------------------------------------------------- error norms
 __global__ __launch_bounds__(kEltThreads) void err_kernel(int64_t rows, int64_t cols, const float* C, int64_t ldc,
                                                           const double* R, int64_t ldr, Red4* part) {

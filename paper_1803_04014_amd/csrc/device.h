@@ -50,6 +50,51 @@ __device__ __forceinline__ int mfma_out_row(int i, int lane) {
     return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
 }
 
+// Epilogue of one row of FN 32x32 accumulator blocks of a wavefront: block
+// fn covers rows rbase + mfma_out_row(i, lane) and column cbase + 32 fn +
+// lane % 32, value val(fn, i).  C = alpha * v when beta == 0 (C is not
+// read), else fma(alpha, v, beta * C).  Every C read of the row of blocks is
+// issued before any of its writes (reads go to clamped, always valid
+// addresses), so the row costs one memory latency rather than one per
+// element: stores and loads to C could otherwise not be reordered.
+template <int FN, class Val>
+__device__ __forceinline__ void store_blocks(float* C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
+                                             int64_t cbase, int lane, float alpha, float beta, Val val) {
+    const int64_t col0 = cbase + (lane & 31);
+    if (beta == 0.0f) {
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+            const int64_t col = col0 + fn * 32;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int64_t row = rbase + mfma_out_row(i, lane);
+                if (row < M && col < N) C[row * ldc + col] = alpha * val(fn, i);
+            }
+        }
+        return;
+    }
+    float c[FN][16];
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) {
+        const int64_t col = col0 + fn * 32;
+        const int64_t cc = col < N ? col : N - 1;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t row = rbase + mfma_out_row(i, lane);
+            c[fn][i] = C[(row < M ? row : M - 1) * ldc + cc];
+        }
+    }
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) {
+        const int64_t col = col0 + fn * 32;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t row = rbase + mfma_out_row(i, lane);
+            if (row < M && col < N) C[row * ldc + col] = __builtin_fmaf(alpha, val(fn, i), beta * c[fn][i]);
+        }
+    }
+}
+
 // XOR swizzle of 16-byte chunks inside an LDS row.  Rows of 8 chunks
 // (128 B): chunk c of row r lives at c ^ ((r ^ (r >> 3)) & 7), so eight
 // consecutive rows read at the same logical chunk hit eight different

@@ -242,21 +242,8 @@ __device__ __forceinline__ void fast_tile(const uint16_t* const (&Ap)[2], const 
 
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int fn = 0; fn < FN; ++fn) {
-            const int64_t col = n0 + wn * G::TNW + fn * 32 + (lane & 31);
-            const int64_t rbase = m0 + wm * G::TMW + fm * 32;
-            if (col < N) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int64_t row = rbase + mfma_out_row(i, lane);
-                    float l = 0.0f, x = 0.0f;
-                    if constexpr (T::LO) l = lo[fm][fn][i];
-                    if constexpr (T::RR) x = rr[fm][fn][i];
-                    if (row < M) store_out(C, row * ldc + col, combine<KIND>(hi[fm][fn][i], l, x), alpha, beta);
-                }
-            }
-        }
+        store_blocks<FN>(C, ldc, M, N, m0 + wm * G::TMW + fm * 32, n0 + wn * G::TNW, lane, alpha, beta,
+                         [&](int fn, int i) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], i); });
 }
 
 template <int KIND, int BM, int BN, int WM, int WN, bool DMA, int BK, int OCC = 1>

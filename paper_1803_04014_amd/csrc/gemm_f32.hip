@@ -11,10 +11,6 @@
 
 namespace mfg {
 
-__device__ __forceinline__ void store_out_f32(float* C, int64_t off, float v, float alpha, float beta) {
-    C[off] = (beta == 0.0f) ? alpha * v : __builtin_fmaf(alpha, v, beta * C[off]);
-}
-
 __device__ __forceinline__ f32x4 load_row4(const float* p, bool valid, int64_t off, int64_t remaining,
                                            bool vec) {
     if (!valid || remaining <= 0) return f32x4{0.f, 0.f, 0.f, 0.f};
@@ -45,13 +41,7 @@ __global__ __launch_bounds__(64) void gemmf32_simple(GemmF32Args p, int vecA) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc = mma_32x32x2_f32(a[j], b[j], acc);
     }
-    if (bn < p.N) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int64_t row = m0 + mfma_out_row(i, lane);
-            if (row < p.M) store_out_f32(C, row * p.ldc + bn, acc[i], p.alpha, p.beta);
-        }
-    }
+    store_blocks<1>(C, p.ldc, p.M, p.N, m0, n0, lane, p.alpha, p.beta, [&](int, int i) { return acc[i]; });
 }
 
 __device__ __forceinline__ int xcd_remap_f32(int bid, int nblk) {
@@ -184,18 +174,8 @@ __global__ __launch_bounds__(256) void gemmf32_tiled(GemmF32Args p, int tiles_m,
     }
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int fn = 0; fn < FN; ++fn) {
-            const int64_t col = n0 + wn * TNW + fn * 32 + (lane & 31);
-            const int64_t rbase = m0 + wm * TMW + fm * 32;
-            if (col < N) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int64_t row = rbase + mfma_out_row(i, lane);
-                    if (row < M) store_out_f32(C, row * p.ldc + col, acc[fm][fn][i], p.alpha, p.beta);
-                }
-            }
-        }
+        store_blocks<FN>(C, p.ldc, M, N, m0 + wm * TMW + fm * 32, n0 + wn * TNW, lane, p.alpha, p.beta,
+                         [&](int fn, int i) { return acc[fm][fn][i]; });
 }
 
 struct CfgF32 {

@@ -7,8 +7,11 @@
 // A 64-deep chunk never straddles a 128-wide K tile and a 32-row / 32-column
 // output block never straddles a 128 tile, so one scale per operand applies
 // to the whole instruction.  Accumulation order: K chunks 0, 64, 128, ...
+#include <type_traits>
+
 #include "device.h"
 #include "internal.h"
+#include "pipe16.h"
 
 namespace mfg {
 
@@ -16,10 +19,6 @@ namespace mfg {
 // exponent field; 2^-127 is the FP32 subnormal with field 0, code 0.
 __device__ __forceinline__ int e8m0_code(float s) {
     return (int)((__builtin_bit_cast(uint32_t, s) >> 23) & 0xFFu);
-}
-
-__device__ __forceinline__ void store_out_f8(float* C, int64_t off, float v, float alpha, float beta) {
-    C[off] = (beta == 0.0f) ? alpha * v : __builtin_fmaf(alpha, v, beta * C[off]);
 }
 
 // One wavefront per 32x32 output tile; operands from global memory.  Lane
@@ -54,25 +53,228 @@ __global__ __launch_bounds__(64) void gemmf8_simple(GemmF8Args p, int vecA) {
         const int sb = e8m0_code(p.sb[kt * ntiles + nt]);
         acc = mma_32x32x64_e4m3(a.v, b.v, acc, sa, sb);
     }
-    if (bn < p.N) {
+    store_blocks<1>(p.C, p.ldc, p.M, p.N, m0, n0, lane, p.alpha, p.beta, [&](int, int i) { return acc[i]; });
+}
+
+// ---------------------------------------------------------------------------
+// gemmf8_pipe: the tiled FP8 kernel.  A (M x K) and Bt = B^T (N x K) are both
+// K-contiguous code matrices, so both operands load and read the same way:
+// LDS stages of 128 K (rows of 128 bytes = one cache line, chunk c of row r
+// at c ^ swz<8>(r), conflict-free), a lane's 32 codes are two ds_read_b128.
+// Each output still accumulates K chunks 0, 64, 128, ... with the same lane
+// data and the same scale codes as gemmf8_simple, so results are bitwise
+// identical.  Pipeline as gemm16_pipe64: S stages in distinct __shared__
+// arrays, fragments double-buffered per 64-deep half step, one barrier per
+// stage, loads S-1 stages ahead.  K must be a multiple of 128; M / N edges
+// clamp rows (and tile-scale indices) to the last valid one.
+template <int BM, int BN, int WM, int WN, int S>
+struct F8Cfg {
+    static constexpr int BK = 128;  // bytes = codes
+    static constexpr int NT = 64 * WM * WN, NW = WM * WN;
+    static constexpr int TMW = BM / WM, TNW = BN / WN;
+    static constexpr int FM = TMW / 32, FN = TNW / 32;
+    static constexpr int A_PLANE = BM * BK, B_PLANE = BN * BK;  // bytes
+    static constexpr int STAGE = A_PLANE + B_PLANE;
+    static constexpr int A_INSTR = A_PLANE / 1024 / NW, B_INSTR = B_PLANE / 1024 / NW;
+    static constexpr int LOADS = A_INSTR + B_INSTR;
+    static constexpr int READS = 2 * (FM + FN);  // per wave per half step
+    static constexpr int MFMAS = FM * FN;        // per wave per half step
+    static_assert(A_PLANE % (1024 * NW) == 0 && B_PLANE % (1024 * NW) == 0, "tile must split into 1 KB loads");
+    static_assert(TMW <= 128 && TNW <= 128 && 128 % TMW == 0 && 128 % TNW == 0, "a wave's rows lie in one scale tile");
+    static_assert(S * STAGE <= 160 * 1024, "LDS budget");
+    static_assert(LOADS * (S - 1) <= 63, "vmcnt range");
+};
+
+template <int BM, int BN, int WM, int WN, int S>
+__device__ __forceinline__ void f8_load(const uint8_t* A, const uint8_t* Bt, int64_t lda, int64_t ldbt, int64_t M,
+                                        int64_t N, int64_t m0, int64_t n0, int64_t k0, uint8_t* st, int wid,
+                                        int lane) {
+    using G = F8Cfg<BM, BN, WM, WN, S>;
+    const int rr = lane >> 3;                 // 8 rows of 128 bytes per 1 KB load
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int64_t row = m0 + mfma_out_row(i, lane);
-            if (row < p.M) store_out_f8(p.C, row * p.ldc + bn, acc[i], p.alpha, p.beta);
-        }
+    for (int i = 0; i < G::A_INSTR; ++i) {
+        const int blk = wid * G::A_INSTR + i;
+        const int row = blk * 8 + rr;
+        const int c = (lane & 7) ^ swz<8>(row);
+        int64_t gm = m0 + row;
+        gm = gm < M ? gm : M - 1;
+        __builtin_amdgcn_global_load_lds((const void*)(A + gm * lda + k0 + c * 16), (lds_void*)(st + blk * 1024), 16,
+                                         0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < G::B_INSTR; ++i) {
+        const int blk = wid * G::B_INSTR + i;
+        const int row = blk * 8 + rr;
+        const int c = (lane & 7) ^ swz<8>(row);
+        int64_t gn = n0 + row;
+        gn = gn < N ? gn : N - 1;
+        __builtin_amdgcn_global_load_lds((const void*)(Bt + gn * ldbt + k0 + c * 16),
+                                         (lds_void*)(st + G::A_PLANE + blk * 1024), 16, 0, 0);
     }
 }
 
-int num_configs_f8() { return 1; }
-const char* config_f8_name(int cfg) { return cfg == 0 ? "simple32" : nullptr; }
-int pick_config_f8(int64_t, int64_t, int64_t, bool) { return 0; }
+template <int FM, int FN>
+struct F8Frags {
+    i32x8 a[FM];
+    i32x8 b[FN];
+};
 
-int launch_gemm_f8(int cfg, const GemmF8Args& a, bool vec_ok, hipStream_t s) {
-    if (cfg != 0) return MFG_ERR_INVALID_ARG;
-    dim3 grid((unsigned)cdiv(a.N, 32), (unsigned)cdiv(a.M, 32), 1);
-    hipLaunchKernelGGL(gemmf8_simple, grid, dim3(64), 0, s, a, vec_ok ? 1 : 0);
+// Lane (r, g) of a 32-row block: the 32 codes at K offset 64 h + 32 g of row r.
+__device__ __forceinline__ i32x8 f8_read_row(const uint8_t* st, int off, int row, int h, int lane) {
+    const int c0 = h * 4 + (lane >> 5) * 2;  // first of the lane's two 16-byte chunks
+    const u32x4 lo = *reinterpret_cast<const u32x4*>(st + off + row * 128 + ((c0 ^ swz<8>(row)) << 4));
+    const u32x4 hi = *reinterpret_cast<const u32x4*>(st + off + row * 128 + (((c0 + 1) ^ swz<8>(row)) << 4));
+    return i32x8{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+}
+
+template <int BM, int BN, int WM, int WN, int S>
+__device__ __forceinline__ void f8_read(const uint8_t* st, int h, int wm, int wn, int lane,
+                                        F8Frags<F8Cfg<BM, BN, WM, WN, S>::FM, F8Cfg<BM, BN, WM, WN, S>::FN>& f) {
+    using G = F8Cfg<BM, BN, WM, WN, S>;
+#pragma unroll
+    for (int fm = 0; fm < G::FM; ++fm) f.a[fm] = f8_read_row(st, 0, wm * G::TMW + fm * 32 + (lane & 31), h, lane);
+#pragma unroll
+    for (int fn = 0; fn < G::FN; ++fn)
+        f.b[fn] = f8_read_row(st, G::A_PLANE, wn * G::TNW + fn * 32 + (lane & 31), h, lane);
+}
+
+template <int BM, int BN, int WM, int WN, int S>
+__global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int tiles_m, int tiles_n, int group_m) {
+    using G = F8Cfg<BM, BN, WM, WN, S>;
+    constexpr int FM = G::FM, FN = G::FN, BK = G::BK;
+    using F = F8Frags<FM, FN>;
+    __shared__ __attribute__((aligned(16))) uint8_t st0[G::STAGE];
+    __shared__ __attribute__((aligned(16))) uint8_t st1[G::STAGE];
+    __shared__ __attribute__((aligned(16))) uint8_t st2[S == 3 ? G::STAGE : 16];
+
+    int tm, tn;
+    raster(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, group_m, tm, tn);
+    const int64_t M = p.M, N = p.N, K = p.K;
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid / WN, wn = wid % WN;
+    const int64_t KTN = K / BK;  // >= 1
+    auto kclamp = [&](int64_t t) { return (t < KTN ? t : KTN - 1) * BK; };
+    auto stage = [&](int s) -> uint8_t* { return s == 0 ? st0 : s == 1 ? st1 : st2; };
+    // this wave's scale tiles (rows clamped like the operand rows)
+    const int64_t ktiles = cdiv(K, MFG_FP8_TILE), ntiles = cdiv(N, MFG_FP8_TILE), mtiles = cdiv(M, MFG_FP8_TILE);
+    int64_t mt = (m0 + wm * G::TMW) / MFG_FP8_TILE, nt = (n0 + wn * G::TNW) / MFG_FP8_TILE;
+    mt = mt < mtiles ? mt : mtiles - 1;
+    nt = nt < ntiles ? nt : ntiles - 1;
+    const float* sa_row = p.sa + mt * ktiles;
+    const float* sb_col = p.sb + nt;
+    auto scale_codes = [&](int64_t t, int& ca, int& cb) {
+        const int64_t kt = t < KTN ? t : KTN - 1;  // stage = one 128-wide scale tile
+        ca = e8m0_code(sa_row[kt]);
+        cb = e8m0_code(sb_col[kt * ntiles]);
+    };
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        f8_load<BM, BN, WM, WN, S>(p.A, p.Bt, p.lda, p.ldbt, M, N, m0, n0, kclamp(s), stage(s), wid, lane);
+    int ca, cb, na, nb;
+    scale_codes(0, ca, cb);
+    F f[2];
+    wait_vmcnt<G::LOADS * (S - 1)>();
+    bare_barrier();
+    f8_read<BM, BN, WM, WN, S>(st0, 0, wm, wn, lane, f[0]);
+
+    auto mma = [&](const F& fr, int sa, int sb) {
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = mma_32x32x64_e4m3(fr.a[fm], fr.b[fn], acc[fm][fn], sa, sb);
+    };
+    auto step = [&](auto ucst, int64_t t) {
+        constexpr int u = decltype(ucst)::value;
+        scale_codes(t + 1, na, nb);  // next stage's scales, early
+        f8_read<BM, BN, WM, WN, S>(stage(u), 1, wm, wn, lane, f[1]);
+        mma(f[0], ca, cb);
+        pipe_interleave<G::READS, G::MFMAS>();
+        __builtin_amdgcn_sched_barrier(0);
+        wait_vmcnt<G::LOADS * (S - 2)>();
+        wait_lgkm0();
+        bare_barrier();
+        f8_load<BM, BN, WM, WN, S>(p.A, p.Bt, p.lda, p.ldbt, M, N, m0, n0, kclamp(t + S), stage(u), wid, lane);
+        f8_read<BM, BN, WM, WN, S>(stage((u + 1) % S), 0, wm, wn, lane, f[0]);
+        mma(f[1], ca, cb);
+        pipe_interleave<G::READS, G::MFMAS>();
+        __builtin_amdgcn_sched_barrier(0);
+        ca = na, cb = nb;
+    };
+    const int64_t KFULL = KTN - KTN % S;
+    for (int64_t t0 = 0; t0 < KFULL; t0 += S) {
+        step(std::integral_constant<int, 0>{}, t0);
+        step(std::integral_constant<int, 1>{}, t0 + 1);
+        if constexpr (S == 3) step(std::integral_constant<int, 2>{}, t0 + 2);
+    }
+    if (KFULL < KTN) step(std::integral_constant<int, 0>{}, KFULL);
+    if constexpr (S == 3)
+        if (KFULL + 1 < KTN) step(std::integral_constant<int, 1>{}, KFULL + 1);
+
+    wait_vmcnt<0>();
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+        store_blocks<FN>(p.C, p.ldc, M, N, m0 + wm * G::TMW + fm * 32, n0 + wn * G::TNW, lane, p.alpha, p.beta,
+                         [&](int fn, int i) { return acc[fm][fn][i]; });
+}
+
+struct CfgF8 {
+    const char* name;
+    int bm, bn, wm, wn, s, group_m;
+};
+static const CfgF8 kCfgF8[] = {
+    {"simple32", 0, 0, 0, 0, 0, 0},
+    {"p256x256k128s2w2x2g8", 256, 256, 2, 2, 2, 8},
+    {"p128x128k128s3w2x2g8", 128, 128, 2, 2, 3, 8},
+    {"p256x128k128s2w2x2g8", 256, 128, 2, 2, 2, 8},
+};
+constexpr int kNumF8 = (int)(sizeof(kCfgF8) / sizeof(kCfgF8[0]));
+
+template <int BM, int BN, int WM, int WN, int S>
+static int launch_f8_pipe(const GemmF8Args& a, int group_m, hipStream_t s) {
+    using G = F8Cfg<BM, BN, WM, WN, S>;
+    const int tiles_m = (int)cdiv(a.M, BM), tiles_n = (int)cdiv(a.N, BN);
+    hipLaunchKernelGGL((gemmf8_pipe<BM, BN, WM, WN, S>), dim3(tiles_m * tiles_n), dim3(G::NT), 0, s, a, tiles_m,
+                       tiles_n, group_m);
     MFG_LAUNCH_CHECK();
     return MFG_OK;
+}
+
+int num_configs_f8() { return kNumF8; }
+const char* config_f8_name(int cfg) { return (cfg >= 0 && cfg < kNumF8) ? kCfgF8[cfg].name : nullptr; }
+bool f8_config_needs_bt(int cfg) { return cfg > 0 && cfg < kNumF8; }
+
+// Tiled from one 128 x 128 tile per CU up (K a multiple of 128), else simple.
+int pick_config_f8(int64_t M, int64_t N, int64_t K, bool vec_ok) {
+    if (!vec_ok || K % 128 != 0 || M < 1 || N < 1) return 0;
+    if (cdiv(M, 256) * cdiv(N, 256) >= 512) return 1;
+    if (cdiv(M, 128) * cdiv(N, 128) >= 256) return 2;
+    return 0;
+}
+
+// The tiled kernels need K % 128 == 0, 16-byte aligned rows of A and Bt.
+int launch_gemm_f8(int cfg, const GemmF8Args& a, bool vec_ok, hipStream_t s) {
+    if (cfg < 0 || cfg >= kNumF8) return MFG_ERR_INVALID_ARG;
+    if (cfg == 0) {
+        dim3 grid((unsigned)cdiv(a.N, 32), (unsigned)cdiv(a.M, 32), 1);
+        hipLaunchKernelGGL(gemmf8_simple, grid, dim3(64), 0, s, a, vec_ok ? 1 : 0);
+        MFG_LAUNCH_CHECK();
+        return MFG_OK;
+    }
+    const bool bt_ok = a.Bt != nullptr && ((uintptr_t)a.Bt % 16) == 0 && a.ldbt % 16 == 0;
+    if (!vec_ok || !bt_ok || a.K % 128 != 0 || a.M < 1 || a.N < 1) return MFG_ERR_UNSUPPORTED;
+    const CfgF8& c = kCfgF8[cfg];
+    if (c.bm == 256 && c.bn == 256) return launch_f8_pipe<256, 256, 2, 2, 2>(a, c.group_m, s);
+    if (c.bm == 128 && c.bn == 128) return launch_f8_pipe<128, 128, 2, 2, 3>(a, c.group_m, s);
+    if (c.bm == 256 && c.bn == 128) return launch_f8_pipe<256, 128, 2, 2, 2>(a, c.group_m, s);
+    return MFG_ERR_INTERNAL;
 }
 
 }  // namespace mfg

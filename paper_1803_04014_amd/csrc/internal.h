@@ -60,6 +60,8 @@ struct GemmF8Args {
     int64_t M, N, K;
     const uint8_t* A;    // codes
     const uint8_t* B;
+    const uint8_t* Bt;   // B's codes transposed (N x K, ld ldbt), for the tiled kernels
+    int64_t ldbt;
     const float* sa;     // ceil(M/128) x ceil(K/128)
     const float* sb;     // ceil(K/128) x ceil(N/128)
     float* C;
@@ -85,6 +87,9 @@ int num_configs_f8();
 const char* config_f8_name(int cfg);
 int pick_config_f8(int64_t M, int64_t N, int64_t K, bool vec_ok);
 int launch_gemm_f8(int cfg, const GemmF8Args& a, bool vec_ok, hipStream_t s);
+bool f8_config_needs_bt(int cfg);
+int launch_transpose_b8(int64_t rows, int64_t cols, const uint8_t* src, int64_t lds, uint8_t* dst, int64_t ldd,
+                        hipStream_t s);
 
 // Conversions (convert.hip).
 int launch_round_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* out,

@@ -45,9 +45,16 @@ __device__ __forceinline__ float combine(float hi, float lo, float rr) {
     }
 }
 
-__device__ __forceinline__ void store_out(float* C, int64_t off, float v, float alpha, float beta) {
-    C[off] = (beta == 0.0f) ? alpha * v : __builtin_fmaf(alpha, v, beta * C[off]);
+// Value i of accumulator block (h, l, r) after combine (l, r unused, and
+// never read, for kinds without them).
+template <int KIND>
+__device__ __forceinline__ float combine_at(const f32x16& h, const f32x16& l, const f32x16& r, int i) {
+    float lv = 0.0f, rv = 0.0f;
+    if constexpr (KT<KIND>::LO) lv = l[i];
+    if constexpr (KT<KIND>::RR) rv = r[i];
+    return combine<KIND>(h[i], lv, rv);
 }
+
 
 __device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) {
     return (uint32_t)lo | ((uint32_t)hi << 16);
@@ -103,13 +110,8 @@ __device__ __forceinline__ void simple_tile(const Gemm16Args& p, int64_t bz, int
         for (int q = 0; q < T::NPB; ++q) b[q] = load_col8(Bp[q], bn < N, kb * p.ldb + bn, p.ldb, K - kb);
         mma_step<KIND>(a, b, hi, lo, rr);
     }
-    if (bn < N) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int64_t row = m0 + mfma_out_row(i, lane);
-            if (row < M) store_out(C, row * p.ldc + bn, combine<KIND>(hi[i], lo[i], rr[i]), p.alpha, p.beta);
-        }
-    }
+    store_blocks<1>(C, p.ldc, M, N, m0, n0, lane, p.alpha, p.beta,
+                    [&](int, int i) { return combine_at<KIND>(hi, lo, rr, i); });
 }
 
 // Simple kernel: one wavefront per 32x32 output tile, operands straight from
@@ -339,21 +341,8 @@ __device__ __forceinline__ void tile_gemm(const uint16_t* const (&Ap)[2], const 
 
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int fn = 0; fn < FN; ++fn) {
-            const int64_t col = n0 + wn * G::TNW + fn * 32 + (lane & 31);
-            const int64_t rbase = m0 + wm * G::TMW + fm * 32;
-            if (col < N) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int64_t row = rbase + mfma_out_row(i, lane);
-                    float l = 0.0f, x = 0.0f;
-                    if constexpr (T::LO) l = lo[fm][fn][i];
-                    if constexpr (T::RR) x = rr[fm][fn][i];
-                    if (row < M) store_out(C, row * ldc + col, combine<KIND>(hi[fm][fn][i], l, x), alpha, beta);
-                }
-            }
-        }
+        store_blocks<FN>(C, ldc, M, N, m0 + wm * G::TMW + fm * 32, n0 + wn * G::TNW, lane, alpha, beta,
+                         [&](int fn, int i) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], i); });
 }
 
 template <int KIND, int BM, int BN, int BK, int WM, int WN>

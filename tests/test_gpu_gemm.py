@@ -37,7 +37,7 @@ def test_256_cube_acceptance(mode):
 
 
 # ------------------------------------------------- every mode, every config
-RAGGED = [(300, 260, 200), (129, 65, 33), (512, 384, 320), (1000, 1000, 512)]
+RAGGED = [(300, 260, 200), (129, 65, 33), (512, 384, 320), (1000, 1000, 512), (257, 130, 384)]
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -54,10 +54,14 @@ def test_mode_parity_all_configs(mode, shape):
             C = run_gemm(mode, A, B, C0, 1.25, -0.5, config=cfg)
         except mfg.MfgError as e:
             # tiled FP32 kernels need 16-byte aligned rows (lda % 4 == 0); the fast
-            # 16-bit kernels need K % 64 == 0 and N % 8 == 0; both report it
+            # 16-bit kernels need K % 64 == 0 and N % 8 == 0; the tiled FP8
+            # kernels K % 128 == 0; all report it
             name = mfg.config_name(mode, cfg)
             assert e.status == mfg.capi.MFG_ERR_UNSUPPORTED, name
-            assert (mode == "f32" and cfg > 0 and K % 4 != 0) or (name[0] in "fp" and (K % 64 or N % 8)), name
+            if mode == "fp8":
+                assert name[0] == "p" and K % 128, name
+            else:
+                assert (mode == "f32" and cfg > 0 and (K % 4 or N % 4)) or (name[0] in "fpq" and (K % 64 or N % 8)), name
             continue
         err, tol = assert_parity(C, ref, f"{mode} cfg {cfg} {mfg.config_name(mode, cfg)}")
         # a-priori accuracy against the exact product
