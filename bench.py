@@ -91,7 +91,7 @@ def pmc_summarize(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_byt
     """HBM bytes per launch of the headline GEMM kernel from two rocprofv3 --pmc
     runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
     counter reads for a plain copy of copy_bytes (torch's elementwise copy)."""
-    kern = "gemm16_fast"
+    kern = "gemm16_"  # the headline run launches one GEMM kernel
     copy = "copy"
     f_k = _per_dispatch(fetch_dir, "FETCH_SIZE", kern)
     w_k = _per_dispatch(write_dir, "WRITE_SIZE", kern)

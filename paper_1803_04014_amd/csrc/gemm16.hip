@@ -142,12 +142,14 @@ static const Cfg16 kCfgSplit[] = {
     {"f128x128k32w2x2g8dma", 128, 128, 8, 5, 2, 2},
     {"f256x128k32w2x2g8dma", 256, 128, 8, 5, 2, 2},
     {"f128x128k64w2x2g8dma", 128, 128, 8, 2, 2, 2},
+    {"q128x128k64s2w2x2g8", 128, 128, 8, 7, 2, 2},
 };
 static const Cfg16 kCfgSplit4[] = {
     {"simple32", 0, 0, 0},
     {"t128x128k32w2x2g8", 128, 128, 8},
     {"t64x64k32w2x2g8", 64, 64, 8},
     {"f128x128k32w2x2g8dma", 128, 128, 8, 5, 2, 2},
+    {"q128x128k64s2w2x2g8", 128, 128, 8, 7, 2, 2},
 };
 
 static const Cfg16* menu(int kind, int* n) {
@@ -173,30 +175,6 @@ const char* config16_name(int kind, int cfg) {
     int n;
     const Cfg16* m = menu(kind, &n);
     return (cfg >= 0 && cfg < n) ? m[cfg].name : nullptr;
-}
-
-// Default configuration per kind, from measured sweeps on MI355X: the fast
-// kernels once the grid has at least one 128 x 128 tile per CU, the 64 x 64
-// tiled kernel below that (more, smaller workgroups fill the chip), the
-// simple kernel when rows are not 16-byte aligned.
-int pick_config16(int kind, int64_t M, int64_t N, int64_t K, bool vec_ok) {
-    if (!vec_ok) return 0;
-    const bool fast = K % 64 == 0 && N % 8 == 0 && N >= 8;
-    const int64_t t128 = cdiv(M, 128) * cdiv(N, 128);
-    const int64_t t256 = cdiv(M, 128) * cdiv(N, 256);
-    const bool big = M >= 64 && N >= 64;
-    if (kind == K_F16 || kind == K_BF16) {
-        if (fast && t256 >= 512) return 16;  // f128x256k32w2x2g8o2
-        if (fast && t128 >= 256) return 11;  // f128x128k64w2x2g8dma
-        return big ? 6 : 0;                  // t64x64k64w2x2g8
-    }
-    if (kind == K_SPLIT4) {
-        if (fast && t128 >= 256) return 3;   // f128x128k32w2x2g8dma
-        return big ? 2 : 0;                  // t64x64k32w2x2g8
-    }
-    if (kind == K_SPLIT3 && fast && cdiv(M, 256) * cdiv(N, 128) >= 512) return 5;  // f256x128k32w2x2g8dma
-    if (fast && t128 >= 256) return 6;       // f128x128k64w2x2g8dma
-    return big ? 3 : 0;                      // t64x64k32w2x2g8
 }
 
 template <int KIND>
@@ -240,6 +218,8 @@ static int launch_kind(int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok,
             if (c.bm == 128 && c.bn == 256) return launch_pipe64<KIND, 128, 256, 2, 2, 3>(a, batch, c.group_m, s);
             if (c.bm == 256 && c.bn == 128) return launch_pipe64<KIND, 256, 128, 2, 2, 3>(a, batch, c.group_m, s);
             if (c.bm == 128 && c.bn == 128) return launch_pipe64<KIND, 128, 128, 2, 2, 3>(a, batch, c.group_m, s);
+        } else {
+            if (c.bm == 128 && c.bn == 128) return launch_pipe64<KIND, 128, 128, 2, 2, 2>(a, batch, c.group_m, s);
         }
         return MFG_ERR_INTERNAL;
     }

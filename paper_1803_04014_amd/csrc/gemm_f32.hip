@@ -191,14 +191,6 @@ static const CfgF32 kCfgF32[] = {
 int num_configs_f32() { return (int)(sizeof(kCfgF32) / sizeof(kCfgF32[0])); }
 const char* config_f32_name(int cfg) { return (cfg >= 0 && cfg < num_configs_f32()) ? kCfgF32[cfg].name : nullptr; }
 
-int pick_config_f32(int64_t M, int64_t N, int64_t K, bool vec_ok) {
-    (void)K;
-    if (!vec_ok) return 0;
-    if (M >= 4096 && N >= 4096) return 2;
-    if (M >= 128 && N >= 128) return 1;
-    return 0;
-}
-
 template <int BM, int BN>
 static int launch_f32_tiled(const GemmF32Args& a, int64_t batch, int group_m, hipStream_t s) {
     constexpr int lds = 2 * (BM + BN) * 32 * 4;

@@ -251,14 +251,6 @@ int num_configs_f8() { return kNumF8; }
 const char* config_f8_name(int cfg) { return (cfg >= 0 && cfg < kNumF8) ? kCfgF8[cfg].name : nullptr; }
 bool f8_config_needs_bt(int cfg) { return cfg > 0 && cfg < kNumF8; }
 
-// Tiled from one 128 x 128 tile per CU up (K a multiple of 128), else simple.
-int pick_config_f8(int64_t M, int64_t N, int64_t K, bool vec_ok) {
-    if (!vec_ok || K % 128 != 0 || M < 1 || N < 1) return 0;
-    if (cdiv(M, 256) * cdiv(N, 256) >= 512) return 1;
-    if (cdiv(M, 128) * cdiv(N, 128) >= 256) return 2;
-    return 0;
-}
-
 // The tiled kernels need K % 128 == 0, 16-byte aligned rows of A and Bt.
 int launch_gemm_f8(int cfg, const GemmF8Args& a, bool vec_ok, hipStream_t s) {
     if (cfg < 0 || cfg >= kNumF8) return MFG_ERR_INVALID_ARG;
