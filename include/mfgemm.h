@@ -149,10 +149,12 @@ int mfg_gemm_batched(int64_t count, int64_t M, int64_t N, int64_t K,
                      float alpha, float beta, int mode, void* stream);
 
 /* --------------------------------------------------------- grouped GEMM
- * Thousands of GEMMs of different shapes in one persistent launch.
- * A problem's operands are 16-bit for F16/BF16 and FP32 for F32; other modes
- * are MFG_ERR_UNSUPPORTED.  The descriptor array is host memory; the plan
- * copies it to the device, so it may be freed after mfg_grouped_plan_create.
+ * Thousands of GEMMs of different shapes in one persistent launch (paper
+ * Sec. IV.B, batched GEMM, generalised to uneven shapes).  Modes MFG_F16 and
+ * MFG_BF16 with preconverted 16-bit operands; other modes are
+ * MFG_ERR_UNSUPPORTED.  Each problem's result is bitwise that of mfg_gemm on
+ * the problem alone.  The descriptor array is host memory; the plan copies it
+ * to the device, so it may be freed after mfg_grouped_plan_create.
  */
 typedef struct mfg_problem {
     int64_t M, N, K;
@@ -164,9 +166,10 @@ typedef struct mfg_problem {
 
 typedef struct mfg_grouped_plan mfg_grouped_plan;
 
-/* Build a plan: validates every problem, assigns each a tile class, orders
- * work items largest first, and uploads descriptors and the work list
- * (device memory owned by the plan).  `out` receives the plan (host). */
+/* Build a plan: validates every problem, splits it into 32 x 32 output
+ * tiles (work items, one wavefront each), orders them by decreasing K, and
+ * uploads descriptors and the work list (device memory owned by the plan).
+ * `out` receives the plan (host). */
 int mfg_grouped_plan_create(int64_t count, const mfg_problem* problems, int mode,
                             mfg_grouped_plan** out);
 /* Run the plan once on `stream` (one persistent kernel launch). */
@@ -244,8 +247,8 @@ int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode);
  * fit waits, and so do the ones behind it).  When a slot (one HIP stream) is
  * free, the oldest admitted request takes up to max_group admitted requests
  * of its mode, alpha and beta into one group: operands are converted on the
- * slot's stream, small FP16/BF16 problems (M*N < 512*512, at most 64 tiles of
- * 64 x 64) run as one persistent grouped launch, the others one by one; one
+ * slot's stream, small FP16/BF16 problems (M*N < 512*512, at most 256 tiles
+ * of 32 x 32) run as one persistent grouped launch, the others one by one; one
  * completion event per group.  Footprint: the mode's converted A (ld = K
  * rounded up to 8, or to 16 for FP8) and B (ld = N rounded likewise), each
  * rounded up to 256 bytes; 0 for MFG_F32 and for empty problems.  The fixed

@@ -312,6 +312,7 @@ struct mfg_grouped_plan {
     int mode = 0, kind = 0, device = 0;
     int64_t count = 0, nwork = 0;
     int grid = 0;
+    GroupedSplit split{};
     GroupedDesc* d_desc = nullptr;
     GroupedWork* d_work = nullptr;
     double flops = 0.0, bytes = 0.0;
@@ -343,21 +344,15 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
         d.pad = 0;
         flops += 2.0 * (double)p.M * (double)p.N * (double)p.K;
         bytes += 2.0 * (double)(p.M * p.K + p.K * p.N) + 4.0 * (double)(p.M * p.N);
-        const int64_t tm = cdiv(p.M, 64), tn = cdiv(p.N, 64);
-        for (int64_t a = 0; a < tm; ++a)
-            for (int64_t b = 0; b < tn; ++b) work.push_back(GroupedWork{(int32_t)i, (int32_t)a, (int32_t)b, 0});
     }
-    // Largest cost (K) first, stable, so the static stride balances like LPT.
-    std::stable_sort(work.begin(), work.end(), [&](const GroupedWork& x, const GroupedWork& y) {
-        return descs[(size_t)x.prob].K > descs[(size_t)y.prob].K;
-    });
+    GroupedSplit split{};
+    build_grouped_work(descs.data(), count, work, split);
     std::unique_ptr<mfg_grouped_plan> plan(new mfg_grouped_plan());
+    plan->split = split;
     plan->mode = m, plan->kind = kind_of(m), plan->count = count, plan->nwork = (int64_t)work.size();
     plan->flops = flops, plan->bytes = bytes;
     MFG_HIP_CHECK(hipGetDevice(&plan->device));
-    // Persistent grid: four 256-thread workgroups per CU (LDS 32 KB each).
-    const int64_t g = (int64_t)device_cu_count() * 4;
-    plan->grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, plan->nwork));
+    plan->grid = grouped_grid(split);
     if (count > 0) {
         if (hipMalloc(&plan->d_desc, descs.size() * sizeof(GroupedDesc)) != hipSuccess) return MFG_ERR_NO_MEMORY;
         MFG_HIP_CHECK(hipMemcpy(plan->d_desc, descs.data(), descs.size() * sizeof(GroupedDesc), hipMemcpyHostToDevice));
@@ -369,9 +364,6 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
         }
         MFG_HIP_CHECK(hipMemcpy(plan->d_work, work.data(), work.size() * sizeof(GroupedWork), hipMemcpyHostToDevice));
     }
-    // Set kernel attributes now, outside any stream capture.
-    int st = grouped_launch(plan->kind, nullptr, nullptr, 0, 1, 1.f, 0.f, nullptr);
-    if (st != MFG_OK) return st;
     *out = plan.release();
     return MFG_OK;
 }
@@ -383,7 +375,7 @@ extern "C" int mfg_grouped_plan_create(int64_t count, const mfg_problem* problem
 
 extern "C" int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, void* stream) {
     if (!plan) return MFG_ERR_INVALID_ARG;
-    MFG_GUARD(grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->nwork, plan->grid, alpha, beta,
+    MFG_GUARD(grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->split, plan->grid, alpha, beta,
                              (hipStream_t)stream));
 }
 
@@ -397,7 +389,7 @@ static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hi
     if (!plan->exec) {
         if (!plan->cap_stream) MFG_HIP_CHECK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
         MFG_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
-        int st = grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->nwork, plan->grid, alpha, beta,
+        int st = grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->split, plan->grid, alpha, beta,
                                 plan->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);

@@ -56,9 +56,10 @@ __device__ __forceinline__ int mfma_out_row(int i, int lane) {
 // read), else fma(alpha, v, beta * C).  Every C read of the row of blocks is
 // issued before any of its writes (reads go to clamped, always valid
 // addresses), so the row costs one memory latency rather than one per
-// element: stores and loads to C could otherwise not be reordered.
-template <int FN, class Val>
-__device__ __forceinline__ void store_blocks(float* C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
+// element: stores and loads to C could otherwise not be reordered.  C may
+// be a generic or a global (address space 1) pointer.
+template <int FN, class Val, class CPtr>
+__device__ __forceinline__ void store_blocks(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
                                              int64_t cbase, int lane, float alpha, float beta, Val val) {
     const int64_t col0 = cbase + (lane & 31);
     if (beta == 0.0f) {

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include <cstddef>
 #include <cstdint>
 
@@ -116,14 +118,23 @@ struct GroupedDesc {  // one problem, device resident
     int32_t vec;  // 1: 16-byte aligned rows (LDS-staged tile), 0: per-wave tile
     int32_t pad;
 };
-struct GroupedWork {  // one 64 x 64 output tile of one problem
+constexpr int kGroupedTile = 32;  // output tile of a grouped work item (one wavefront)
+struct GroupedWork {  // one kGroupedTile x kGroupedTile output tile of one problem
     int32_t prob, tm, tn, pad;
 };
 int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_ok, int num_cu,
                          hipStream_t s);
-int grouped_launch(int kind, const GroupedDesc* descs, const GroupedWork* work, int64_t nwork,
+// Work list of a grouped launch, split into one contiguous range per XCD
+// (workgroup b runs on XCD b % kXcds): each problem's tiles stay on one XCD,
+// so its operands are fetched into one L2.
+constexpr int kXcds = 8;
+struct GroupedSplit {
+    int64_t off[kXcds + 1];
+};
+void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split);
+int grouped_launch(int kind, const GroupedDesc* descs, const GroupedWork* work, const GroupedSplit& split,
                    int grid, float alpha, float beta, hipStream_t s);
-int grouped_lds_bytes();
+int grouped_grid(const GroupedSplit& split);  // workgroups of a grouped launch (a multiple of kXcds)
 
 // Validation (validate.cpp; pure host code).
 int validate_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,

@@ -83,10 +83,11 @@ void plan_footprint(Req& q) {
     q.footprint = q.off_b + up(bb, 256);
 }
 
-// A problem the grouped kernel takes (64 x 64 work items, few per problem).
+// A problem the grouped kernel takes (few 32 x 32 work items).
+constexpr int64_t kSmallTiles = 256;
 bool grouped_small(const mfg_request& r) {
     return (r.mode == MFG_F16 || r.mode == MFG_BF16) && r.M * r.N < (int64_t)512 * 512 &&
-           cdiv(r.M, 64) * cdiv(r.N, 64) <= 64;
+           cdiv(r.M, kGroupedTile) * cdiv(r.N, kGroupedTile) <= kSmallTiles;
 }
 
 struct Slot {
@@ -140,7 +141,7 @@ int mfg_server::init_device() {
     int pools = 0;  // converted operands live in stream-ordered allocations
     MFG_HIP_CHECK(hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, cfg.device));
     if (!pools) return MFG_ERR_UNSUPPORTED;
-    work_cap = (int64_t)cfg.max_group * 64;
+    work_cap = (int64_t)cfg.max_group * kSmallTiles;
     for (auto& sl : slots) {
         MFG_HIP_CHECK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
         MFG_HIP_CHECK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
@@ -149,10 +150,7 @@ int mfg_server::init_device() {
         MFG_HIP_CHECK(hipMalloc((void**)&sl.d_desc, sizeof(GroupedDesc) * cfg.max_group));
         MFG_HIP_CHECK(hipMalloc((void**)&sl.d_work, sizeof(GroupedWork) * work_cap));
     }
-    // kernel attributes of the grouped kernel, once, before any launch
-    int s = grouped_launch(K_F16, nullptr, nullptr, 0, 1, 1.f, 0.f, nullptr);
-    if (s == MFG_OK) s = grouped_launch(K_BF16, nullptr, nullptr, 0, 1, 1.f, 0.f, nullptr);
-    return s;
+    return MFG_OK;
 }
 
 void mfg_server::release_device() {
@@ -279,28 +277,27 @@ int mfg_server::run_request(Slot& sl, Req* q, bool& grouped) {
 // One persistent grouped launch over the group's small FP16 / BF16 problems
 // (the same descriptors and work order as a grouped plan; one alpha, beta).
 int mfg_server::run_grouped(Slot& sl, const std::vector<Req*>& g) {
-    int64_t nd = 0, nw = 0;
+    int64_t nd = 0;
     for (Req* q : g) {
         const mfg_request& r = q->r;
-        GroupedDesc& d = sl.h_desc[nd];
+        GroupedDesc& d = sl.h_desc[nd++];
         d.M = r.M, d.N = r.N, d.K = r.K, d.lda = q->lda_c, d.ldb = q->ldb_c, d.ldc = r.ldc;
         d.A = static_cast<const uint16_t*>(q->ws);
         d.B = reinterpret_cast<const uint16_t*>(static_cast<const char*>(q->ws) + q->off_b);
         d.C = r.C;
         d.vec = 1;  // workspace planes: 256-byte aligned, ld a multiple of 8
         d.pad = 0;
-        for (int64_t a = 0; a < cdiv(r.M, 64); ++a)
-            for (int64_t b = 0; b < cdiv(r.N, 64); ++b) sl.h_work[nw++] = GroupedWork{(int32_t)nd, (int32_t)a, (int32_t)b, 0};
-        ++nd;
     }
-    std::stable_sort(sl.h_work, sl.h_work + nw, [&](const GroupedWork& x, const GroupedWork& y) {
-        return sl.h_desc[x.prob].K > sl.h_desc[y.prob].K;
-    });
+    GroupedSplit split{};
+    std::vector<GroupedWork> work;
+    build_grouped_work(sl.h_desc, nd, work, split);
+    const int64_t nw = (int64_t)work.size();  // <= max_group * kSmallTiles (grouped_small)
+    std::copy(work.begin(), work.end(), sl.h_work);
     MFG_HIP_CHECK(hipMemcpyAsync(sl.d_desc, sl.h_desc, sizeof(GroupedDesc) * nd, hipMemcpyHostToDevice, sl.stream));
     MFG_HIP_CHECK(hipMemcpyAsync(sl.d_work, sl.h_work, sizeof(GroupedWork) * nw, hipMemcpyHostToDevice, sl.stream));
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)device_cu_count() * 4, nw));
     const int kind = g.front()->r.mode == MFG_BF16 ? K_BF16 : K_F16;
-    return grouped_launch(kind, sl.d_desc, sl.d_work, nw, grid, g.front()->r.alpha, g.front()->r.beta, sl.stream);
+    return grouped_launch(kind, sl.d_desc, sl.d_work, split, grouped_grid(split), g.front()->r.alpha,
+                          g.front()->r.beta, sl.stream);
 }
 
 void mfg_server::launch_group(int si, std::vector<Req*>& g) {

@@ -89,7 +89,7 @@ def test_grouped_equals_solo_and_graph_replays():
     probs, host_ops = _grouped_problems(300, 16, 200, 6, unaligned_every=7)
     plan = mfg.GroupedPlan(probs, "f16")
     info = plan.info()
-    assert info["work_items"] == sum(-(-p[0].shape[0] // 64) * -(-p[1].shape[1] // 64) for p in probs)
+    assert info["work_items"] == sum(-(-p[0].shape[0] // 32) * -(-p[1].shape[1] // 32) for p in probs)
     plan.run(1.0, 0.0)
     first = [host(p[2]).copy() for p in probs]
     for i in range(0, 300, 23):
