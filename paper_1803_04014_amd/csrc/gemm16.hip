@@ -62,12 +62,13 @@ static int launch_pipe(const Gemm16Args& a, int64_t batch, int group_m, hipStrea
     return MFG_OK;
 }
 
-template <int KIND, int BM, int BN, int WM, int WN, int S>
+template <int KIND, int BM, int BN, int WM, int WN, int S, int KK = 2>
 static int launch_pipe64(const Gemm16Args& a, int64_t batch, int group_m, hipStream_t s) {
-    using G = Pipe64Cfg<KIND, BM, BN, WM, WN, S>;
+    using G = Pipe64Cfg<KIND, BM, BN, WM, WN, S, KK>;
     const int tiles_m = (int)cdiv(a.M, BM), tiles_n = (int)cdiv(a.N, BN);
     dim3 grid(tiles_m * tiles_n, (unsigned)batch, 1);
-    hipLaunchKernelGGL((gemm16_pipe64<KIND, BM, BN, WM, WN, S>), grid, dim3(G::NT), 0, s, a, tiles_m, tiles_n, group_m);
+    hipLaunchKernelGGL((gemm16_pipe64<KIND, BM, BN, WM, WN, S, KK>), grid, dim3(G::NT), 0, s, a, tiles_m, tiles_n,
+                       group_m);
     MFG_LAUNCH_CHECK();
     return MFG_OK;
 }

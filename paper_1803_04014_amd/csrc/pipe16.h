@@ -278,16 +278,20 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe(Gemm16Args p, int ti
 // BK = 64 swizzle of fast16.h), while the operand fragments stay double-
 // buffered at 32-wide half steps, which keeps the register budget of a
 // 256 x 256 tile (256 accumulators + 2 x 64 fragment VGPRs):
-//   first half of stage step T:  read T's second-half fragments into f[1],
-//                                MFMAs on f[0];
-//   second half:                 wait for stage T+1's loads and this wave's
-//                                LDS reads, barrier, refill stage T's array
-//                                with step T+S, read T+1's first-half
-//                                fragments into f[0], MFMAs on f[1].
+// KK = 2: fragment steps of 32 (two per stage); KK = 1: of 16 (four per
+// stage), which halves the fragment registers (measured slower for the
+// tiles in the menus, so they all use KK = 2):
+//   fragment steps but the last:  read the next step's fragments into the
+//                                 other buffer, MFMAs on this one;
+//   the last:                     wait for stage T+1's loads and this wave's
+//                                 LDS reads, barrier, refill stage T's array
+//                                 with step T+S, read T+1's first fragments,
+//                                 MFMAs.
 // Loads run S-1 stage steps ahead; one barrier per stage step.
-template <int KIND, int BM, int BN, int WM, int WN, int S>
+template <int KIND, int BM, int BN, int WM, int WN, int S, int KK = 2>
 struct Pipe64Cfg {
     static constexpr int BK = 64;
+    static constexpr int KSUB = 4 / KK;  // fragment steps per stage (KK 16-deep chunks each)
     static constexpr int NT = 64 * WM * WN, NW = WM * WN;
     static constexpr int TMW = BM / WM, TNW = BN / WN;
     static constexpr int FM = TMW / 32, FN = TNW / 32;
@@ -299,12 +303,13 @@ struct Pipe64Cfg {
     static constexpr int B_INSTR = B_PLANE / 512 / NW;
     static constexpr int LOADS = NPA * A_INSTR + NPB * B_INSTR;  // per wave per stage
     static constexpr int B_ROWS_PER_INSTR = 512 / BN, B_CPR = BN / 8;
-    static constexpr int READS = 2 * (FM * NPA + 2 * FN * NPB);  // LDS reads per wave per half step
+    static constexpr int READS = KK * (FM * NPA + 2 * FN * NPB);  // LDS reads per wave per fragment step
     static constexpr int PRODUCTS = KIND == K_REFINE_A ? 2 : KIND == K_SPLIT3 ? 3 : KIND == K_SPLIT4 ? 4 : 1;
-    static constexpr int MFMAS = 2 * FM * FN * PRODUCTS;  // per wave per half step
+    static constexpr int MFMAS = KK * FM * FN * PRODUCTS;  // per wave per fragment step
     static_assert(A_PLANE % (512 * NW) == 0 && B_PLANE % (512 * NW) == 0, "tile must split into 1 KB loads");
     static_assert(BN == 128 || BN == 256, "B rows of 256 or 512 bytes");
     static_assert(S == 2 || S == 3, "2 or 3 stages");
+    static_assert(KK == 1 || KK == 2, "fragment steps of 16 or 32");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(LOADS * (S - 1) <= 63, "vmcnt range");
 };
@@ -347,15 +352,25 @@ __device__ __forceinline__ void pipe64_load(const uint16_t* const (&Ap)[2], cons
     }
 }
 
-// Fragments of one 32-wide half step: half h (0 or 1) of the stage in `st`.
-template <int KIND, int BM, int BN, int WM, int WN, int S>
+// Operand fragments of one fragment step: KK 16-deep chunks.
+template <int FM, int FN, int KK>
+struct P64Frags {
+    u32x4 a[KK][FM][2];
+    u32x4 b[KK][FN][2];
+};
+
+// Fragments of fragment step h (chunks KK h .. KK h + KK - 1 of the 64-wide
+// stage in `st`).
+template <int KIND, int BM, int BN, int WM, int WN, int S, int KK>
 __device__ __forceinline__ void pipe64_read(const uint16_t* st, int h, int wm, int wn, int lane,
-                                            PipeFrags<KIND, BM, BN, WM, WN, 4>& f) {
-    using G = Pipe64Cfg<KIND, BM, BN, WM, WN, S>;
+                                            P64Frags<Pipe64Cfg<KIND, BM, BN, WM, WN, S, KK>::FM,
+                                                     Pipe64Cfg<KIND, BM, BN, WM, WN, S, KK>::FN, KK>& f) {
+    using G = Pipe64Cfg<KIND, BM, BN, WM, WN, S, KK>;
     using T = KT<KIND>;
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-        const int c = (h * 2 + kk) * 2 + (lane >> 5);  // 16-byte chunk of the 64-wide row
+    for (int kk = 0; kk < KK; ++kk) {
+        const int ch = h * KK + kk;             // 16-deep chunk of the stage
+        const int c = ch * 2 + (lane >> 5);      // 16-byte chunk of the 64-wide row
 #pragma unroll
         for (int fm = 0; fm < G::FM; ++fm) {
             const int row = wm * G::TMW + fm * 32 + (lane & 31);
@@ -369,20 +384,19 @@ __device__ __forceinline__ void pipe64_read(const uint16_t* st, int h, int wm, i
         for (int fn = 0; fn < G::FN; ++fn) {
 #pragma unroll
             for (int q = 0; q < 2; ++q)
-                f.b[kk][fn][q] = (q < T::NPB) ? read_b_tr<BN>(st, G::NPA * G::A_PLANE + q * G::B_PLANE,
-                                                              (h * 2 + kk) * 16, wn * G::TNW + fn * 32, lane)
+                f.b[kk][fn][q] = (q < T::NPB) ? read_b_tr<BN>(st, G::NPA * G::A_PLANE + q * G::B_PLANE, ch * 16,
+                                                              wn * G::TNW + fn * 32, lane)
                                               : zero4();
         }
     }
 }
 
-template <int KIND, int BM, int BN, int WM, int WN, int S>
+template <int KIND, int BM, int BN, int WM, int WN, int S, int KK>
 __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe64(Gemm16Args p, int tiles_m, int tiles_n, int group_m) {
     using T = KT<KIND>;
-    using G = Pipe64Cfg<KIND, BM, BN, WM, WN, S>;
-    using F = PipeFrags<KIND, BM, BN, WM, WN, 4>;  // same fragment shapes (FM, FN) as the 32-wide pipeline
-    static_assert(PipeCfg<KIND, BM, BN, WM, WN, 4>::FM == G::FM && PipeCfg<KIND, BM, BN, WM, WN, 4>::FN == G::FN, "");
-    constexpr int FM = G::FM, FN = G::FN, BK = G::BK;
+    using G = Pipe64Cfg<KIND, BM, BN, WM, WN, S, KK>;
+    constexpr int FM = G::FM, FN = G::FN, BK = G::BK, KSUB = G::KSUB;
+    using F = P64Frags<FM, FN, KK>;
     __shared__ __attribute__((aligned(16))) uint16_t st0[G::STAGE];
     __shared__ __attribute__((aligned(16))) uint16_t st1[G::STAGE];
     __shared__ __attribute__((aligned(16))) uint16_t st2[S == 3 ? G::STAGE : 8];
@@ -416,41 +430,50 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe64(Gemm16Args p, int 
             if constexpr (T::RR) rr[i][j] = f32x16{};
         }
 
-    // prologue: stages 0 .. S-1 in flight; wait for stage 0, read its first half
+    // prologue: stages 0 .. S-1 in flight; wait for stage 0, read its first fragments
 #pragma unroll
     for (int s = 0; s < S; ++s)
         pipe64_load<KIND, BM, BN, WM, WN, S>(Ap, Bp, lda, ldb, M, N, m0, n0, kclamp(s), stage(s), wid, lane);
     F f[2];
     wait_vmcnt<G::LOADS * (S - 1)>();
     bare_barrier();
-    pipe64_read<KIND, BM, BN, WM, WN, S>(st0, 0, wm, wn, lane, f[0]);
+    pipe64_read<KIND, BM, BN, WM, WN, S, KK>(st0, 0, wm, wn, lane, f[0]);
 
     auto mma = [&](const F& fr) {
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
+        for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
                 for (int fn = 0; fn < FN; ++fn)
                     mma_step<KIND>(fr.a[kk][fm], fr.b[kk][fn], hi[fm][fn], lo[fm][fn], rr[fm][fn]);
     };
-    // one stage step T (u = T % S, a compile-time constant inside the unrolled loop)
+    // One stage step T (u = T % S, a compile-time constant inside the
+    // unrolled loop): KSUB fragment steps; each reads the next step's
+    // fragments while its MFMAs run.  Before the last one, whose read
+    // crosses into stage T+1: wait for that stage's loads (this wave) and
+    // for this wave's reads of stage T, barrier, refill stage T's array with
+    // step T+S.  KSUB is even, so fragment step h always uses f[h & 1].
     auto step = [&](auto ucst, int64_t t) {
         constexpr int u = decltype(ucst)::value;
-        // first half: second-half fragments of T, MFMAs on the first half
-        pipe64_read<KIND, BM, BN, WM, WN, S>(stage(u), 1, wm, wn, lane, f[1]);
-        mma(f[0]);
-        pipe_interleave<G::READS, G::MFMAS>();
-        __builtin_amdgcn_sched_barrier(0);
-        // second half: stage T+1 landed (this wave) and T's reads returned; barrier
-        wait_vmcnt<G::LOADS * (S - 2)>();
-        wait_lgkm0();
-        bare_barrier();
-        pipe64_load<KIND, BM, BN, WM, WN, S>(Ap, Bp, lda, ldb, M, N, m0, n0, kclamp(t + S), stage(u), wid, lane);
-        pipe64_read<KIND, BM, BN, WM, WN, S>(stage((u + 1) % S), 0, wm, wn, lane, f[0]);
-        mma(f[1]);
-        pipe_interleave_loads<G::READS, G::LOADS, G::MFMAS>();
-        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int h = 0; h < KSUB; ++h) {
+            if (h == KSUB - 1) {
+                wait_vmcnt<G::LOADS * (S - 2)>();
+                wait_lgkm0();
+                bare_barrier();
+                pipe64_load<KIND, BM, BN, WM, WN, S>(Ap, Bp, lda, ldb, M, N, m0, n0, kclamp(t + S), stage(u), wid,
+                                                     lane);
+                pipe64_read<KIND, BM, BN, WM, WN, S, KK>(stage((u + 1) % S), 0, wm, wn, lane, f[(h + 1) & 1]);
+                mma(f[h & 1]);
+                pipe_interleave_loads<G::READS, G::LOADS, G::MFMAS>();
+            } else {
+                pipe64_read<KIND, BM, BN, WM, WN, S, KK>(stage(u), h + 1, wm, wn, lane, f[(h + 1) & 1]);
+                mma(f[h & 1]);
+                pipe_interleave<G::READS, G::MFMAS>();
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
     };
     const int64_t KFULL = KTN - KTN % S;
     for (int64_t t0 = 0; t0 < KFULL; t0 += S) {
