@@ -31,7 +31,8 @@ struct Cfg16 {
     int fast;    // 0: tile16 kernel; 1: fast kernel, loads via VGPRs; 2: fast kernel, loads straight to LDS;
                  // 3: pipelined kernel, 4 stages; 5: fast kernel with BK = 32, loads straight to LDS;
                  // 6: as 5 with a register budget for 2 (or 4) wavefronts per SIMD;
-                 // 7: pipelined kernel with 64-wide LDS stages (2 or 3)
+                 // 7: pipelined kernel with 64-wide LDS stages (2 or 3); 8: the
+                 //    same with the LDS reads spread evenly over the MFMAs
     int wm, wn;  // wavefront grid of the fast kernel
 };
 
@@ -62,13 +63,13 @@ static int launch_pipe(const Gemm16Args& a, int64_t batch, int group_m, hipStrea
     return MFG_OK;
 }
 
-template <int KIND, int BM, int BN, int WM, int WN, int S, int KK = 2>
+template <int KIND, int BM, int BN, int WM, int WN, int S, int KK = 2, bool EVEN = false>
 static int launch_pipe64(const Gemm16Args& a, int64_t batch, int group_m, hipStream_t s) {
     using G = Pipe64Cfg<KIND, BM, BN, WM, WN, S, KK>;
     const int tiles_m = (int)cdiv(a.M, BM), tiles_n = (int)cdiv(a.N, BN);
     dim3 grid(tiles_m * tiles_n, (unsigned)batch, 1);
-    hipLaunchKernelGGL((gemm16_pipe64<KIND, BM, BN, WM, WN, S, KK>), grid, dim3(G::NT), 0, s, a, tiles_m, tiles_n,
-                       group_m);
+    hipLaunchKernelGGL((gemm16_pipe64<KIND, BM, BN, WM, WN, S, KK, EVEN>), grid, dim3(G::NT), 0, s, a, tiles_m,
+                       tiles_n, group_m);
     MFG_LAUNCH_CHECK();
     return MFG_OK;
 }
@@ -134,6 +135,8 @@ static const Cfg16 kCfgPlain[] = {
     {"q128x256k64s3w2x2g8", 128, 256, 8, 7, 2, 2},
     {"q256x128k64s3w2x2g8", 256, 128, 8, 7, 2, 2},
     {"q128x128k64s3w2x2g8", 128, 128, 8, 7, 2, 2},
+    {"q256x256k64s2w2x2g8e", 256, 256, 8, 8, 2, 2},
+    {"q256x128k64s3w2x2g8e", 256, 128, 8, 8, 2, 2},
 };
 static const Cfg16 kCfgSplit[] = {
     {"simple32", 0, 0, 0},
@@ -144,6 +147,7 @@ static const Cfg16 kCfgSplit[] = {
     {"f256x128k32w2x2g8dma", 256, 128, 8, 5, 2, 2},
     {"f128x128k64w2x2g8dma", 128, 128, 8, 2, 2, 2},
     {"q128x128k64s2w2x2g8", 128, 128, 8, 7, 2, 2},
+    {"q128x128k64s2w2x2g8e", 128, 128, 8, 8, 2, 2},
 };
 static const Cfg16 kCfgSplit4[] = {
     {"simple32", 0, 0, 0},
@@ -151,6 +155,7 @@ static const Cfg16 kCfgSplit4[] = {
     {"t64x64k32w2x2g8", 64, 64, 8},
     {"f128x128k32w2x2g8dma", 128, 128, 8, 5, 2, 2},
     {"q128x128k64s2w2x2g8", 128, 128, 8, 7, 2, 2},
+    {"q128x128k64s2w2x2g8e", 128, 128, 8, 8, 2, 2},
 };
 
 static const Cfg16* menu(int kind, int* n) {
@@ -208,6 +213,16 @@ static int launch_kind(int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok,
             if (c.bm == 128 && c.bn == 128) return launch_fast<KIND, 128, 128, 2, 2, true, 32>(a, batch, c.group_m, s);
             if constexpr (KIND != K_SPLIT4)
                 if (c.bm == 256 && c.bn == 128) return launch_fast<KIND, 256, 128, 2, 2, true, 32>(a, batch, c.group_m, s);
+        }
+        return MFG_ERR_INTERNAL;
+    }
+    if (c.fast == 8) {  // even read interleave
+        if (!fast_ok(a, vec_ok)) return MFG_ERR_UNSUPPORTED;
+        if constexpr (KIND == K_F16 || KIND == K_BF16) {
+            if (c.bm == 256 && c.bn == 256) return launch_pipe64<KIND, 256, 256, 2, 2, 2, 2, true>(a, batch, c.group_m, s);
+            if (c.bm == 256 && c.bn == 128) return launch_pipe64<KIND, 256, 128, 2, 2, 3, 2, true>(a, batch, c.group_m, s);
+        } else {
+            if (c.bm == 128 && c.bn == 128) return launch_pipe64<KIND, 128, 128, 2, 2, 2, 2, true>(a, batch, c.group_m, s);
         }
         return MFG_ERR_INTERNAL;
     }

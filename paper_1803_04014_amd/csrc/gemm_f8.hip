@@ -138,7 +138,7 @@ __device__ __forceinline__ void f8_read(const uint8_t* st, int h, int wm, int wn
         f.b[fn] = f8_read_row(st, G::A_PLANE, wn * G::TNW + fn * 32 + (lane & 31), h, lane);
 }
 
-template <int BM, int BN, int WM, int WN, int S>
+template <int BM, int BN, int WM, int WN, int S, bool EVEN = false>
 __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int tiles_m, int tiles_n, int group_m) {
     using G = F8Cfg<BM, BN, WM, WN, S>;
     constexpr int FM = G::FM, FN = G::FN, BK = G::BK;
@@ -196,7 +196,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
         scale_codes(t + 1, na, nb);  // next stage's scales, early
         f8_read<BM, BN, WM, WN, S>(stage(u), 1, wm, wn, lane, f[1]);
         mma(f[0], ca, cb);
-        pipe_interleave<G::READS, G::MFMAS>();
+        if constexpr (EVEN) pipe_interleave_even<G::READS, G::MFMAS>();
+        else pipe_interleave<G::READS, G::MFMAS>();
         __builtin_amdgcn_sched_barrier(0);
         wait_vmcnt<G::LOADS * (S - 2)>();
         wait_lgkm0();
@@ -204,7 +205,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
         f8_load<BM, BN, WM, WN, S>(p.A, p.Bt, p.lda, p.ldbt, M, N, m0, n0, kclamp(t + S), stage(u), wid, lane);
         f8_read<BM, BN, WM, WN, S>(stage((u + 1) % S), 0, wm, wn, lane, f[0]);
         mma(f[1], ca, cb);
-        pipe_interleave<G::READS, G::MFMAS>();
+        if constexpr (EVEN) pipe_interleave_even<G::READS, G::MFMAS>();
+        else pipe_interleave<G::READS, G::MFMAS>();
         __builtin_amdgcn_sched_barrier(0);
         ca = na, cb = nb;
     };
@@ -234,15 +236,16 @@ static const CfgF8 kCfgF8[] = {
     {"p256x256k128s2w2x2g8", 256, 256, 2, 2, 2, 8},
     {"p128x128k128s3w2x2g8", 128, 128, 2, 2, 3, 8},
     {"p256x128k128s2w2x2g8", 256, 128, 2, 2, 2, 8},
+    {"p256x256k128s2w2x2g8e", 256, 256, 2, 2, 2, 8},
 };
 constexpr int kNumF8 = (int)(sizeof(kCfgF8) / sizeof(kCfgF8[0]));
 
-template <int BM, int BN, int WM, int WN, int S>
+template <int BM, int BN, int WM, int WN, int S, bool EVEN = false>
 static int launch_f8_pipe(const GemmF8Args& a, int group_m, hipStream_t s) {
     using G = F8Cfg<BM, BN, WM, WN, S>;
     const int tiles_m = (int)cdiv(a.M, BM), tiles_n = (int)cdiv(a.N, BN);
-    hipLaunchKernelGGL((gemmf8_pipe<BM, BN, WM, WN, S>), dim3(tiles_m * tiles_n), dim3(G::NT), 0, s, a, tiles_m,
-                       tiles_n, group_m);
+    hipLaunchKernelGGL((gemmf8_pipe<BM, BN, WM, WN, S, EVEN>), dim3(tiles_m * tiles_n), dim3(G::NT), 0, s, a,
+                       tiles_m, tiles_n, group_m);
     MFG_LAUNCH_CHECK();
     return MFG_OK;
 }
@@ -263,6 +266,7 @@ int launch_gemm_f8(int cfg, const GemmF8Args& a, bool vec_ok, hipStream_t s) {
     const bool bt_ok = a.Bt != nullptr && ((uintptr_t)a.Bt % 16) == 0 && a.ldbt % 16 == 0;
     if (!vec_ok || !bt_ok || a.K % 128 != 0 || a.M < 1 || a.N < 1) return MFG_ERR_UNSUPPORTED;
     const CfgF8& c = kCfgF8[cfg];
+    if (cfg == 4) return launch_f8_pipe<256, 256, 2, 2, 2, true>(a, c.group_m, s);
     if (c.bm == 256 && c.bn == 256) return launch_f8_pipe<256, 256, 2, 2, 2>(a, c.group_m, s);
     if (c.bm == 128 && c.bn == 128) return launch_f8_pipe<128, 128, 2, 2, 3>(a, c.group_m, s);
     if (c.bm == 256 && c.bn == 128) return launch_f8_pipe<256, 128, 2, 2, 2>(a, c.group_m, s);

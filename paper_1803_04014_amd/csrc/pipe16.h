@@ -170,6 +170,28 @@ __device__ __forceinline__ void pipe_interleave() {
     }
 }
 
+// Even interleave: the LDS reads spread over all MFMAs of the step (one read
+// after MFMA i when floor((i+1) READS / MFMAS) grows), instead of one after
+// each of the first READS MFMAs.
+template <int READS, int MFMAS>
+__device__ __forceinline__ void pipe_interleave_even() {
+#pragma unroll
+    for (int i = 0; i < MFMAS; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if ((i + 1) * READS / MFMAS > i * READS / MFMAS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+}
+
+template <int READS, int LOADS, int MFMAS>
+__device__ __forceinline__ void pipe_interleave_loads_even() {
+#pragma unroll
+    for (int i = 0; i < MFMAS; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if ((i + 1) * READS / MFMAS > i * READS / MFMAS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        if ((i + 1) * LOADS / MFMAS > i * LOADS / MFMAS) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+}
+
 // Interleave of the step that also issues the next stage's global->LDS
 // loads: MFMA, LDS read, global load, ... while each kind lasts.  Issued in
 // one burst, the loads back up in the texture-address unit and hold the
@@ -391,7 +413,7 @@ __device__ __forceinline__ void pipe64_read(const uint16_t* st, int h, int wm, i
     }
 }
 
-template <int KIND, int BM, int BN, int WM, int WN, int S, int KK>
+template <int KIND, int BM, int BN, int WM, int WN, int S, int KK, bool EVEN = false>
 __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe64(Gemm16Args p, int tiles_m, int tiles_n, int group_m) {
     using T = KT<KIND>;
     using G = Pipe64Cfg<KIND, BM, BN, WM, WN, S, KK>;
@@ -466,11 +488,13 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe64(Gemm16Args p, int 
                                                      lane);
                 pipe64_read<KIND, BM, BN, WM, WN, S, KK>(stage((u + 1) % S), 0, wm, wn, lane, f[(h + 1) & 1]);
                 mma(f[h & 1]);
-                pipe_interleave_loads<G::READS, G::LOADS, G::MFMAS>();
+                if constexpr (EVEN) pipe_interleave_loads_even<G::READS, G::LOADS, G::MFMAS>();
+                else pipe_interleave_loads<G::READS, G::LOADS, G::MFMAS>();
             } else {
                 pipe64_read<KIND, BM, BN, WM, WN, S, KK>(stage(u), h + 1, wm, wn, lane, f[(h + 1) & 1]);
                 mma(f[h & 1]);
-                pipe_interleave<G::READS, G::MFMAS>();
+                if constexpr (EVEN) pipe_interleave_even<G::READS, G::MFMAS>();
+                else pipe_interleave<G::READS, G::MFMAS>();
             }
             __builtin_amdgcn_sched_barrier(0);
         }

@@ -21,12 +21,12 @@ int pick_config16(int kind, int64_t M, int64_t N, int64_t K, bool vec_ok) {
     const int64_t t128 = cdiv(M, 128) * cdiv(N, 128);
     const bool big = M >= 64 && N >= 64;
     if (kind == K_F16 || kind == K_BF16) {
-        if (fast && t256 >= 256) return 24;  // q256x256k64s2w2x2g8
+        if (fast && t256 >= 256) return 29;  // q256x256k64s2w2x2g8e
         if (fast && t128 >= 64) return 28;   // q128x128k64s3w2x2g8
         return big ? 6 : 0;                  // t64x64k64w2x2g8
     }
     if (kind == K_SPLIT4) {
-        if (fast && t128 >= 256) return 4;   // q128x128k64s2w2x2g8
+        if (fast && t128 >= 256) return 5;   // q128x128k64s2w2x2g8e
         if (fast && t128 >= 64) return 3;    // f128x128k32w2x2g8dma
         return big ? 2 : 0;                  // t64x64k32w2x2g8
     }
@@ -39,7 +39,7 @@ int pick_config16(int kind, int64_t M, int64_t N, int64_t K, bool vec_ok) {
 // square N = 1024 .. 8192), else the simple kernel.
 int pick_config_f8(int64_t M, int64_t N, int64_t K, bool vec_ok) {
     if (!vec_ok || K % 128 != 0 || M < 1 || N < 1) return 0;
-    if (cdiv(M, 256) * cdiv(N, 256) >= 512) return 1;  // p256x256
+    if (cdiv(M, 256) * cdiv(N, 256) >= 512) return 4;  // p256x256k128s2w2x2g8e
     if (cdiv(M, 256) * cdiv(N, 128) >= 256) return 3;  // p256x128
     if (cdiv(M, 128) * cdiv(N, 128) >= 64) return 2;   // p128x128
     return 0;
