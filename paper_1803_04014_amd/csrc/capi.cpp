@@ -60,7 +60,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         a.M = M, a.N = N, a.K = K;
         a.A = static_cast<const float*>(A), a.B = static_cast<const float*>(B), a.C = C;
         a.lda = lda, a.ldb = ldb, a.ldc = ldc, a.alpha = alpha, a.beta = beta;
-        const bool vec = al16(A) && al16(B) && lda % 4 == 0 && ldb % 4 == 0;
+        const bool vec = al16(A) && al16(B) && lda % 4 == 0 && ldb % 4 == 0 && buffer_ldc_ok(ldc);
         int cfg = config;
         if (cfg < 0) {
             const int t = tuned_lookup(m, M, N, K);
@@ -85,7 +85,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
             a.B = static_cast<const uint8_t*>(B), a.ldb = ldb;
             a.sa = reinterpret_cast<const float*>(a.A + mfg_fp8_scale_offset(M, lda));
             a.sb = reinterpret_cast<const float*>(a.B + mfg_fp8_scale_offset(K, ldb));
-            const bool vec = al16(A) && lda % 16 == 0;
+            const bool vec = al16(A) && lda % 16 == 0 && buffer_ldc_ok(ldc);
             const int cfg = choose(vec);
             if (cfg < 0 || cfg >= num_configs_f8()) return MFG_ERR_INVALID_ARG;
             if (!f8_config_needs_bt(cfg)) return launch_gemm_f8(cfg, a, vec, s);
@@ -97,7 +97,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
             a.Bt = bt, a.ldbt = ldt;
             return launch_gemm_f8(cfg, a, vec, s);
         }
-        const int cfg = choose(true);
+        const int cfg = choose(buffer_ldc_ok(ldc));
         if (cfg < 0 || cfg >= num_configs_f8()) return MFG_ERR_INVALID_ARG;
         const bool need_bt = f8_config_needs_bt(cfg);
         if (need_bt && K % 128 != 0) return MFG_ERR_UNSUPPORTED;
@@ -118,7 +118,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
             if ((st = launch_transpose_b8(K, N, qb, ldn, bt, ldt, s)) != MFG_OK) return st;
             a.Bt = bt, a.ldbt = ldt;
         }
-        return launch_gemm_f8(cfg, a, true, s);
+        return launch_gemm_f8(cfg, a, buffer_ldc_ok(ldc), s);
     }
 
     // 16-bit modes
@@ -131,7 +131,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         a.A[0] = pa, a.A[1] = npa(m) == 2 ? pa + M * lda : nullptr;
         a.B[0] = pb, a.B[1] = npb(m) == 2 ? pb + K * ldb : nullptr;
         a.lda = lda, a.ldb = ldb;
-        const bool vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0;
+        const bool vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && buffer_ldc_ok(ldc);
         return launch_gemm16(kind, choose16(m, config, M, N, K, vec), a, 1, vec, s);
     }
     const int64_t ldk = up(K, 8), ldn = up(N, 8);
@@ -147,7 +147,8 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     if ((st = convert16(m, M, K, static_cast<const float*>(A), lda, a0, a1, ldk, npa(m) == 2, s)) != MFG_OK) return st;
     if ((st = convert16(m, K, N, static_cast<const float*>(B), ldb, b0, b1, ldn, npb(m) == 2, s)) != MFG_OK) return st;
     a.A[0] = a0, a.A[1] = a1, a.B[0] = b0, a.B[1] = b1, a.lda = ldk, a.ldb = ldn;
-    return launch_gemm16(kind, choose16(m, config, M, N, K, true), a, 1, true, s);
+    const bool vec = buffer_ldc_ok(ldc);  // workspace planes: aligned, ld a multiple of 8
+    return launch_gemm16(kind, choose16(m, config, M, N, K, vec), a, 1, vec, s);
 }
 
 }  // namespace mfg
@@ -226,7 +227,8 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
         GemmF32Args a{};
         a.M = M, a.N = N, a.K = K, a.ldc = ldc, a.alpha = alpha, a.beta = beta;
         a.lda = lda, a.ldb = ldb, a.sA = strideA, a.sB = strideB, a.sC = strideC;
-        const bool vec = al16(A) && al16(B) && lda % 4 == 0 && ldb % 4 == 0 && strideA % 4 == 0 && strideB % 4 == 0;
+        const bool vec = al16(A) && al16(B) && lda % 4 == 0 && ldb % 4 == 0 && strideA % 4 == 0 && strideB % 4 == 0 &&
+                         buffer_ldc_ok(ldc);
         const int cfg = (M >= 128 && N >= 128 && vec) ? 1 : 0;
         for (int64_t b0 = 0; b0 < count; b0 += 65535) {
             a.A = static_cast<const float*>(A) + b0 * strideA;
@@ -246,7 +248,8 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
     if (!split_mode) {
         a.A[0] = static_cast<const uint16_t*>(A), a.B[0] = static_cast<const uint16_t*>(B);
         a.lda = lda, a.ldb = ldb, a.sA = strideA, a.sB = strideB;
-        vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && strideA % 8 == 0 && strideB % 8 == 0;
+        vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && strideA % 8 == 0 && strideB % 8 == 0 &&
+              buffer_ldc_ok(ldc);
     } else {
         // FP32 operands split into the workspace, packed per batch entry.
         const int64_t ldk = up(K, 8), ldn = up(N, 8);
@@ -284,7 +287,7 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
         }
         a.A[0] = a0, a.A[1] = a1, a.B[0] = b0, a.B[1] = b1;
         a.lda = ldk, a.ldb = ldn, a.sA = pa, a.sB = pb;
-        vec = true;
+        vec = buffer_ldc_ok(ldc);
     }
     if (M <= 32 && N <= 32) return launch_batched_small(kind, a, count, vec, device_cu_count(), s);
     const int cfg = vec ? pick_config16(kind, M, N, K, vec) : 0;

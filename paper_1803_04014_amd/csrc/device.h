@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "internal.h"
+
 namespace mfg {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -45,22 +47,35 @@ __device__ __forceinline__ f32x16 mma_32x32x64_e4m3(i32x8 a, i32x8 b, f32x16 c, 
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
 }
 
+// A value the caller knows to be the same in every lane, made visibly so
+// (scalar registers) for the compiler.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Buffer resource for raw (untyped) accesses to `bytes` bytes from `base`:
+// loads at or beyond the end return 0 and stores there are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
 // Row of the 32x32 MFMA output held in element i of lane l.
 __device__ __forceinline__ int mfma_out_row(int i, int lane) {
     return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
 }
 
-// Epilogue of one row of FN 32x32 accumulator blocks of a wavefront: block
-// fn covers rows rbase + mfma_out_row(i, lane) and column cbase + 32 fn +
-// lane % 32, value val(fn, i).  C = alpha * v when beta == 0 (C is not
-// read), else fma(alpha, v, beta * C).  Every C read of the row of blocks is
-// issued before any of its writes (reads go to clamped, always valid
-// addresses), so the row costs one memory latency rather than one per
-// element: stores and loads to C could otherwise not be reordered.  C may
-// be a generic or a global (address space 1) pointer.
+// Epilogue of one row of FN 32x32 accumulator blocks of a wavefront, any
+// leading dimension: block fn covers rows rbase + mfma_out_row(i, lane) and
+// column cbase + 32 fn + lane % 32, value val(fn, i).  C = alpha * v when
+// beta == 0 (C is not read), else fma(alpha, v, beta * C).  Every C read of
+// the row of blocks is issued before any of its writes (reads go to
+// clamped, always valid addresses), so the row costs one memory latency
+// rather than one per element.
 template <int FN, class Val, class CPtr>
-__device__ __forceinline__ void store_blocks(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
-                                             int64_t cbase, int lane, float alpha, float beta, Val val) {
+__device__ __forceinline__ void store_blocks_wide(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
+                                                  int64_t cbase, int lane, float alpha, float beta, Val val) {
     const int64_t col0 = cbase + (lane & 31);
     if (beta == 0.0f) {
 #pragma unroll
@@ -93,6 +108,119 @@ __device__ __forceinline__ void store_blocks(CPtr C, int64_t ldc, int64_t M, int
             const int64_t row = rbase + mfma_out_row(i, lane);
             if (row < M && col < N) C[row * ldc + col] = __builtin_fmaf(alpha, val(fn, i), beta * c[fn][i]);
         }
+    }
+}
+
+// The same epilogue with buffer instructions (ldc < kBufferLdcLimit, the
+// bound of 32-bit offsets over a 32-row block; for FN = 1 any ldc).  rbase and cbase are the same in every lane.  One buffer
+// resource covers the row of blocks; element i of a lane sits at a per-lane
+// byte offset (four of them, one per i % 4) plus a scalar offset of
+// 8 (i / 4) rows, so each value costs one memory instruction and no address
+// arithmetic.  Blocks that cross the edge of C give the elements outside it
+// an offset beyond the resource's range: the hardware drops those stores
+// and returns 0 for those loads, so there are no branches.  All loads of
+// the row are issued before its stores.
+template <int FN, class Val, class CPtr>
+__device__ __forceinline__ void store_blocks(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
+                                             int64_t cbase, int lane, float alpha, float beta, Val val) {
+    if constexpr (FN == 1) {
+        if (ldc >= kBufferLdcLimit) {
+            store_blocks_wide<1>(C, ldc, M, N, rbase, cbase, lane, alpha, beta, val);
+            return;
+        }
+    }
+    const int64_t rb = uniform64(rbase), cb = uniform64(cbase);
+    const __amdgpu_buffer_rsrc_t rs =
+        buffer_rsrc((float*)C + rb * ldc + cb, (uint32_t)((31 * ldc + 32 * FN) * 4));
+    const int l4 = (int)ldc * 4;
+    int vo[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) vo[j] = (4 * (lane >> 5) + j) * l4 + (lane & 31) * 4;
+    int off[FN][16];
+    if (rb + 32 <= M && cb + 32 * FN <= N) {
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) off[fn][i] = vo[i & 3] + fn * 128;
+    } else {
+        constexpr int kOut = INT32_MIN;  // 2^31 as an unsigned offset: beyond any resource here
+        const int64_t rows = M - rb, cols = N - cb;
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                off[fn][i] = (mfma_out_row(i, lane) < rows && (lane & 31) + 32 * fn < cols) ? vo[i & 3] + fn * 128
+                                                                                             : kOut;
+    }
+    if (beta == 0.0f) {
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, alpha * val(fn, i)), rs,
+                                                      off[fn][i], 8 * (i >> 2) * l4, 0);
+        return;
+    }
+    float c[FN][16];
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            c[fn][i] = __builtin_bit_cast(float,
+                                          __builtin_amdgcn_raw_buffer_load_b32(rs, off[fn][i], 8 * (i >> 2) * l4, 0));
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            __builtin_amdgcn_raw_buffer_store_b32(
+                __builtin_bit_cast(uint32_t, __builtin_fmaf(alpha, val(fn, i), beta * c[fn][i])), rs, off[fn][i],
+                8 * (i >> 2) * l4, 0);
+}
+
+// Epilogue of a wavefront's FM x FN accumulator blocks: rows rbase + 32 fm,
+// columns cbase + 32 fn, value val(fm, fn, i).  When beta != 0 and the
+// whole FM x FN tile lies inside C, the C reads of block row fm + 1 are
+// issued before the writes of row fm (two rows of C values in registers),
+// so the tile exposes one read latency instead of one per row; otherwise
+// it is store_blocks row by row.
+template <int FM, int FN, class Val, class CPtr>
+__device__ __forceinline__ void store_tile(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase, int64_t cbase,
+                                           int lane, float alpha, float beta, Val val) {
+    const int64_t rb = uniform64(rbase), cb = uniform64(cbase);
+    if (FM == 1 || beta == 0.0f || ldc >= kBufferLdcLimit || rb + 32 * FM > M || cb + 32 * FN > N) {
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+            store_blocks<FN>(C, ldc, M, N, rb + 32 * fm, cb, lane, alpha, beta,
+                             [&](int fn, int i) { return val(fm, fn, i); });
+        return;
+    }
+    const int l4 = (int)ldc * 4;
+    const uint32_t extent = (uint32_t)((31 * ldc + 32 * FN) * 4);
+    int vo[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) vo[j] = (4 * (lane >> 5) + j) * l4 + (lane & 31) * 4;
+    float c[2][FN][16];
+    auto load = [&](int fm, float (&d)[FN][16]) {
+        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc((float*)C + (rb + 32 * fm) * ldc + cb, extent);
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                d[fn][i] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo[i & 3] + fn * 128, 8 * (i >> 2) * l4, 0));
+    };
+    load(0, c[0]);
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+        if (fm + 1 < FM) load(fm + 1, c[(fm + 1) & 1]);
+        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc((float*)C + (rb + 32 * fm) * ldc + cb, extent);
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                __builtin_amdgcn_raw_buffer_store_b32(
+                    __builtin_bit_cast(uint32_t, __builtin_fmaf(alpha, val(fm, fn, i), beta * c[fm & 1][fn][i])), rs,
+                    vo[i & 3] + fn * 128, 8 * (i >> 2) * l4, 0);
     }
 }
 

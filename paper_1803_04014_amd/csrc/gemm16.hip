@@ -188,7 +188,7 @@ static int launch_kind(int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok,
     int n;
     const Cfg16* m = menu(KIND, &n);
     if (cfg < 0 || cfg >= n) return MFG_ERR_INVALID_ARG;
-    if (cfg != 0 && !vec_ok) return MFG_ERR_UNSUPPORTED;
+    if (cfg != 0 && (!vec_ok || !buffer_ldc_ok(a.ldc))) return MFG_ERR_UNSUPPORTED;
     const Cfg16& c = m[cfg];
     if (c.bm == 0) return launch_simple<KIND>(a, batch, vec_ok, s);
     if (c.fast == 6) {  // BK = 32 with a higher occupancy target

@@ -172,10 +172,8 @@ __global__ __launch_bounds__(256) void gemmf32_tiled(GemmF32Args p, int tiles_m,
             __syncthreads();
         }
     }
-#pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-        store_blocks<FN>(C, p.ldc, M, N, m0 + wm * TMW + fm * 32, n0 + wn * TNW, lane, p.alpha, p.beta,
-                         [&](int fn, int i) { return acc[fm][fn][i]; });
+    store_tile<FM, FN>(C, p.ldc, M, N, m0 + wm * TMW, n0 + wn * TNW, lane, p.alpha, p.beta,
+                       [&](int fm, int fn, int i) { return acc[fm][fn][i]; });
 }
 
 struct CfgF32 {
@@ -209,7 +207,7 @@ static int launch_f32_tiled(const GemmF32Args& a, int64_t batch, int group_m, hi
 
 int launch_gemm_f32(int cfg, const GemmF32Args& a, int64_t batch, bool vec_ok, hipStream_t s) {
     if (cfg < 0 || cfg >= num_configs_f32()) return MFG_ERR_INVALID_ARG;
-    if (cfg != 0 && !vec_ok) return MFG_ERR_UNSUPPORTED;
+    if (cfg != 0 && (!vec_ok || !buffer_ldc_ok(a.ldc))) return MFG_ERR_UNSUPPORTED;
     const CfgF32& c = kCfgF32[cfg];
     if (c.bm == 0) {
         dim3 grid((unsigned)cdiv(a.N, 32), (unsigned)cdiv(a.M, 32), (unsigned)batch);

@@ -221,10 +221,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
         if (KFULL + 1 < KTN) step(std::integral_constant<int, 1>{}, KFULL + 1);
 
     wait_vmcnt<0>();
-#pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-        store_blocks<FN>(p.C, p.ldc, M, N, m0 + wm * G::TMW + fm * 32, n0 + wn * G::TNW, lane, p.alpha, p.beta,
-                         [&](int fn, int i) { return acc[fm][fn][i]; });
+    store_tile<FM, FN>(p.C, p.ldc, M, N, m0 + wm * G::TMW, n0 + wn * G::TNW, lane, p.alpha, p.beta,
+                       [&](int fm, int fn, int i) { return acc[fm][fn][i]; });
 }
 
 struct CfgF8 {
@@ -264,7 +262,7 @@ int launch_gemm_f8(int cfg, const GemmF8Args& a, bool vec_ok, hipStream_t s) {
         return MFG_OK;
     }
     const bool bt_ok = a.Bt != nullptr && ((uintptr_t)a.Bt % 16) == 0 && a.ldbt % 16 == 0;
-    if (!vec_ok || !bt_ok || a.K % 128 != 0 || a.M < 1 || a.N < 1) return MFG_ERR_UNSUPPORTED;
+    if (!vec_ok || !bt_ok || a.K % 128 != 0 || a.M < 1 || a.N < 1 || !buffer_ldc_ok(a.ldc)) return MFG_ERR_UNSUPPORTED;
     const CfgF8& c = kCfgF8[cfg];
     if (cfg == 4) return launch_f8_pipe<256, 256, 2, 2, 2, true>(a, c.group_m, s);
     if (c.bm == 256 && c.bn == 256) return launch_f8_pipe<256, 256, 2, 2, 2>(a, c.group_m, s);

@@ -118,6 +118,12 @@ struct GroupedDesc {  // one problem, device resident
     int32_t vec;  // 1: 16-byte aligned rows (LDS-staged tile), 0: per-wave tile
     int32_t pad;
 };
+// Tiled kernels address C with 32-bit buffer offsets within a 32-row block:
+// ldc must stay below this bound for them; larger ldc uses the simple
+// kernels (single 32 x 32 blocks, 64-bit addressing).
+constexpr int64_t kBufferLdcLimit = int64_t(1) << 24;
+inline bool buffer_ldc_ok(int64_t ldc) { return ldc < kBufferLdcLimit; }
+
 constexpr int kGroupedTile = 32;  // output tile of a grouped work item (one wavefront)
 struct GroupedWork {  // one kGroupedTile x kGroupedTile output tile of one problem
     int32_t prob, tm, tn, pad;

@@ -283,10 +283,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe(Gemm16Args p, int ti
     if (KFULL + 2 < KTN) step(std::integral_constant<int, 2>{}, KFULL + 2);
 
     wait_vmcnt<0>();  // no global->LDS load may outlive the workgroup's LDS
-#pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-        store_blocks<FN>(C, p.ldc, M, N, m0 + wm * G::TMW + fm * 32, n0 + wn * G::TNW, lane, p.alpha, p.beta,
-                         [&](int fn, int i) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], i); });
+    store_tile<FM, FN>(C, p.ldc, M, N, m0 + wm * G::TMW, n0 + wn * G::TNW, lane, p.alpha, p.beta,
+                       [&](int fm, int fn, int i) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], i); });
 }
 
 
@@ -510,10 +508,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe64(Gemm16Args p, int 
         if (KFULL + 1 < KTN) step(std::integral_constant<int, 1>{}, KFULL + 1);
 
     wait_vmcnt<0>();  // no global->LDS load may outlive the workgroup's LDS
-#pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-        store_blocks<FN>(C, p.ldc, M, N, m0 + wm * G::TMW + fm * 32, n0 + wn * G::TNW, lane, p.alpha, p.beta,
-                         [&](int fn, int i) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], i); });
+    store_tile<FM, FN>(C, p.ldc, M, N, m0 + wm * G::TMW, n0 + wn * G::TNW, lane, p.alpha, p.beta,
+                       [&](int fm, int fn, int i) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], i); });
 }
 
 }  // namespace mfg

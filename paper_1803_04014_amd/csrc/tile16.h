@@ -339,10 +339,8 @@ __device__ __forceinline__ void tile_gemm(const uint16_t* const (&Ap)[2], const 
         }
     }
 
-#pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-        store_blocks<FN>(C, ldc, M, N, m0 + wm * G::TMW + fm * 32, n0 + wn * G::TNW, lane, alpha, beta,
-                         [&](int fn, int i) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], i); });
+    store_tile<FM, FN>(C, ldc, M, N, m0 + wm * G::TMW, n0 + wn * G::TNW, lane, alpha, beta,
+                       [&](int fm, int fn, int i) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], i); });
 }
 
 template <int KIND, int BM, int BN, int BK, int WM, int WN>
