@@ -183,3 +183,32 @@ def test_run_to_run_bitwise(mode):
     A, B, C0 = workloads.normal(12, [(512, 512), (512, 512), (512, 512)])
     a, b = (run_gemm(mode, A, B, C0, 1.0, 1.0) for _ in range(2))
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+# ------------------------------------------- leading dimension of 2^24 and up
+def test_huge_leading_dimension_of_c():
+    """ldc >= 2^24: the tiled kernels address a 32-row block of C with 32-bit
+    offsets, so such C runs on the simple kernels (an explicit tiled
+    configuration reports MFG_ERR_UNSUPPORTED) and the grouped kernel takes
+    its 64-bit path; results stay within the parity bar."""
+    M, N, K = 40, 72, 128
+    ldc = (1 << 24) + 16
+    A, B, C0 = workloads.uniform(13, [(M, K), (K, N), (M, N)])
+    buf = torch.zeros((M - 1) * ldc + N, dtype=torch.float32, device=DEV)
+    C = buf.as_strided((M, N), (ldc, 1))
+    for mode in ("f16", "f32", "fp8"):
+        C.copy_(dev(C0))
+        mfg.gemm(dev(A), dev(B), C, 1.0, 1.0, mode=mode)
+        assert_parity(host(C.contiguous()), oracle.reference(mode, A, B, 1.0, 1.0, C0), f"{mode} ldc=2^24+16")
+        tiled = next(c for c in range(1, mfg.num_configs(mode)) if mfg.config_name(mode, c)[0] in "tfpq")
+        with pytest.raises(mfg.MfgError) as e:
+            mfg.gemm(dev(A), dev(B), C, 1.0, 1.0, mode=mode, config=tiled)
+        assert e.value.status == mfg.capi.MFG_ERR_UNSUPPORTED
+    dA, dB = dev(A).half(), dev(B).half()
+    C.copy_(dev(C0))
+    plan = mfg.GroupedPlan([(dA, dB, C)], mode="f16")
+    plan.run(1.0, 1.0)
+    ref = oracle.reference("f32", host(dA.float()), host(dB.float()), 1.0, 1.0, C0)
+    assert_parity(host(C.contiguous()), ref, "grouped f16 ldc=2^24+16", mode="f16")
+    plan.close()
+    del C, buf
