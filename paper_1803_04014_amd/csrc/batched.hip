@@ -13,12 +13,14 @@
 //     read back transposed (ds_read_b64_tr_b16), and the 32 x 32 result goes
 //     through LDS so that C is read and written in 16-byte row pieces.
 //   gemm16_grouped : thousands of GEMMs of different shapes in one
-//     persistent launch.  The work list holds one entry per 32x32 output
-//     tile of every problem (ordered by decreasing K, the tile's cost);
-//     wavefronts take entries with a static grid stride.
+//     persistent launch.  The work list holds one self-contained record per
+//     32x32 output tile of every problem (ordered by decreasing K, the
+//     tile's cost); wavefronts take records with a static grid stride and
+//     prefetch records and operand blocks across item boundaries.
 // Both reuse the tile functions of the single GEMM, so each problem's result
 // is bitwise identical to mfg_gemm on that problem alone.
 #include <algorithm>
+#include <type_traits>
 
 #include "tile16.h"
 
@@ -175,115 +177,226 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
 }
 
 // ------------------------------------------------------------------ grouped
-// Every wavefront is an independent worker: it takes work items (one 32 x 32
-// output tile of one problem) with a grid-wide stride.  Per 32-deep block of
-// K it issues all global loads of the block first (A: one 16-byte row piece
-// per lane and 16-deep chunk; B: one 16-byte row piece per lane of a 16 x 32
-// chunk), then per chunk stages B in the wave's LDS slab, reads it back
-// transposed and runs the 32x32x16 MFMA -- the same operands, in the same
-// order, as the simple kernel on that tile.  Many independent waves per CU
-// hide the memory latency of these HBM-bound problems.
-constexpr int kGroupedWavesPerWG = 4;
-constexpr int kGroupedChunks = 2;  // 16-deep K chunks whose loads are issued together
+// Each workgroup (four wavefronts) takes work items -- one 64 x 64 output
+// tile of one problem -- with a stride over its XCD's range of the work
+// list; wavefront (wm, wn) computes the 32 x 32 quarter (wm, wn).  The work
+// list is denormalised: each record carries the tile's operand pointers,
+// leading dimensions and extent, and 16 lanes of one load fetch one record,
+// so one load brings four records; two such windows are kept ahead of the
+// item being computed.
+//
+// The items' 64-deep K blocks form one stream per workgroup.  Block s + 2 is
+// loaded (16-byte pieces, 2 of A and 2 of B per lane: whole 128-byte rows of
+// the A and B tiles) while block s is multiplied, and written into the LDS
+// buffer of block s + 1's parity after it -- across item boundaries, so a
+// short item's loads overlap its predecessor's MFMAs and C stores.  One
+// barrier per block.  A rows sit in LDS as 8 XOR-swizzled 16-byte pieces; B
+// as 16 x 32 slabs read back transposed.  Every wavefront runs the 32x32x16
+// MFMA on 16-deep chunks in K order from zero, with zeros beyond K: the
+// operands and order of the simple kernel on that tile.
+constexpr int kGroupedBK = 64;  // K per block: 128-byte A and B rows
 // 16 zero bytes in device memory: the load source of lanes with nothing to load
 __device__ __attribute__((aligned(16))) const uint16_t kZero16[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 typedef __attribute__((address_space(1))) const uint16_t g_u16;
 typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
+typedef __attribute__((address_space(1))) const uint32_t g_u32;
 typedef __attribute__((address_space(1))) float g_f32;
-constexpr int kGroupedWGPerCU = 3;  // resident at 3 waves per SIMD (<= 168 VGPRs)
+constexpr int kGroupedWGPerCU = 3;  // resident at 3 waves per SIMD (<= 168 VGPRs, 32 KB of LDS each)
+static_assert(kGroupedTile == 64, "two 32 x 32 MFMA blocks per tile side");
+
+// One work record in scalar registers.
+struct GItem {
+    const g_u16* A;
+    const g_u16* B;
+    g_f32* C;
+    int64_t lda, ldb, ldc;
+    int rows, cols, K, vec;
+};
+
+// Record q (0..3) of a window: dword f of it sits in lane 16 q + f.
+__device__ __forceinline__ GItem window_item(uint32_t win, int q) {
+    auto dw = [&](int f) { return (uint32_t)__builtin_amdgcn_readlane((int)win, 16 * q + f); };
+    auto qw = [&](int f) { return (uint64_t)dw(f) | ((uint64_t)dw(f + 1) << 32); };
+    GItem t;
+    t.A = (const g_u16*)qw(0);
+    t.B = (const g_u16*)qw(2);
+    t.C = (g_f32*)qw(4);
+    t.lda = (int64_t)qw(6), t.ldb = (int64_t)qw(8), t.ldc = (int64_t)qw(10);
+    t.rows = (int)dw(12), t.cols = (int)dw(13), t.K = (int)dw(14), t.vec = (int)dw(15);
+    return t;
+}
+
+__device__ __forceinline__ int grouped_blocks(int K) { return max(1, (K + kGroupedBK - 1) / kGroupedBK); }
+
+// Workgroup barrier after this wave's LDS accesses completed (global stores
+// and loads stay in flight).
+__device__ __forceinline__ void grouped_barrier() {
+    lds_wait();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 template <int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gemm16_grouped(
-    const GroupedDesc* descs, const GroupedWork* work, GroupedSplit split, float alpha, float beta) {
-    __shared__ __attribute__((aligned(16))) uint16_t slabs[kGroupedWavesPerWG][16 * 32];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint16_t* slab = slabs[wid];
-    const int r = lane & 31, g = lane >> 5;
-    const int krow = lane >> 2, c8 = (lane & 3) * 8;
-    // this XCD's range of the work list, shared by its workgroups
+    const GroupedWork* work, GroupedSplit split, float alpha, float beta) {
+    // per buffer: A 64 rows x 64, B 4 chunks x 2 column halves x (16 x 32)
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][64 * 64];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][4][2][16 * 32];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), wm = wid >> 1, wn = wid & 1;
     const int xcd = blockIdx.x % kXcds;
-    const int64_t nwaves = (int64_t)(gridDim.x / kXcds) * kGroupedWavesPerWG;
-    const int64_t end = split.off[xcd + 1];
-    // the wave's item index is uniform across its lanes (SGPRs)
-    const int64_t first = split.off[xcd] + __builtin_amdgcn_readfirstlane((int)((blockIdx.x / kXcds) * kGroupedWavesPerWG + wid));
-    for (int64_t it = first; it < end; it += nwaves) {
-        const GroupedWork w = work[it];
-        const GroupedDesc d = descs[w.prob];
-        // The descriptor's pointers are device (global) memory.  Typed as such,
-        // or every access is a flat one, which also counts against lgkmcnt
-        // and so would wait behind (and be waited for by) the LDS traffic.
-        const g_u16* gA = (const g_u16*)d.A;
-        const g_u16* gB = (const g_u16*)d.B;
-        g_f32* gC = (g_f32*)d.C;
-        const int64_t m0 = (int64_t)w.tm * kGroupedTile, n0 = (int64_t)w.tn * kGroupedTile;
-        const int64_t am = m0 + r;
-        const bool vec = d.vec != 0;
-        f32x16 hi = {}, lo = {}, rr = {};
-        const int64_t bn = n0 + c8;
-        // Loads of one block of kGroupedChunks 16-deep chunks: whole 16-byte
-        // pieces first (all of them in flight together), then the ragged
-        // pieces (K tail, N edge, unaligned rows) element by element.
-        auto load_block = [&](int64_t kb0, u32x4 (&a)[kGroupedChunks], u32x4 (&b)[kGroupedChunks]) {
-            bool ragged = false;
+    const int64_t stride = gridDim.x / kXcds;
+    const int64_t first = split.off[xcd] + blockIdx.x / kXcds, end = split.off[xcd + 1];
+    if (first >= end) return;
+    const int64_t count = (end - first + stride - 1) / stride;  // items of this workgroup
+    // record windows: items w0 .. w0 + 3 and w0 + 4 .. w0 + 7 of this workgroup
+    const g_u32* wbase = (const g_u32*)work;
+    auto load_window = [&](int64_t w) -> uint32_t {
+        const int64_t it = first + (w + (lane >> 4)) * stride;
+        return it < end ? wbase[it * 16 + (lane & 15)] : 0u;
+    };
+    int64_t w0 = 0;
+    uint32_t win0 = load_window(0), win1 = load_window(4);
+    auto item_at = [&](int64_t i) {  // i in [w0, w0 + 8)
+        const int64_t d = i - w0;
+        return window_item(d < 4 ? win0 : win1, (int)(d & 3));
+    };
+
+    // This thread's two pieces of each operand block.  Aligned items (vec)
+    // load every piece that starts inside the operand as a whole 16-byte
+    // piece: with 16-byte aligned rows and ld a multiple of 8 the piece lies
+    // in the same aligned 16 bytes as its first element, inside the row's
+    // ld extent (and never across a page).  A's elements at or beyond K are
+    // then zeroed in registers; B's columns at or beyond the tile's width
+    // only reach discarded outputs, and B rows at or beyond K, like A rows
+    // beyond the tile, read 16 zero bytes.  So every block issues the same
+    // four loads and no branch.  Unaligned items load element by element.
+    auto load_block = [&](const GItem& t, int kb0, u32x4 (&a)[2], u32x4 (&b)[2], int (&nv)[2]) {
+        if (t.vec) {
 #pragma unroll
-            for (int c = 0; c < kGroupedChunks; ++c) {
-                const int64_t ka = kb0 + 16 * c + 8 * g, kr = kb0 + 16 * c + krow;
-                const bool fa = vec && am < d.M && ka + 8 <= d.K;
-                const bool fb = vec && kr < d.K && bn + 8 <= d.N;
-                // unconditional loads (a lane with no whole piece reads 16 zero
-                // bytes): no branch, so no wait at a join between the loads
-                a[c] = *(const g_u32x4*)(fa ? gA + am * d.lda + ka : (const g_u16*)kZero16);
-                b[c] = *(const g_u32x4*)(fb ? gB + kr * d.ldb + bn : (const g_u16*)kZero16);
-                ragged |= (!fa && am < d.M && ka < d.K) || (!fb && kr < d.K && bn < d.N);
+            for (int j = 0; j < 2; ++j) {
+                const int p = tid + 256 * j, row = p >> 3, ka = kb0 + 8 * (p & 7);
+                const int kr = kb0 + row, cb = 8 * (p & 7);  // B: K row kb0 + p / 8, columns cb .. cb + 7
+                const bool fa = row < t.rows && ka < t.K, fb = kr < t.K && cb < t.cols;
+                a[j] = *(const g_u32x4*)(fa ? t.A + row * t.lda + ka : (const g_u16*)kZero16);
+                b[j] = *(const g_u32x4*)(fb ? t.B + kr * t.ldb + cb : (const g_u16*)kZero16);
+                nv[j] = t.K - ka;  // valid elements of the A piece (masked when it is stored)
             }
-            if (ragged) {
+        } else {
 #pragma unroll
-                for (int c = 0; c < kGroupedChunks; ++c) {
-                    const int64_t ka = kb0 + 16 * c + 8 * g, kr = kb0 + 16 * c + krow;
-                    if (!(vec && am < d.M && ka + 8 <= d.K) && am < d.M && ka < d.K) {
-                        uint16_t e[8];
+            for (int j = 0; j < 2; ++j) {
+                const int p = tid + 256 * j, row = p >> 3, ka = kb0 + 8 * (p & 7);
+                const int kr = kb0 + row, cb = 8 * (p & 7);
+                uint16_t e[8], f[8];
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) e[j] = (ka + j < d.K) ? gA[am * d.lda + ka + j] : (uint16_t)0;
-                        a[c] = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
-                    }
-                    if (!(vec && kr < d.K && bn + 8 <= d.N) && kr < d.K && bn < d.N) {
-                        uint16_t e[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) e[j] = (bn + j < d.N) ? gB[kr * d.ldb + bn + j] : (uint16_t)0;
-                        b[c] = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
-                    }
+                for (int q = 0; q < 8; ++q) {
+                    e[q] = (row < t.rows && ka + q < t.K) ? t.A[row * t.lda + ka + q] : (uint16_t)0;
+                    f[q] = (kr < t.K && cb + q < t.cols) ? t.B[kr * t.ldb + cb + q] : (uint16_t)0;
                 }
-            }
-        };
-        // software pipeline over K blocks: block j+1's loads are in flight
-        // while block j runs through the LDS slab and the MFMAs
-        u32x4 ca[kGroupedChunks], cb[kGroupedChunks], na[kGroupedChunks], nb[kGroupedChunks];
-        load_block(0, ca, cb);
-        for (int64_t kb0 = 0; kb0 < d.K; kb0 += 16 * kGroupedChunks) {
-            const bool more = kb0 + 16 * kGroupedChunks < d.K;
-            if (more) load_block(kb0 + 16 * kGroupedChunks, na, nb);
-#pragma unroll
-            for (int c = 0; c < kGroupedChunks; ++c) {
-                if (kb0 + 16 * c >= d.K) break;
-                *reinterpret_cast<u32x4*>(slab + krow * 32 + c8) = cb[c];
-                lds_wait();
-                u32x4 aa[2] = {ca[c], zero4()}, bb[2] = {slab_read_b(slab, lane), zero4()};
-                lds_wait();  // the slab is rewritten by the next chunk
-                mma_step<KIND>(aa, bb, hi, lo, rr);
-            }
-            if (more) {
-#pragma unroll
-                for (int c = 0; c < kGroupedChunks; ++c) ca[c] = na[c], cb[c] = nb[c];
+                a[j] = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
+                b[j] = u32x4{pack2(f[0], f[1]), pack2(f[2], f[3]), pack2(f[4], f[5]), pack2(f[6], f[7])};
+                nv[j] = 8;
             }
         }
-        store_blocks<1>(gC, d.ldc, d.M, d.N, m0, n0, lane, alpha, beta,
-                        [&](int, int i) { return combine_at<KIND>(hi, lo, rr, i); });
+    };
+    auto store_block = [&](int buf, const u32x4 (&a)[2], const u32x4 (&b)[2], const int (&nv)[2]) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int p = tid + 256 * j, row = p >> 3, c = p & 7;
+            u32x4 am = a[j];
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                am[d] &= (2 * d < nv[j] ? 0xFFFFu : 0u) | (2 * d + 1 < nv[j] ? 0xFFFF0000u : 0u);
+            *reinterpret_cast<u32x4*>(&As[buf][row * 64 + ((c ^ swz<8>(row)) * 8)]) = am;
+            // B row `row` of the block: chunk row / 16, slab row row % 16,
+            // column half c / 4, columns 8 (c % 4) .. +7 of the half
+            *reinterpret_cast<u32x4*>(&Bs[buf][row >> 4][c >> 2][(row & 15) * 32 + 8 * (c & 3)]) = b[j];
+        }
+    };
+
+    // cursors: the computed block (item ci, block cb) and the loaded one,
+    // two blocks ahead (item li, block lb); both advance through the stream
+    int64_t ci = 0, li = 0;
+    int cbk = 0, lbk = 0;
+    GItem cur = item_at(0), ld = cur;
+    auto advance_load = [&]() {
+        if (++lbk >= grouped_blocks(ld.K)) {
+            lbk = 0;
+            if (++li < count) {
+                ld = item_at(li);
+            } else {  // past the stream: an empty item (every piece reads zeros)
+                ld.rows = ld.cols = ld.K = 0;
+                ld.vec = 1;
+                li = count;
+            }
+        }
+    };
+    u32x4 ra[2][2], rb[2][2];  // register sets of the two blocks in flight
+    int rn[2][2];
+    // prologue: block 0 into LDS buffer 0, block 1 into registers
+    load_block(ld, 0, ra[0], rb[0], rn[0]);
+    store_block(0, ra[0], rb[0], rn[0]);
+    advance_load();
+    load_block(ld, lbk * kGroupedBK, ra[1], rb[1], rn[1]);
+    advance_load();
+    grouped_barrier();
+
+    f32x16 hi = {}, lo = {}, rr = {};
+    // one block of the stream; BUF: its LDS buffer and register set (block
+    // parity).  Returns true after the last item's last block.
+    auto step = [&](auto bufc) -> bool {
+        constexpr int buf = decltype(bufc)::value;
+        // loads of block s + 2 into the register set block s used (kept
+        // ahead of everything below: the compiler would otherwise sink them)
+        load_block(ld, lbk * kGroupedBK, ra[buf], rb[buf], rn[buf]);
+        __builtin_amdgcn_sched_barrier(0);
+        const int kb0 = cbk * kGroupedBK;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (kb0 + 16 * c >= cur.K) break;
+            const int row = wm * 32 + (lane & 31), piece = 2 * c + (lane >> 5);
+            u32x4 aa[2] = {*reinterpret_cast<const u32x4*>(&As[buf][row * 64 + ((piece ^ swz<8>(row)) * 8)]), zero4()};
+            u32x4 bb[2] = {slab_read_b(Bs[buf][c][wn], lane), zero4()};
+            mma_step<KIND>(aa, bb, hi, lo, rr);
+        }
+        // block s + 1 (loaded during block s - 1) into the other buffer
+        store_block(buf ^ 1, ra[buf ^ 1], rb[buf ^ 1], rn[buf ^ 1]);
+        advance_load();
+        bool done = false;
+        if (cbk + 1 >= grouped_blocks(cur.K)) {  // the item's last block: its C, then the next item
+            store_blocks<1>(cur.C + (int64_t)(wm * 32) * cur.ldc + wn * 32, cur.ldc, cur.rows - wm * 32,
+                            cur.cols - wn * 32, 0, 0, lane, alpha, beta,
+                            [&](int, int e) { return combine_at<KIND>(hi, lo, rr, e); });
+            hi = f32x16{}, lo = f32x16{}, rr = f32x16{};
+            cbk = 0;
+            if (++ci >= count) {
+                done = true;
+            } else {
+                if (ci >= w0 + 4) {  // window 1 becomes window 0; fetch the four records after it
+                    w0 += 4;
+                    win0 = win1;
+                    win1 = load_window(w0 + 4);
+                }
+                cur = item_at(ci);
+            }
+        } else {
+            ++cbk;
+        }
+        if (done) return true;
+        grouped_barrier();
+        return false;
+    };
+    for (;;) {
+        if (step(std::integral_constant<int, 0>{})) break;
+        if (step(std::integral_constant<int, 1>{})) break;
     }
 }
 
 // Problems (or, for a problem above 1/16 of the total, bands of its tile
 // rows) go to the XCD with the least work so far, largest first (LPT on
-// flops); each XCD's items are then ordered by decreasing K, their cost.
+// flops); each XCD's items are then ordered by decreasing K, their cost, and
+// written out as self-contained records.
 void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split) {
     struct Unit {
         int64_t prob, tm0, tm1;
@@ -305,22 +418,36 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
         }
     }
     std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) { return x.flops > y.flops; });
+    struct Tile {
+        int32_t prob, tm, tn;
+    };
     std::vector<double> load(kXcds, 0.0);
-    std::vector<std::vector<GroupedWork>> per(kXcds);
+    std::vector<std::vector<Tile>> per(kXcds);
     for (const Unit& u : units) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[x] += u.flops;
         const int64_t tn = cdiv(descs[u.prob].N, kGroupedTile);
         for (int64_t a = u.tm0; a < u.tm1; ++a)
-            for (int64_t b = 0; b < tn; ++b) per[x].push_back(GroupedWork{(int32_t)u.prob, (int32_t)a, (int32_t)b, 0});
+            for (int64_t b = 0; b < tn; ++b) per[x].push_back(Tile{(int32_t)u.prob, (int32_t)a, (int32_t)b});
     }
     work.clear();
     split.off[0] = 0;
     for (int x = 0; x < kXcds; ++x) {
-        std::stable_sort(per[x].begin(), per[x].end(), [&](const GroupedWork& p, const GroupedWork& q) {
-            return descs[p.prob].K > descs[q.prob].K;
-        });
-        work.insert(work.end(), per[x].begin(), per[x].end());
+        std::stable_sort(per[x].begin(), per[x].end(),
+                         [&](const Tile& p, const Tile& q) { return descs[p.prob].K > descs[q.prob].K; });
+        for (const Tile& t : per[x]) {
+            const GroupedDesc& d = descs[t.prob];
+            const int64_t m0 = (int64_t)t.tm * kGroupedTile, n0 = (int64_t)t.tn * kGroupedTile;
+            GroupedWork w;
+            w.A = d.A + m0 * d.lda;
+            w.B = d.B + n0;
+            w.C = d.C + m0 * d.ldc + n0;
+            w.lda = d.lda, w.ldb = d.ldb, w.ldc = d.ldc;
+            w.rows = (int32_t)std::min<int64_t>(kGroupedTile, d.M - m0);
+            w.cols = (int32_t)std::min<int64_t>(kGroupedTile, d.N - n0);
+            w.K = (int32_t)d.K, w.vec = d.vec;
+            work.push_back(w);
+        }
         split.off[x + 1] = (int64_t)work.size();
     }
 }
@@ -328,20 +455,20 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
 int grouped_grid(const GroupedSplit& split) {
     int64_t most = 0;  // the largest per-XCD range sets how many workgroups each XCD needs
     for (int x = 0; x < kXcds; ++x) most = std::max<int64_t>(most, split.off[x + 1] - split.off[x]);
-    const int64_t per_xcd = std::max<int64_t>(
-        1, std::min<int64_t>(cdiv(most, kGroupedWavesPerWG), (int64_t)device_cu_count() / kXcds * kGroupedWGPerCU));
+    const int64_t per_xcd =
+        std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)device_cu_count() / kXcds * kGroupedWGPerCU));
     return (int)(per_xcd * kXcds);
 }
 
-int grouped_launch(int kind, const GroupedDesc* descs, const GroupedWork* work, const GroupedSplit& split, int grid,
-                   float alpha, float beta, hipStream_t s) {
+int grouped_launch(int kind, const GroupedWork* work, const GroupedSplit& split, int grid, float alpha, float beta,
+                   hipStream_t s) {
     if (kind != K_F16 && kind != K_BF16) return MFG_ERR_UNSUPPORTED;
     if (split.off[kXcds] == 0) return MFG_OK;
     if (grid % kXcds != 0 || grid <= 0) return MFG_ERR_INTERNAL;
     if (kind == K_F16)
-        hipLaunchKernelGGL(gemm16_grouped<K_F16>, dim3(grid), dim3(256), 0, s, descs, work, split, alpha, beta);
+        hipLaunchKernelGGL(gemm16_grouped<K_F16>, dim3(grid), dim3(256), 0, s, work, split, alpha, beta);
     else
-        hipLaunchKernelGGL(gemm16_grouped<K_BF16>, dim3(grid), dim3(256), 0, s, descs, work, split, alpha, beta);
+        hipLaunchKernelGGL(gemm16_grouped<K_BF16>, dim3(grid), dim3(256), 0, s, work, split, alpha, beta);
     MFG_LAUNCH_CHECK();
     return MFG_OK;
 }

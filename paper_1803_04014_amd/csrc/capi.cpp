@@ -316,7 +316,6 @@ struct mfg_grouped_plan {
     int64_t count = 0, nwork = 0;
     int grid = 0;
     GroupedSplit split{};
-    GroupedDesc* d_desc = nullptr;
     GroupedWork* d_work = nullptr;
     double flops = 0.0, bytes = 0.0;
     hipGraph_t graph = nullptr;
@@ -339,7 +338,7 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
         const mfg_problem& p = probs[i];
         int st = validate_gemm(p.M, p.N, p.K, p.A, p.lda, p.B, p.ldb, p.C, p.ldc, m);
         if (st != MFG_OK) return st;
-        if (p.M > ((int64_t)1 << 24) || p.N > ((int64_t)1 << 24)) return MFG_ERR_UNSUPPORTED;
+        if (p.M > ((int64_t)1 << 24) || p.N > ((int64_t)1 << 24) || p.K > INT32_MAX) return MFG_ERR_UNSUPPORTED;
         GroupedDesc& d = descs[(size_t)i];
         d.M = p.M, d.N = p.N, d.K = p.K, d.lda = p.lda, d.ldb = p.ldb, d.ldc = p.ldc;
         d.A = static_cast<const uint16_t*>(p.A), d.B = static_cast<const uint16_t*>(p.B), d.C = p.C;
@@ -356,16 +355,13 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
     plan->flops = flops, plan->bytes = bytes;
     MFG_HIP_CHECK(hipGetDevice(&plan->device));
     plan->grid = grouped_grid(split);
-    if (count > 0) {
-        if (hipMalloc(&plan->d_desc, descs.size() * sizeof(GroupedDesc)) != hipSuccess) return MFG_ERR_NO_MEMORY;
-        MFG_HIP_CHECK(hipMemcpy(plan->d_desc, descs.data(), descs.size() * sizeof(GroupedDesc), hipMemcpyHostToDevice));
-    }
     if (!work.empty()) {
-        if (hipMalloc(&plan->d_work, work.size() * sizeof(GroupedWork)) != hipSuccess) {
-            (void)hipFree(plan->d_desc);
-            return MFG_ERR_NO_MEMORY;
+        if (hipMalloc(&plan->d_work, work.size() * sizeof(GroupedWork)) != hipSuccess) return MFG_ERR_NO_MEMORY;
+        const hipError_t e = hipMemcpy(plan->d_work, work.data(), work.size() * sizeof(GroupedWork), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(plan->d_work);
+            return hip_fail(e);
         }
-        MFG_HIP_CHECK(hipMemcpy(plan->d_work, work.data(), work.size() * sizeof(GroupedWork), hipMemcpyHostToDevice));
     }
     *out = plan.release();
     return MFG_OK;
@@ -378,8 +374,7 @@ extern "C" int mfg_grouped_plan_create(int64_t count, const mfg_problem* problem
 
 extern "C" int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, void* stream) {
     if (!plan) return MFG_ERR_INVALID_ARG;
-    MFG_GUARD(grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->split, plan->grid, alpha, beta,
-                             (hipStream_t)stream));
+    MFG_GUARD(grouped_launch(plan->kind, plan->d_work, plan->split, plan->grid, alpha, beta, (hipStream_t)stream));
 }
 
 static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hipStream_t s) {
@@ -392,8 +387,7 @@ static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hi
     if (!plan->exec) {
         if (!plan->cap_stream) MFG_HIP_CHECK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
         MFG_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
-        int st = grouped_launch(plan->kind, plan->d_desc, plan->d_work, plan->split, plan->grid, alpha, beta,
-                                plan->cap_stream);
+        int st = grouped_launch(plan->kind, plan->d_work, plan->split, plan->grid, alpha, beta, plan->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
         if (st != MFG_OK) {
@@ -430,7 +424,6 @@ extern "C" int mfg_grouped_plan_destroy(mfg_grouped_plan* plan) {
     if (!plan) return MFG_ERR_INVALID_ARG;
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
-    if (plan->d_desc) (void)hipFree(plan->d_desc);
     if (plan->d_work) (void)hipFree(plan->d_work);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;

@@ -110,12 +110,12 @@ int launch_scale_c(int64_t M, int64_t N, float* C, int64_t ldc, float beta, int6
                    int64_t sC, hipStream_t s);
 
 // Batched and grouped launches (batched.hip).
-struct GroupedDesc {  // one problem, device resident
+struct GroupedDesc {  // one problem (host side; the kernel reads GroupedWork)
     int64_t M, N, K, lda, ldb, ldc;
     const uint16_t* A;
     const uint16_t* B;
     float* C;
-    int32_t vec;  // 1: 16-byte aligned rows (LDS-staged tile), 0: per-wave tile
+    int32_t vec;  // 1: 16-byte aligned rows and ld a multiple of 8 (whole 16-byte loads)
     int32_t pad;
 };
 // Tiled kernels address C with 32-bit buffer offsets within a 32-row block:
@@ -124,10 +124,18 @@ struct GroupedDesc {  // one problem, device resident
 constexpr int64_t kBufferLdcLimit = int64_t(1) << 24;
 inline bool buffer_ldc_ok(int64_t ldc) { return ldc < kBufferLdcLimit; }
 
-constexpr int kGroupedTile = 32;  // output tile of a grouped work item (one wavefront)
-struct GroupedWork {  // one kGroupedTile x kGroupedTile output tile of one problem
-    int32_t prob, tm, tn, pad;
+constexpr int kGroupedTile = 64;  // output tile of a grouped work item (one workgroup)
+// One kGroupedTile x kGroupedTile output tile with everything its workgroup
+// reads (16 dwords, so that 16 lanes fetch one record with one load each).
+struct GroupedWork {
+    const uint16_t* A;  // row m0 of the problem's A
+    const uint16_t* B;  // column n0 of its B
+    float* C;           // element (m0, n0) of its C
+    int64_t lda, ldb, ldc;
+    int32_t rows, cols;  // of the tile inside the problem: min(64, M - m0), min(64, N - n0)
+    int32_t K, vec;
 };
+static_assert(sizeof(GroupedWork) == 64, "a work record is 16 dwords");
 int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_ok, int num_cu,
                          hipStream_t s);
 // Work list of a grouped launch, split into one contiguous range per XCD
@@ -138,8 +146,8 @@ struct GroupedSplit {
     int64_t off[kXcds + 1];
 };
 void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split);
-int grouped_launch(int kind, const GroupedDesc* descs, const GroupedWork* work, const GroupedSplit& split,
-                   int grid, float alpha, float beta, hipStream_t s);
+int grouped_launch(int kind, const GroupedWork* work, const GroupedSplit& split, int grid, float alpha, float beta,
+                   hipStream_t s);
 int grouped_grid(const GroupedSplit& split);  // workgroups of a grouped launch (a multiple of kXcds)
 
 // Validation (validate.cpp; pure host code).

@@ -97,9 +97,8 @@ struct Slot {
     bool force_ready = false;  // the group's end is already known (its event could not be recorded)
     int64_t dry_end_ns = 0;
     std::vector<Req*> running;
-    GroupedDesc* h_desc = nullptr;  // pinned staging of the group's descriptors
+    std::vector<GroupedDesc> h_desc;  // the group's problems (host side)
     GroupedWork* h_work = nullptr;
-    GroupedDesc* d_desc = nullptr;
     GroupedWork* d_work = nullptr;
 };
 
@@ -145,9 +144,8 @@ int mfg_server::init_device() {
     for (auto& sl : slots) {
         MFG_HIP_CHECK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
         MFG_HIP_CHECK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-        MFG_HIP_CHECK(hipHostMalloc((void**)&sl.h_desc, sizeof(GroupedDesc) * cfg.max_group, 0));
+        sl.h_desc.resize((size_t)cfg.max_group);
         MFG_HIP_CHECK(hipHostMalloc((void**)&sl.h_work, sizeof(GroupedWork) * work_cap, 0));
-        MFG_HIP_CHECK(hipMalloc((void**)&sl.d_desc, sizeof(GroupedDesc) * cfg.max_group));
         MFG_HIP_CHECK(hipMalloc((void**)&sl.d_work, sizeof(GroupedWork) * work_cap));
     }
     return MFG_OK;
@@ -158,9 +156,7 @@ void mfg_server::release_device() {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        if (sl.h_desc) (void)hipHostFree(sl.h_desc);
         if (sl.h_work) (void)hipHostFree(sl.h_work);
-        if (sl.d_desc) (void)hipFree(sl.d_desc);
         if (sl.d_work) (void)hipFree(sl.d_work);
         sl = Slot{};
     }
@@ -290,14 +286,13 @@ int mfg_server::run_grouped(Slot& sl, const std::vector<Req*>& g) {
     }
     GroupedSplit split{};
     std::vector<GroupedWork> work;
-    build_grouped_work(sl.h_desc, nd, work, split);
+    build_grouped_work(sl.h_desc.data(), nd, work, split);
     const int64_t nw = (int64_t)work.size();  // <= max_group * kSmallTiles (grouped_small)
     std::copy(work.begin(), work.end(), sl.h_work);
-    MFG_HIP_CHECK(hipMemcpyAsync(sl.d_desc, sl.h_desc, sizeof(GroupedDesc) * nd, hipMemcpyHostToDevice, sl.stream));
     MFG_HIP_CHECK(hipMemcpyAsync(sl.d_work, sl.h_work, sizeof(GroupedWork) * nw, hipMemcpyHostToDevice, sl.stream));
     const int kind = g.front()->r.mode == MFG_BF16 ? K_BF16 : K_F16;
-    return grouped_launch(kind, sl.d_desc, sl.d_work, split, grouped_grid(split), g.front()->r.alpha,
-                          g.front()->r.beta, sl.stream);
+    return grouped_launch(kind, sl.d_work, split, grouped_grid(split), g.front()->r.alpha, g.front()->r.beta,
+                          sl.stream);
 }
 
 void mfg_server::launch_group(int si, std::vector<Req*>& g) {

@@ -77,8 +77,10 @@ def _grouped_problems(count, lo, hi, seed, unaligned_every=0):
         else:
             lda, ldb = -(-k // 8) * 8, -(-n // 8) * 8
         A, B = workloads.uniform(1000 + i, [(m, lda), (k, ldb)])
-        dA = dev(A).half()[:, :k]
-        dB = dev(B).half()[:, :n]
+        fa, fb = dev(A).half(), dev(B).half()
+        fa[:, k:] = float("nan")  # row padding never reaches a result
+        fb[:, n:] = float("nan")
+        dA, dB = fa[:, :k], fb[:, :n]
         dC = torch.zeros((m, n), dtype=torch.float32, device=DEV)
         probs.append((dA, dB, dC))
         host_ops.append((A[:, :k], B[:, :n]))
@@ -89,17 +91,29 @@ def test_grouped_equals_solo_and_graph_replays():
     probs, host_ops = _grouped_problems(300, 16, 200, 6, unaligned_every=7)
     plan = mfg.GroupedPlan(probs, "f16")
     info = plan.info()
-    assert info["work_items"] == sum(-(-p[0].shape[0] // 32) * -(-p[1].shape[1] // 32) for p in probs)
+    # one work item per 64 x 64 output tile
+    assert info["work_items"] == sum(-(-p[0].shape[0] // 64) * -(-p[1].shape[1] // 64) for p in probs)
     plan.run(1.0, 0.0)
     first = [host(p[2]).copy() for p in probs]
-    for i in range(0, 300, 23):
+    for i in range(300):
         A, B, C = probs[i]
         solo = torch.zeros_like(C)
         mfg.gemm(A, B, solo, 1.0, 0.0, mode="f16", preconverted=True)
         assert np.array_equal(first[i].view(np.uint32), host(solo).view(np.uint32)), f"problem {i}"
-        a16 = oracle.f16_round(host_ops[i][0]).astype(np.float32)
-        b16 = oracle.f16_round(host_ops[i][1]).astype(np.float32)
-        assert_parity(first[i], oracle.reference("f32", a16, b16), f"grouped problem {i}")
+        if i % 23 == 0:
+            a16 = oracle.f16_round(host_ops[i][0]).astype(np.float32)
+            b16 = oracle.f16_round(host_ops[i][1]).astype(np.float32)
+            assert_parity(first[i], oracle.reference("f32", a16, b16), f"grouped problem {i}")
+    # alpha and beta: C = 0.75 A B - 0.5 C, against the solo GEMM on the same C
+    c0 = [torch.randn_like(p[2]) for p in probs]
+    for p, c in zip(probs, c0):
+        p[2].copy_(c)
+    plan.run(0.75, -0.5)
+    for i in range(0, 300, 3):
+        A, B, C = probs[i]
+        solo = c0[i].clone()
+        mfg.gemm(A, B, solo, 0.75, -0.5, mode="f16", preconverted=True)
+        assert np.array_equal(host(C).view(np.uint32), host(solo).view(np.uint32)), f"beta problem {i}"
     # graph replays with eager work in between; every replay must equal the eager result
     for rep in range(3):
         for p in probs:
