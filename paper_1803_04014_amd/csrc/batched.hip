@@ -237,9 +237,10 @@ __device__ __forceinline__ void grouped_barrier() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <int KIND>
+template <int KIND, bool VEC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gemm16_grouped(
     const GroupedWork* work, GroupedSplit split, float alpha, float beta) {
+    const int64_t* off = split.off[VEC ? 0 : 1];
     // per buffer: A 64 rows x 64, B 4 chunks x 2 column halves x (16 x 32)
     __shared__ __attribute__((aligned(16))) uint16_t As[2][64 * 64];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][4][2][16 * 32];
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), wm = wid >> 1, wn = wid & 1;
     const int xcd = blockIdx.x % kXcds;
     const int64_t stride = gridDim.x / kXcds;
-    const int64_t first = split.off[xcd] + blockIdx.x / kXcds, end = split.off[xcd + 1];
+    const int64_t first = off[xcd] + blockIdx.x / kXcds, end = off[xcd + 1];
     if (first >= end) return;
     const int64_t count = (end - first + stride - 1) / stride;  // items of this workgroup
     // record windows: items w0 .. w0 + 3 and w0 + 4 .. w0 + 7 of this workgroup
@@ -263,8 +264,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
         return window_item(d < 4 ? win0 : win1, (int)(d & 3));
     };
 
-    // This thread's two pieces of each operand block.  Aligned items (vec)
-    // load every piece that starts inside the operand as a whole 16-byte
+    // This thread's two pieces of each operand block.  Aligned items (the
+    // VEC list: vec records only) load every piece that starts inside the operand as a whole 16-byte
     // piece: with 16-byte aligned rows and ld a multiple of 8 the piece lies
     // in the same aligned 16 bytes as its first element, inside the row's
     // ld extent (and never across a page).  A's elements at or beyond K are
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
     // beyond the tile, read 16 zero bytes.  So every block issues the same
     // four loads and no branch.  Unaligned items load element by element.
     auto load_block = [&](const GItem& t, int kb0, u32x4 (&a)[2], u32x4 (&b)[2], int (&nv)[2]) {
-        if (t.vec) {
+        if constexpr (VEC) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int p = tid + 256 * j, row = p >> 3, ka = kb0 + 8 * (p & 7);
@@ -327,7 +328,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
                 ld = item_at(li);
             } else {  // past the stream: an empty item (every piece reads zeros)
                 ld.rows = ld.cols = ld.K = 0;
-                ld.vec = 1;
                 li = count;
             }
         }
@@ -365,9 +365,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
         advance_load();
         bool done = false;
         if (cbk + 1 >= grouped_blocks(cur.K)) {  // the item's last block: its C, then the next item
-            store_blocks<1>(cur.C + (int64_t)(wm * 32) * cur.ldc + wn * 32, cur.ldc, cur.rows - wm * 32,
-                            cur.cols - wn * 32, 0, 0, lane, alpha, beta,
-                            [&](int, int e) { return combine_at<KIND>(hi, lo, rr, e); });
+            auto val = [&](int, int e) { return combine_at<KIND>(hi, lo, rr, e); };
+            g_f32* cq = cur.C + (int64_t)(wm * 32) * cur.ldc + wn * 32;
+            // the VEC list holds only ldc < kBufferLdcLimit: no 64-bit path
+            // (whose C reads may stay unconsumed on masked lanes)
+            if constexpr (VEC)
+                store_blocks_buf<1>(cq, cur.ldc, cur.rows - wm * 32, cur.cols - wn * 32, 0, 0, lane, alpha, beta, val);
+            else
+                store_blocks<1>(cq, cur.ldc, cur.rows - wm * 32, cur.cols - wn * 32, 0, 0, lane, alpha, beta, val);
             hi = f32x16{}, lo = f32x16{}, rr = f32x16{};
             cbk = 0;
             if (++ci >= count) {
@@ -402,74 +407,84 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
         int64_t prob, tm0, tm1;
         double flops;
     };
-    double total = 0.0;
-    for (int64_t i = 0; i < n; ++i) total += 2.0 * (double)descs[i].M * (double)descs[i].N * (double)descs[i].K;
-    const double cap = total / (2.0 * kXcds);
-    std::vector<Unit> units;
-    for (int64_t i = 0; i < n; ++i) {
-        const GroupedDesc& d = descs[i];
-        const int64_t tm = cdiv(d.M, kGroupedTile), tn = cdiv(d.N, kGroupedTile);
-        if (tm == 0 || tn == 0) continue;
-        const double f = 2.0 * (double)d.M * (double)d.N * (double)d.K;
-        const int64_t parts = std::min<int64_t>(tm, cap > 0.0 ? std::max<int64_t>(1, (int64_t)(f / cap)) : 1);
-        for (int64_t q = 0; q < parts; ++q) {
-            const int64_t a = tm * q / parts, b = tm * (q + 1) / parts;
-            units.push_back(Unit{i, a, b, f * (double)(b - a) / (double)tm});
-        }
-    }
-    std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) { return x.flops > y.flops; });
     struct Tile {
         int32_t prob, tm, tn;
     };
-    std::vector<double> load(kXcds, 0.0);
-    std::vector<std::vector<Tile>> per(kXcds);
-    for (const Unit& u : units) {
-        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[x] += u.flops;
-        const int64_t tn = cdiv(descs[u.prob].N, kGroupedTile);
-        for (int64_t a = u.tm0; a < u.tm1; ++a)
-            for (int64_t b = 0; b < tn; ++b) per[x].push_back(Tile{(int32_t)u.prob, (int32_t)a, (int32_t)b});
-    }
     work.clear();
-    split.off[0] = 0;
-    for (int x = 0; x < kXcds; ++x) {
-        std::stable_sort(per[x].begin(), per[x].end(),
-                         [&](const Tile& p, const Tile& q) { return descs[p.prob].K > descs[q.prob].K; });
-        for (const Tile& t : per[x]) {
-            const GroupedDesc& d = descs[t.prob];
-            const int64_t m0 = (int64_t)t.tm * kGroupedTile, n0 = (int64_t)t.tn * kGroupedTile;
-            GroupedWork w;
-            w.A = d.A + m0 * d.lda;
-            w.B = d.B + n0;
-            w.C = d.C + m0 * d.ldc + n0;
-            w.lda = d.lda, w.ldb = d.ldb, w.ldc = d.ldc;
-            w.rows = (int32_t)std::min<int64_t>(kGroupedTile, d.M - m0);
-            w.cols = (int32_t)std::min<int64_t>(kGroupedTile, d.N - n0);
-            w.K = (int32_t)d.K, w.vec = d.vec;
-            work.push_back(w);
+    for (int list = 0; list < 2; ++list) {  // 0: aligned problems with ldc < kBufferLdcLimit, 1: the rest
+        auto in_list = [&](const GroupedDesc& d) { return (d.vec != 0 && buffer_ldc_ok(d.ldc)) == (list == 0); };
+        double total = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            if (in_list(descs[i])) total += 2.0 * (double)descs[i].M * (double)descs[i].N * (double)descs[i].K;
+        const double cap = total / (2.0 * kXcds);
+        std::vector<Unit> units;
+        for (int64_t i = 0; i < n; ++i) {
+            const GroupedDesc& d = descs[i];
+            const int64_t tm = cdiv(d.M, kGroupedTile), tn = cdiv(d.N, kGroupedTile);
+            if (!in_list(d) || tm == 0 || tn == 0) continue;
+            const double f = 2.0 * (double)d.M * (double)d.N * (double)d.K;
+            const int64_t parts = std::min<int64_t>(tm, cap > 0.0 ? std::max<int64_t>(1, (int64_t)(f / cap)) : 1);
+            for (int64_t q = 0; q < parts; ++q) {
+                const int64_t a = tm * q / parts, b = tm * (q + 1) / parts;
+                units.push_back(Unit{i, a, b, f * (double)(b - a) / (double)tm});
+            }
         }
-        split.off[x + 1] = (int64_t)work.size();
+        std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) { return x.flops > y.flops; });
+        std::vector<double> load(kXcds, 0.0);
+        std::vector<std::vector<Tile>> per(kXcds);
+        for (const Unit& u : units) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[x] += u.flops;
+            const int64_t tn = cdiv(descs[u.prob].N, kGroupedTile);
+            for (int64_t a = u.tm0; a < u.tm1; ++a)
+                for (int64_t b = 0; b < tn; ++b) per[x].push_back(Tile{(int32_t)u.prob, (int32_t)a, (int32_t)b});
+        }
+        split.off[list][0] = (int64_t)work.size();
+        for (int x = 0; x < kXcds; ++x) {
+            std::stable_sort(per[x].begin(), per[x].end(),
+                             [&](const Tile& p, const Tile& q) { return descs[p.prob].K > descs[q.prob].K; });
+            for (const Tile& t : per[x]) {
+                const GroupedDesc& d = descs[t.prob];
+                const int64_t m0 = (int64_t)t.tm * kGroupedTile, n0 = (int64_t)t.tn * kGroupedTile;
+                GroupedWork w;
+                w.A = d.A + m0 * d.lda;
+                w.B = d.B + n0;
+                w.C = d.C + m0 * d.ldc + n0;
+                w.lda = d.lda, w.ldb = d.ldb, w.ldc = d.ldc;
+                w.rows = (int32_t)std::min<int64_t>(kGroupedTile, d.M - m0);
+                w.cols = (int32_t)std::min<int64_t>(kGroupedTile, d.N - n0);
+                w.K = (int32_t)d.K, w.vec = d.vec;
+                work.push_back(w);
+            }
+            split.off[list][x + 1] = (int64_t)work.size();
+        }
     }
 }
 
-int grouped_grid(const GroupedSplit& split) {
+int grouped_grid(const GroupedSplit& split, int list) {
     int64_t most = 0;  // the largest per-XCD range sets how many workgroups each XCD needs
-    for (int x = 0; x < kXcds; ++x) most = std::max<int64_t>(most, split.off[x + 1] - split.off[x]);
+    for (int x = 0; x < kXcds; ++x) most = std::max<int64_t>(most, split.off[list][x + 1] - split.off[list][x]);
     const int64_t per_xcd =
         std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)device_cu_count() / kXcds * kGroupedWGPerCU));
     return (int)(per_xcd * kXcds);
 }
 
-int grouped_launch(int kind, const GroupedWork* work, const GroupedSplit& split, int grid, float alpha, float beta,
+int grouped_launch(int kind, const GroupedWork* work, const GroupedSplit& split, float alpha, float beta,
                    hipStream_t s) {
     if (kind != K_F16 && kind != K_BF16) return MFG_ERR_UNSUPPORTED;
-    if (split.off[kXcds] == 0) return MFG_OK;
-    if (grid % kXcds != 0 || grid <= 0) return MFG_ERR_INTERNAL;
-    if (kind == K_F16)
-        hipLaunchKernelGGL(gemm16_grouped<K_F16>, dim3(grid), dim3(256), 0, s, work, split, alpha, beta);
-    else
-        hipLaunchKernelGGL(gemm16_grouped<K_BF16>, dim3(grid), dim3(256), 0, s, work, split, alpha, beta);
-    MFG_LAUNCH_CHECK();
+    for (int list = 0; list < 2; ++list) {
+        if (split.off[list][kXcds] == split.off[list][0]) continue;  // empty list
+        const dim3 grid((unsigned)grouped_grid(split, list));
+        if (kind == K_F16 && list == 0)
+            hipLaunchKernelGGL((gemm16_grouped<K_F16, true>), grid, dim3(256), 0, s, work, split, alpha, beta);
+        else if (kind == K_F16)
+            hipLaunchKernelGGL((gemm16_grouped<K_F16, false>), grid, dim3(256), 0, s, work, split, alpha, beta);
+        else if (list == 0)
+            hipLaunchKernelGGL((gemm16_grouped<K_BF16, true>), grid, dim3(256), 0, s, work, split, alpha, beta);
+        else
+            hipLaunchKernelGGL((gemm16_grouped<K_BF16, false>), grid, dim3(256), 0, s, work, split, alpha, beta);
+        MFG_LAUNCH_CHECK();
+    }
     return MFG_OK;
 }
 

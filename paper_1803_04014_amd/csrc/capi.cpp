@@ -314,7 +314,6 @@ extern "C" int mfg_gemm_batched(int64_t count, int64_t M, int64_t N, int64_t K, 
 struct mfg_grouped_plan {
     int mode = 0, kind = 0, device = 0;
     int64_t count = 0, nwork = 0;
-    int grid = 0;
     GroupedSplit split{};
     GroupedWork* d_work = nullptr;
     double flops = 0.0, bytes = 0.0;
@@ -354,7 +353,6 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
     plan->mode = m, plan->kind = kind_of(m), plan->count = count, plan->nwork = (int64_t)work.size();
     plan->flops = flops, plan->bytes = bytes;
     MFG_HIP_CHECK(hipGetDevice(&plan->device));
-    plan->grid = grouped_grid(split);
     if (!work.empty()) {
         if (hipMalloc(&plan->d_work, work.size() * sizeof(GroupedWork)) != hipSuccess) return MFG_ERR_NO_MEMORY;
         const hipError_t e = hipMemcpy(plan->d_work, work.data(), work.size() * sizeof(GroupedWork), hipMemcpyHostToDevice);
@@ -374,7 +372,7 @@ extern "C" int mfg_grouped_plan_create(int64_t count, const mfg_problem* problem
 
 extern "C" int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, void* stream) {
     if (!plan) return MFG_ERR_INVALID_ARG;
-    MFG_GUARD(grouped_launch(plan->kind, plan->d_work, plan->split, plan->grid, alpha, beta, (hipStream_t)stream));
+    MFG_GUARD(grouped_launch(plan->kind, plan->d_work, plan->split, alpha, beta, (hipStream_t)stream));
 }
 
 static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hipStream_t s) {
@@ -387,7 +385,7 @@ static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hi
     if (!plan->exec) {
         if (!plan->cap_stream) MFG_HIP_CHECK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
         MFG_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
-        int st = grouped_launch(plan->kind, plan->d_work, plan->split, plan->grid, alpha, beta, plan->cap_stream);
+        int st = grouped_launch(plan->kind, plan->d_work, plan->split, alpha, beta, plan->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
         if (st != MFG_OK) {

@@ -112,7 +112,7 @@ __device__ __forceinline__ void store_blocks_wide(CPtr C, int64_t ldc, int64_t M
 }
 
 // The same epilogue with buffer instructions (ldc < kBufferLdcLimit, the
-// bound of 32-bit offsets over a 32-row block; for FN = 1 any ldc).  rbase and cbase are the same in every lane.  One buffer
+// bound of 32-bit offsets over a 32-row block).  rbase and cbase are the same in every lane.  One buffer
 // resource covers the row of blocks; element i of a lane sits at a per-lane
 // byte offset (four of them, one per i % 4) plus a scalar offset of
 // 8 (i / 4) rows, so each value costs one memory instruction and no address
@@ -121,14 +121,8 @@ __device__ __forceinline__ void store_blocks_wide(CPtr C, int64_t ldc, int64_t M
 // and returns 0 for those loads, so there are no branches.  All loads of
 // the row are issued before its stores.
 template <int FN, class Val, class CPtr>
-__device__ __forceinline__ void store_blocks(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
-                                             int64_t cbase, int lane, float alpha, float beta, Val val) {
-    if constexpr (FN == 1) {
-        if (ldc >= kBufferLdcLimit) {
-            store_blocks_wide<1>(C, ldc, M, N, rbase, cbase, lane, alpha, beta, val);
-            return;
-        }
-    }
+__device__ __forceinline__ void store_blocks_buf(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
+                                                 int64_t cbase, int lane, float alpha, float beta, Val val) {
     const int64_t rb = uniform64(rbase), cb = uniform64(cbase);
     const __amdgpu_buffer_rsrc_t rs =
         buffer_rsrc((float*)C + rb * ldc + cb, (uint32_t)((31 * ldc + 32 * FN) * 4));
@@ -175,6 +169,20 @@ __device__ __forceinline__ void store_blocks(CPtr C, int64_t ldc, int64_t M, int
             __builtin_amdgcn_raw_buffer_store_b32(
                 __builtin_bit_cast(uint32_t, __builtin_fmaf(alpha, val(fn, i), beta * c[fn][i])), rs, off[fn][i],
                 8 * (i >> 2) * l4, 0);
+}
+
+// store_blocks_buf, or for single blocks with ldc >= kBufferLdcLimit the
+// 64-bit path.
+template <int FN, class Val, class CPtr>
+__device__ __forceinline__ void store_blocks(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
+                                             int64_t cbase, int lane, float alpha, float beta, Val val) {
+    if constexpr (FN == 1) {
+        if (ldc >= kBufferLdcLimit) {
+            store_blocks_wide<1>(C, ldc, M, N, rbase, cbase, lane, alpha, beta, val);
+            return;
+        }
+    }
+    store_blocks_buf<FN>(C, ldc, M, N, rbase, cbase, lane, alpha, beta, val);
 }
 
 // Epilogue of a wavefront's FM x FN accumulator blocks: rows rbase + 32 fm,

@@ -143,12 +143,13 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
 // so its operands are fetched into one L2.
 constexpr int kXcds = 8;
 struct GroupedSplit {
-    int64_t off[kXcds + 1];
+    int64_t off[2][kXcds + 1];  // list 0: aligned rows (vec) and ldc < kBufferLdcLimit, list 1: the rest
 };
 void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split);
-int grouped_launch(int kind, const GroupedWork* work, const GroupedSplit& split, int grid, float alpha, float beta,
+// One launch per non-empty list (the grid of each from grouped_grid).
+int grouped_launch(int kind, const GroupedWork* work, const GroupedSplit& split, float alpha, float beta,
                    hipStream_t s);
-int grouped_grid(const GroupedSplit& split);  // workgroups of a grouped launch (a multiple of kXcds)
+int grouped_grid(const GroupedSplit& split, int list);  // workgroups of a list's launch (a multiple of kXcds)
 
 // Validation (validate.cpp; pure host code).
 int validate_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,

@@ -291,8 +291,7 @@ int mfg_server::run_grouped(Slot& sl, const std::vector<Req*>& g) {
     std::copy(work.begin(), work.end(), sl.h_work);
     MFG_HIP_CHECK(hipMemcpyAsync(sl.d_work, sl.h_work, sizeof(GroupedWork) * nw, hipMemcpyHostToDevice, sl.stream));
     const int kind = g.front()->r.mode == MFG_BF16 ? K_BF16 : K_F16;
-    return grouped_launch(kind, sl.d_work, split, grouped_grid(split), g.front()->r.alpha, g.front()->r.beta,
-                          sl.stream);
+    return grouped_launch(kind, sl.d_work, split, g.front()->r.alpha, g.front()->r.beta, sl.stream);
 }
 
 void mfg_server::launch_group(int si, std::vector<Req*>& g) {
