@@ -111,31 +111,30 @@ __device__ __forceinline__ void store_blocks_wide(CPtr C, int64_t ldc, int64_t M
     }
 }
 
-// The same epilogue with buffer instructions (ldc < kBufferLdcLimit, the
-// bound of 32-bit offsets over a 32-row block).  rbase and cbase are the same in every lane.  One buffer
-// resource covers the row of blocks; element i of a lane sits at a per-lane
-// byte offset (four of them, one per i % 4) plus a scalar offset of
-// 8 (i / 4) rows, so each value costs one memory instruction and no address
-// arithmetic.  Blocks that cross the edge of C give the elements outside it
-// an offset beyond the resource's range: the hardware drops those stores
-// and returns 0 for those loads, so there are no branches.  All loads of
-// the row are issued before its stores.
-template <int FN, class Val, class CPtr>
-__device__ __forceinline__ void store_blocks_buf(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
-                                                 int64_t cbase, int lane, float alpha, float beta, Val val) {
+// Addressing of one row of FN 32x32 blocks for buffer instructions:
+// resource, per-element offsets (out of range outside C) and the row pitch.
+template <int FN>
+struct BlockAddr {
+    __amdgpu_buffer_rsrc_t rs;
+    int off[FN][16];
+    int l4;
+};
+
+template <int FN, class CPtr>
+__device__ __forceinline__ BlockAddr<FN> block_addr(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
+                                                    int64_t cbase, int lane) {
     const int64_t rb = uniform64(rbase), cb = uniform64(cbase);
-    const __amdgpu_buffer_rsrc_t rs =
-        buffer_rsrc((float*)C + rb * ldc + cb, (uint32_t)((31 * ldc + 32 * FN) * 4));
-    const int l4 = (int)ldc * 4;
+    BlockAddr<FN> a;
+    a.rs = buffer_rsrc((float*)C + rb * ldc + cb, (uint32_t)((31 * ldc + 32 * FN) * 4));
+    a.l4 = (int)ldc * 4;
     int vo[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) vo[j] = (4 * (lane >> 5) + j) * l4 + (lane & 31) * 4;
-    int off[FN][16];
+    for (int j = 0; j < 4; ++j) vo[j] = (4 * (lane >> 5) + j) * a.l4 + (lane & 31) * 4;
     if (rb + 32 <= M && cb + 32 * FN <= N) {
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn)
 #pragma unroll
-            for (int i = 0; i < 16; ++i) off[fn][i] = vo[i & 3] + fn * 128;
+            for (int i = 0; i < 16; ++i) a.off[fn][i] = vo[i & 3] + fn * 128;
     } else {
         constexpr int kOut = INT32_MIN;  // 2^31 as an unsigned offset: beyond any resource here
         const int64_t rows = M - rb, cols = N - cb;
@@ -143,32 +142,54 @@ __device__ __forceinline__ void store_blocks_buf(CPtr C, int64_t ldc, int64_t M,
         for (int fn = 0; fn < FN; ++fn)
 #pragma unroll
             for (int i = 0; i < 16; ++i)
-                off[fn][i] = (mfma_out_row(i, lane) < rows && (lane & 31) + 32 * fn < cols) ? vo[i & 3] + fn * 128
-                                                                                             : kOut;
+                a.off[fn][i] = (mfma_out_row(i, lane) < rows && (lane & 31) + 32 * fn < cols) ? vo[i & 3] + fn * 128
+                                                                                               : kOut;
     }
+    return a;
+}
+
+// C values of the blocks (0 outside C).
+template <int FN>
+__device__ __forceinline__ void block_load(const BlockAddr<FN>& a, float (&c)[FN][16]) {
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            c[fn][i] = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(a.rs, a.off[fn][i], 8 * (i >> 2) * a.l4, 0));
+}
+
+// C = v(fn, i) for the elements inside C.
+template <int FN, class V>
+__device__ __forceinline__ void block_store(const BlockAddr<FN>& a, V v) {
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v(fn, i)), a.rs, a.off[fn][i],
+                                                  8 * (i >> 2) * a.l4, 0);
+}
+
+// The epilogue with buffer instructions (ldc < kBufferLdcLimit, the bound of
+// 32-bit offsets over a 32-row block).  rbase and cbase are the same in
+// every lane.  One buffer resource covers the row of blocks; element i of a
+// lane sits at a per-lane byte offset (four of them, one per i % 4) plus a
+// scalar offset of 8 (i / 4) rows, so each value costs one memory
+// instruction and no address arithmetic.  Blocks that cross the edge of C
+// give the elements outside it an offset beyond the resource's range: the
+// hardware drops those stores and returns 0 for those loads, so there are
+// no branches.  All loads of the row are issued before its stores.
+template <int FN, class Val, class CPtr>
+__device__ __forceinline__ void store_blocks_buf(CPtr C, int64_t ldc, int64_t M, int64_t N, int64_t rbase,
+                                                 int64_t cbase, int lane, float alpha, float beta, Val val) {
+    const BlockAddr<FN> a = block_addr<FN>(C, ldc, M, N, rbase, cbase, lane);
     if (beta == 0.0f) {
-#pragma unroll
-        for (int fn = 0; fn < FN; ++fn)
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, alpha * val(fn, i)), rs,
-                                                      off[fn][i], 8 * (i >> 2) * l4, 0);
+        block_store<FN>(a, [&](int fn, int i) { return alpha * val(fn, i); });
         return;
     }
     float c[FN][16];
-#pragma unroll
-    for (int fn = 0; fn < FN; ++fn)
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            c[fn][i] = __builtin_bit_cast(float,
-                                          __builtin_amdgcn_raw_buffer_load_b32(rs, off[fn][i], 8 * (i >> 2) * l4, 0));
-#pragma unroll
-    for (int fn = 0; fn < FN; ++fn)
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            __builtin_amdgcn_raw_buffer_store_b32(
-                __builtin_bit_cast(uint32_t, __builtin_fmaf(alpha, val(fn, i), beta * c[fn][i])), rs, off[fn][i],
-                8 * (i >> 2) * l4, 0);
+    block_load<FN>(a, c);
+    block_store<FN>(a, [&](int fn, int i) { return __builtin_fmaf(alpha, val(fn, i), beta * c[fn][i]); });
 }
 
 // store_blocks_buf, or for single blocks with ldc >= kBufferLdcLimit the
