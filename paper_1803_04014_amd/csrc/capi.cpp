@@ -103,20 +103,26 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         if (need_bt && K % 128 != 0) return MFG_ERR_UNSUPPORTED;
         const int64_t ldk = up(K, 16), ldn = up(N, 16);
         const int64_t bA = mfg_convert_bytes(M, K, ldk, MFG_FP8_E4M3);
-        const int64_t bB = mfg_convert_bytes(K, N, ldn, MFG_FP8_E4M3);
+        // B: row-major codes and their scales, or for the tiled kernels only the
+        // scales, the codes being quantised straight into the K-contiguous layout
+        const int64_t bB = need_bt ? cdiv(K, MFG_FP8_TILE) * cdiv(N, MFG_FP8_TILE) * 4
+                                   : mfg_convert_bytes(K, N, ldn, MFG_FP8_E4M3);
         WsLease ws(s, (size_t)(up(bA, 256) + up(bB, 256) + (need_bt ? bT : 0)));
         if (!ws.ptr()) return ws.status();
         uint8_t* qa = static_cast<uint8_t*>(ws.ptr());
         uint8_t* qb = qa + up(bA, 256);
         float* sa = reinterpret_cast<float*>(qa + mfg_fp8_scale_offset(M, ldk));
-        float* sb = reinterpret_cast<float*>(qb + mfg_fp8_scale_offset(K, ldn));
+        float* sb = need_bt ? reinterpret_cast<float*>(qb) : reinterpret_cast<float*>(qb + mfg_fp8_scale_offset(K, ldn));
         if ((st = launch_quantize_fp8(M, K, static_cast<const float*>(A), lda, qa, ldk, sa, s)) != MFG_OK) return st;
-        if ((st = launch_quantize_fp8(K, N, static_cast<const float*>(B), ldb, qb, ldn, sb, s)) != MFG_OK) return st;
-        a.A = qa, a.lda = ldk, a.B = qb, a.ldb = ldn, a.sa = sa, a.sb = sb;
+        a.A = qa, a.lda = ldk, a.sa = sa, a.sb = sb, a.ldb = ldn;
         if (need_bt) {
             uint8_t* bt = qb + up(bB, 256);
-            if ((st = launch_transpose_b8(K, N, qb, ldn, bt, ldt, s)) != MFG_OK) return st;
-            a.Bt = bt, a.ldbt = ldt;
+            if ((st = launch_quantize_fp8_t(K, N, static_cast<const float*>(B), ldb, bt, ldt, sb, s)) != MFG_OK)
+                return st;
+            a.B = nullptr, a.Bt = bt, a.ldbt = ldt;
+        } else {
+            if ((st = launch_quantize_fp8(K, N, static_cast<const float*>(B), ldb, qb, ldn, sb, s)) != MFG_OK) return st;
+            a.B = qb;
         }
         return launch_gemm_f8(cfg, a, buffer_ldc_ok(ldc), s);
     }

@@ -236,29 +236,40 @@ int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, ui
 }
 
 // ---------------------------------------------------------------- FP8 quant
-// One workgroup per 128 x 128 tile.  Thread t covers columns 4*(t%32)+0..3
-// of rows t/32 + 8 i, i = 0..15: a wavefront reads two full 512-byte rows.
+// One workgroup per 128 x 128 tile.  Thread t holds columns 4 (t % 32) .. +3
+// of rows t / 32 + 8 i, i = 0..15 (a wavefront reads two full 512-byte rows
+// per load) in registers, so the tile is read from memory once: amax over
+// the tile, the tile's power-of-two scale, then the codes.  Elements outside
+// the matrix count as 0 (they cannot raise the amax) and are not written.
+// TRANS: the codes are written transposed (the code of X[r][c] at
+// codes[c * ldo + r]) through LDS in 16-byte row pieces -- B's codes in the
+// K-contiguous layout the tiled FP8 kernels read; `scales` keep the
+// untransposed tile order.
+template <bool TRANS>
 __global__ __launch_bounds__(256) void quant_fp8_kernel(int64_t rows, int64_t cols, const float* X, int64_t ldx,
                                                         uint8_t* codes, int64_t ldo, float* scales, int vec) {
     const int64_t r0 = (int64_t)blockIdx.y * MFG_FP8_TILE, c0 = (int64_t)blockIdx.x * MFG_FP8_TILE;
     const int t = threadIdx.x;
     const int64_t cc = c0 + (t & 31) * 4;
-    const bool full = vec && (cc + 4 <= cols);
-    float amax = 0.0f;
-#pragma unroll 4
-    for (int i = 0; i < 16; ++i) {
-        const int64_t r = r0 + (t >> 5) + 8 * i;
-        if (r >= rows) break;
-        const float* x = X + r * ldx;
-        if (full) {
-            const f32x4 v = *reinterpret_cast<const f32x4*>(x + cc);
-            amax = fmaxf(amax, fmaxf(fmaxf(__builtin_fabsf(v[0]), __builtin_fabsf(v[1])),
-                                     fmaxf(__builtin_fabsf(v[2]), __builtin_fabsf(v[3]))));
-        } else {
-            for (int j = 0; j < 4; ++j)
-                if (cc + j < cols) amax = fmaxf(amax, __builtin_fabsf(x[cc + j]));
+    const bool whole = vec && r0 + MFG_FP8_TILE <= rows && c0 + MFG_FP8_TILE <= cols;
+    f32x4 v[16];
+    if (whole) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            v[i] = *reinterpret_cast<const f32x4*>(X + (r0 + (t >> 5) + 8 * i) * ldx + cc);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t r = r0 + (t >> 5) + 8 * i;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[i][j] = (r < rows && cc + j < cols) ? X[r * ldx + cc + j] : 0.0f;
         }
     }
+    float amax = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        amax = fmaxf(amax, fmaxf(fmaxf(__builtin_fabsf(v[i][0]), __builtin_fabsf(v[i][1])),
+                                 fmaxf(__builtin_fabsf(v[i][2]), __builtin_fabsf(v[i][3]))));
     // max over the workgroup (order-independent)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
@@ -269,22 +280,47 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(int64_t rows, int64_t co
     const int E = fp8_scale_exp(amax);
     const float inv = __builtin_ldexpf(1.0f, -E);
     if (t == 0) scales[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = __builtin_ldexpf(1.0f, E);
-    const bool vec_out = full && (((uintptr_t)codes % 4) == 0) && (ldo % 4 == 0);
-#pragma unroll 4
-    for (int i = 0; i < 16; ++i) {
-        const int64_t r = r0 + (t >> 5) + 8 * i;
-        if (r >= rows) break;
-        const float* x = X + r * ldx;
-        uint8_t* o = codes + r * ldo;
-        if (vec_out) {
-            const f32x4 v = *reinterpret_cast<const f32x4*>(x + cc);
-            uint32_t w = (uint32_t)f32_to_e4m3_sat(v[0] * inv) | ((uint32_t)f32_to_e4m3_sat(v[1] * inv) << 8) |
-                         ((uint32_t)f32_to_e4m3_sat(v[2] * inv) << 16) |
-                         ((uint32_t)f32_to_e4m3_sat(v[3] * inv) << 24);
-            *reinterpret_cast<uint32_t*>(o + cc) = w;
-        } else {
-            for (int j = 0; j < 4; ++j)
-                if (cc + j < cols) o[cc + j] = f32_to_e4m3_sat(x[cc + j] * inv);
+    uint32_t w[16];  // the four codes of each register
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        w[i] = (uint32_t)f32_to_e4m3_sat(v[i][0] * inv) | ((uint32_t)f32_to_e4m3_sat(v[i][1] * inv) << 8) |
+               ((uint32_t)f32_to_e4m3_sat(v[i][2] * inv) << 16) | ((uint32_t)f32_to_e4m3_sat(v[i][3] * inv) << 24);
+    if constexpr (!TRANS) {
+        const bool vec_out = whole && (((uintptr_t)codes % 4) == 0) && (ldo % 4 == 0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t r = r0 + (t >> 5) + 8 * i;
+            uint8_t* o = codes + r * ldo;
+            if (vec_out) {
+                *reinterpret_cast<uint32_t*>(o + cc) = w[i];
+            } else if (r < rows) {
+                for (int j = 0; j < 4; ++j)
+                    if (cc + j < cols) o[cc + j] = (uint8_t)(w[i] >> (8 * j));
+            }
+        }
+    } else {
+        // tile rows (source) x 32 words; row r, word q holds columns 4q .. 4q+3
+        __shared__ uint32_t sq[MFG_FP8_TILE][33];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sq[(t >> 5) + 8 * i][t & 31] = w[i];
+        __syncthreads();
+        // thread t: output row c0 + t / 2 (source column), source rows 64 (t % 2) .. +63
+        const int oc = t >> 1, rb = 64 * (t & 1), sh = 8 * (oc & 3), qw = oc >> 2;
+        u32x4 o[4];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) x |= ((sq[rb + 4 * q + b][qw] >> sh) & 0xFFu) << (8 * b);
+            o[q >> 2][q & 3] = x;
+        }
+        uint8_t* d = codes + (c0 + oc) * ldo + r0 + rb;
+        if (whole && ((uintptr_t)codes % 16) == 0 && ldo % 16 == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) *reinterpret_cast<u32x4*>(d + 16 * k) = o[k];
+        } else if (c0 + oc < cols) {
+            for (int j = 0; j < 64; ++j)
+                if (r0 + rb + j < rows) d[j] = (uint8_t)(o[j >> 4][(j >> 2) & 3] >> (8 * (j & 3)));
         }
     }
 }
@@ -295,8 +331,20 @@ int launch_quantize_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx,
     const int64_t tr = cdiv(rows, MFG_FP8_TILE), tc = cdiv(cols, MFG_FP8_TILE);
     if (tr > 65535) return MFG_ERR_UNSUPPORTED;
     const int vec = aligned(X, ldx, 16, 4);
-    hipLaunchKernelGGL(quant_fp8_kernel, dim3((unsigned)tc, (unsigned)tr), dim3(256), 0, s, rows, cols, X, ldx,
+    hipLaunchKernelGGL(quant_fp8_kernel<false>, dim3((unsigned)tc, (unsigned)tr), dim3(256), 0, s, rows, cols, X, ldx,
                        codes, ldo, scales, vec);
+    MFG_LAUNCH_CHECK();
+    return MFG_OK;
+}
+
+int launch_quantize_fp8_t(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint8_t* codes_t, int64_t ldt,
+                          float* scales, hipStream_t s) {
+    if (rows == 0 || cols == 0) return MFG_OK;
+    const int64_t tr = cdiv(rows, MFG_FP8_TILE), tc = cdiv(cols, MFG_FP8_TILE);
+    if (tr > 65535) return MFG_ERR_UNSUPPORTED;
+    const int vec = aligned(X, ldx, 16, 4);
+    hipLaunchKernelGGL(quant_fp8_kernel<true>, dim3((unsigned)tc, (unsigned)tr), dim3(256), 0, s, rows, cols, X, ldx,
+                       codes_t, ldt, scales, vec);
     MFG_LAUNCH_CHECK();
     return MFG_OK;
 }

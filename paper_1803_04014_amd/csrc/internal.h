@@ -102,6 +102,10 @@ int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, ui
                      uint16_t* resid, int64_t ldo, double* norms, hipStream_t s);
 int launch_quantize_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint8_t* codes,
                         int64_t ldo, float* scales, hipStream_t s);
+// The same codes written transposed (code of X[r][c] at codes_t[c * ldt + r]),
+// scales in the untransposed tile order.
+int launch_quantize_fp8_t(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint8_t* codes_t, int64_t ldt,
+                          float* scales, hipStream_t s);
 int launch_error_norms(int64_t M, int64_t N, const float* C, int64_t ldc, const double* R,
                        int64_t ldr, double* out4, hipStream_t s);
 int launch_count_mismatch(int64_t M, int64_t N, const float* C, int64_t ldc, const float* R,
