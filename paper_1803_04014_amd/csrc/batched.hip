@@ -52,12 +52,18 @@ __device__ __forceinline__ u32x4 slab_read_b(const uint16_t* slab, int lane) {
     return u32x4{a[0], a[1], b[0], b[1]};
 }
 
-template <int KIND>
+// PAIR (M, N <= 16): two problems share one 32x32x16 MFMA -- problem 2j in
+// rows and columns 0..15, problem 2j + 1 in 16..31 (A rows stacked, B
+// columns side by side); the diagonal blocks of the product are the two
+// results and the off-diagonal blocks are discarded.  Every element is the
+// same dot product, in the same order, as the one-problem MFMA.
+template <int KIND, bool PAIR>
 __global__ __launch_bounds__(256) void gemm16_batched_lds(Gemm16Args p, int64_t count, int vecC) {
     using T = KT<KIND>;
     constexpr int SLAB = 16 * 32;           // halfs per B plane slab
     constexpr int CROW = 33;                // floats per padded C row in LDS
     constexpr int WAVE_LDS = T::NPB * SLAB * 2 + 32 * CROW * 4;  // bytes
+    constexpr int PER = PAIR ? 2 : 1;        // problems per wavefront step
     __shared__ __attribute__((aligned(16))) unsigned char lds[4 * WAVE_LDS];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint16_t* slab = reinterpret_cast<uint16_t*>(lds + wid * WAVE_LDS);
@@ -65,31 +71,37 @@ __global__ __launch_bounds__(256) void gemm16_batched_lds(Gemm16Args p, int64_t 
     const int r = lane & 31, g = lane >> 5;
     const int64_t M = p.M, N = p.N, K = p.K;
     const int krow = lane >> 2, c8 = (lane & 3) * 8;  // this lane's piece of a B chunk
+    // PAIR: A row r belongs to problem r / 16 (row r % 16), B columns c8 ..
+    // c8 + 7 to problem c8 / 16 (columns c8 % 16 ..)
+    const int pa = PAIR ? (r >> 4) : 0, ar = PAIR ? (r & 15) : r;
+    const int pb = PAIR ? (c8 >> 4) : 0, bc = PAIR ? (c8 & 15) : c8;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t b = (int64_t)blockIdx.x * 4 + wid; b < count; b += nwaves) {
+    for (int64_t b0 = ((int64_t)blockIdx.x * 4 + wid) * PER; b0 < count; b0 += nwaves * PER) {
+        const bool has_a = b0 + pa < count, has_b = b0 + pb < count;
         const uint16_t* Ap[2];
         const uint16_t* Bp[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            Ap[q] = (q < T::NPA) ? p.A[q] + b * p.sA : nullptr;
-            Bp[q] = (q < T::NPB) ? p.B[q] + b * p.sB : nullptr;
+            Ap[q] = (q < T::NPA) ? p.A[q] + (b0 + pa) * p.sA : nullptr;
+            Bp[q] = (q < T::NPB) ? p.B[q] + (b0 + pb) * p.sB : nullptr;
         }
         f32x16 hi = {}, lo = {}, rr = {};
         for (int64_t k0 = 0; k0 < K; k0 += 16) {
             const int64_t kb = k0 + g * 8;
             u32x4 a[2] = {zero4(), zero4()}, bb[2] = {zero4(), zero4()};
 #pragma unroll
-            for (int q = 0; q < T::NPA; ++q) a[q] = load_row8(Ap[q], r < M, r * p.lda + kb, K - kb, true);
+            for (int q = 0; q < T::NPA; ++q) a[q] = load_row8(Ap[q], has_a && ar < M, ar * p.lda + kb, K - kb, true);
             const int64_t kr = k0 + krow;
 #pragma unroll
             for (int q = 0; q < T::NPB; ++q) {
                 u32x4 v;
-                if (kr < K && c8 + 8 <= N) {
-                    v = *reinterpret_cast<const u32x4*>(Bp[q] + kr * p.ldb + c8);
+                if (has_b && kr < K && bc + 8 <= N) {
+                    v = *reinterpret_cast<const u32x4*>(Bp[q] + kr * p.ldb + bc);
                 } else {
                     uint16_t e[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) e[j] = (kr < K && c8 + j < N) ? Bp[q][kr * p.ldb + c8 + j] : (uint16_t)0;
+                    for (int j = 0; j < 8; ++j)
+                        e[j] = (has_b && kr < K && bc + j < N) ? Bp[q][kr * p.ldb + bc + j] : (uint16_t)0;
                     v = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
                 }
                 *reinterpret_cast<u32x4*>(slab + q * SLAB + krow * 32 + c8) = v;
@@ -104,13 +116,14 @@ __global__ __launch_bounds__(256) void gemm16_batched_lds(Gemm16Args p, int64_t 
 #pragma unroll
         for (int i = 0; i < 16; ++i) ct[mfma_out_row(i, lane) * CROW + r] = combine_at<KIND>(hi, lo, rr, i);
         lds_wait();
-        float* C = p.C + b * p.sC;
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int row = it * 8 + (lane >> 3), c4 = (lane & 7) * 4;
-            if (row >= M) continue;
-            const float* src = ct + row * CROW + c4;
-            float* dst = C + row * p.ldc + c4;
+        for (int it = 0; it < (PAIR ? 2 : 4); ++it) {
+            // PAIR: pass `it` stores problem b0 + it, rows lane / 4, columns 4 (lane % 4) ..
+            const int row = PAIR ? (lane >> 2) : it * 8 + (lane >> 3), c4 = PAIR ? (lane & 3) * 4 : (lane & 7) * 4;
+            const int64_t bq = PAIR ? b0 + it : b0;
+            if (row >= M || bq >= count) continue;
+            const float* src = ct + (PAIR ? (16 * it + row) * CROW + 16 * it + c4 : row * CROW + c4);
+            float* dst = p.C + bq * p.sC + row * p.ldc + c4;
             if (vecC && c4 + 4 <= N) {
                 f32x4 v = {src[0], src[1], src[2], src[3]};
                 if (p.beta == 0.0f) {
@@ -141,20 +154,22 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
     const int v = vec_ok ? 1 : 0;
     if (vec_ok) {  // 16-byte aligned A and B rows: the LDS-staged kernel
         const int vc = (((uintptr_t)a.C % 16) == 0 && a.ldc % 4 == 0 && a.sC % 4 == 0) ? 1 : 0;
+        const bool pair = a.M <= 16 && a.N <= 16;  // two problems per MFMA
+        const unsigned g2 = pair ? (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(count, 8), cap)) : grid;
+#define MFG_BATCHED_LDS(KIND_)                                                                                     \
+    if (pair)                                                                                                       \
+        hipLaunchKernelGGL((gemm16_batched_lds<KIND_, true>), dim3(g2), dim3(256), 0, s, a, count, vc);          \
+    else                                                                                                            \
+        hipLaunchKernelGGL((gemm16_batched_lds<KIND_, false>), dim3(grid), dim3(256), 0, s, a, count, vc);
         switch (kind) {
-            case K_F16: hipLaunchKernelGGL(gemm16_batched_lds<K_F16>, dim3(grid), dim3(256), 0, s, a, count, vc); break;
-            case K_BF16: hipLaunchKernelGGL(gemm16_batched_lds<K_BF16>, dim3(grid), dim3(256), 0, s, a, count, vc); break;
-            case K_REFINE_A:
-                hipLaunchKernelGGL(gemm16_batched_lds<K_REFINE_A>, dim3(grid), dim3(256), 0, s, a, count, vc);
-                break;
-            case K_SPLIT3:
-                hipLaunchKernelGGL(gemm16_batched_lds<K_SPLIT3>, dim3(grid), dim3(256), 0, s, a, count, vc);
-                break;
-            case K_SPLIT4:
-                hipLaunchKernelGGL(gemm16_batched_lds<K_SPLIT4>, dim3(grid), dim3(256), 0, s, a, count, vc);
-                break;
+            case K_F16: MFG_BATCHED_LDS(K_F16) break;
+            case K_BF16: MFG_BATCHED_LDS(K_BF16) break;
+            case K_REFINE_A: MFG_BATCHED_LDS(K_REFINE_A) break;
+            case K_SPLIT3: MFG_BATCHED_LDS(K_SPLIT3) break;
+            case K_SPLIT4: MFG_BATCHED_LDS(K_SPLIT4) break;
             default: return MFG_ERR_INVALID_ARG;
         }
+#undef MFG_BATCHED_LDS
         MFG_LAUNCH_CHECK();
         return MFG_OK;
     }
