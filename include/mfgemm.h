@@ -167,7 +167,7 @@ typedef struct mfg_problem {
 typedef struct mfg_grouped_plan mfg_grouped_plan;
 
 /* Build a plan: validates every problem (M, N <= 2^24, K < 2^31), splits it
- * into 64 x 64 output tiles (work items, one workgroup each), orders them by
+ * into 128 x 128 output tiles (work items, one workgroup each), orders them by
  * decreasing K, and uploads the work list: one self-contained record per
  * item (device memory owned by the plan).  Rows of A and B that are 16-byte
  * aligned with ld a multiple of 8 are read in whole 16-byte pieces, which may
@@ -252,7 +252,7 @@ int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode);
  * free, the oldest admitted request takes up to max_group admitted requests
  * of its mode, alpha and beta into one group: operands are converted on the
  * slot's stream, small FP16/BF16 problems (M*N < 512*512, at most 256 tiles
- * of 64 x 64) run as one persistent grouped launch, the others one by one; one
+ * of 128 x 128) run as one persistent grouped launch, the others one by one; one
  * completion event per group.  Footprint: the mode's converted A (ld = K
  * rounded up to 8, or to 16 for FP8) and B (ld = N rounded likewise), each
  * rounded up to 256 bytes; 0 for MFG_F32 and for empty problems.  The fixed

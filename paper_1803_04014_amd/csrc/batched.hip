@@ -192,9 +192,11 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
 }
 
 // ------------------------------------------------------------------ grouped
-// Each workgroup (four wavefronts) takes work items -- one 64 x 64 output
-// tile of one problem -- with a stride over its XCD's range of the work
-// list; wavefront (wm, wn) computes the 32 x 32 quarter (wm, wn).  The work
+// Each workgroup (four wavefronts) takes work items -- one kGroupedTile
+// square output tile of one problem (128: measured 13% faster than 64 on
+// 4096 uneven problems, with two workgroups per CU instead of three) --
+// with a stride over its XCD's range of the work list; wavefront (wm, wn)
+// computes the quarter (wm, wn).  The work
 // list is denormalised: each record carries the tile's operand pointers,
 // leading dimensions and extent, and 16 lanes of one load fetch one record,
 // so one load brings four records; two such windows are kept ahead of the
@@ -216,8 +218,11 @@ typedef __attribute__((address_space(1))) const uint16_t g_u16;
 typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
 typedef __attribute__((address_space(1))) const uint32_t g_u32;
 typedef __attribute__((address_space(1))) float g_f32;
-constexpr int kGroupedWGPerCU = 3;  // resident at 3 waves per SIMD (<= 168 VGPRs, 32 KB of LDS each)
-static_assert(kGroupedTile == 64, "two 32 x 32 MFMA blocks per tile side");
+// Occupancy of the grouped kernel: workgroups per CU (kGroupedTile 64: 32 KB
+// of LDS each, <= 168 VGPRs; 128: 64 KB, <= 256 VGPRs).
+constexpr int kGroupedWGPerCU = kGroupedTile == 64 ? 3 : 2;
+constexpr int kGroupedWavesPerEU = kGroupedWGPerCU;
+static_assert(kGroupedTile == 64 || kGroupedTile == 128, "wavefront tiles of 1 or 2 MFMA blocks a side");
 
 // One work record in scalar registers.
 struct GItem {
@@ -253,12 +258,16 @@ __device__ __forceinline__ void grouped_barrier() {
 }
 
 template <int KIND, bool VEC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gemm16_grouped(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGroupedWavesPerEU))) void gemm16_grouped(
     const GroupedWork* work, GroupedSplit split, float alpha, float beta) {
+    constexpr int TT = kGroupedTile, TH = TT / 2;  // workgroup tile, wavefront tile
+    constexpr int FM = TH / 32, FN = TH / 32;       // 32 x 32 MFMA blocks per wavefront
+    constexpr int PA = TT / 32, PB = TT / 32;       // 16-byte pieces per thread and block: A, B
+    constexpr int BPR = TT / 8;                     // pieces per B row
     const int64_t* off = split.off[VEC ? 0 : 1];
-    // per buffer: A 64 rows x 64, B 4 chunks x 2 column halves x (16 x 32)
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][64 * 64];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][4][2][16 * 32];
+    // per buffer: A TT rows x 64, B 4 chunks x TT/32 column slabs x (16 x 32)
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][TT * 64];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][4][TT / 32][16 * 32];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), wm = wid >> 1, wn = wid & 1;
     const int xcd = blockIdx.x % kXcds;
@@ -279,55 +288,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
         return window_item(d < 4 ? win0 : win1, (int)(d & 3));
     };
 
-    // This thread's two pieces of each operand block.  Aligned items (the
-    // VEC list: vec records only) load every piece that starts inside the operand as a whole 16-byte
-    // piece: with 16-byte aligned rows and ld a multiple of 8 the piece lies
-    // in the same aligned 16 bytes as its first element, inside the row's
-    // ld extent (and never across a page).  A's elements at or beyond K are
-    // then zeroed in registers; B's columns at or beyond the tile's width
-    // only reach discarded outputs, and B rows at or beyond K, like A rows
-    // beyond the tile, read 16 zero bytes.  So every block issues the same
-    // four loads and no branch.  Unaligned items load element by element.
-    auto load_block = [&](const GItem& t, int kb0, u32x4 (&a)[2], u32x4 (&b)[2], int (&nv)[2]) {
+    // This thread's pieces of each operand block (piece p = tid + 256 j: A row
+    // p / 8, K columns 8 (p % 8) ..; B K row p / BPR, columns 8 (p % BPR) ..).
+    // Aligned items (the VEC list: vec records only) load every piece that
+    // starts inside the operand as a whole 16-byte piece: with 16-byte
+    // aligned rows and ld a multiple of 8 the piece lies in the same aligned
+    // 16 bytes as its first element, inside the row's ld extent (and never
+    // across a page).  A's elements at or beyond K are then zeroed in
+    // registers; B's columns at or beyond the tile's width only reach
+    // discarded outputs, and B rows at or beyond K, like A rows beyond the
+    // tile, read 16 zero bytes.  So every block issues the same loads and no
+    // branch.  Unaligned items load element by element.
+    auto load_block = [&](const GItem& t, int kb0, u32x4 (&a)[PA], u32x4 (&b)[PB], int (&nv)[PA]) {
         if constexpr (VEC) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < PA; ++j) {
                 const int p = tid + 256 * j, row = p >> 3, ka = kb0 + 8 * (p & 7);
-                const int kr = kb0 + row, cb = 8 * (p & 7);  // B: K row kb0 + p / 8, columns cb .. cb + 7
-                const bool fa = row < t.rows && ka < t.K, fb = kr < t.K && cb < t.cols;
+                const bool fa = row < t.rows && ka < t.K;
                 a[j] = *(const g_u32x4*)(fa ? t.A + row * t.lda + ka : (const g_u16*)kZero16);
-                b[j] = *(const g_u32x4*)(fb ? t.B + kr * t.ldb + cb : (const g_u16*)kZero16);
                 nv[j] = t.K - ka;  // valid elements of the A piece (masked when it is stored)
+            }
+#pragma unroll
+            for (int j = 0; j < PB; ++j) {
+                const int p = tid + 256 * j, kr = kb0 + p / BPR, cb = 8 * (p % BPR);
+                const bool fb = kr < t.K && cb < t.cols;
+                b[j] = *(const g_u32x4*)(fb ? t.B + kr * t.ldb + cb : (const g_u16*)kZero16);
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < PA; ++j) {
                 const int p = tid + 256 * j, row = p >> 3, ka = kb0 + 8 * (p & 7);
-                const int kr = kb0 + row, cb = 8 * (p & 7);
-                uint16_t e[8], f[8];
+                uint16_t e[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < 8; ++q)
                     e[q] = (row < t.rows && ka + q < t.K) ? t.A[row * t.lda + ka + q] : (uint16_t)0;
-                    f[q] = (kr < t.K && cb + q < t.cols) ? t.B[kr * t.ldb + cb + q] : (uint16_t)0;
-                }
                 a[j] = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
-                b[j] = u32x4{pack2(f[0], f[1]), pack2(f[2], f[3]), pack2(f[4], f[5]), pack2(f[6], f[7])};
                 nv[j] = 8;
+            }
+#pragma unroll
+            for (int j = 0; j < PB; ++j) {
+                const int p = tid + 256 * j, kr = kb0 + p / BPR, cb = 8 * (p % BPR);
+                uint16_t f[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    f[q] = (kr < t.K && cb + q < t.cols) ? t.B[kr * t.ldb + cb + q] : (uint16_t)0;
+                b[j] = u32x4{pack2(f[0], f[1]), pack2(f[2], f[3]), pack2(f[4], f[5]), pack2(f[6], f[7])};
             }
         }
     };
-    auto store_block = [&](int buf, const u32x4 (&a)[2], const u32x4 (&b)[2], const int (&nv)[2]) {
+    auto store_block = [&](int buf, const u32x4 (&a)[PA], const u32x4 (&b)[PB], const int (&nv)[PA]) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < PA; ++j) {
             const int p = tid + 256 * j, row = p >> 3, c = p & 7;
             u32x4 am = a[j];
 #pragma unroll
             for (int d = 0; d < 4; ++d)
                 am[d] &= (2 * d < nv[j] ? 0xFFFFu : 0u) | (2 * d + 1 < nv[j] ? 0xFFFF0000u : 0u);
             *reinterpret_cast<u32x4*>(&As[buf][row * 64 + ((c ^ swz<8>(row)) * 8)]) = am;
-            // B row `row` of the block: chunk row / 16, slab row row % 16,
-            // column half c / 4, columns 8 (c % 4) .. +7 of the half
-            *reinterpret_cast<u32x4*>(&Bs[buf][row >> 4][c >> 2][(row & 15) * 32 + 8 * (c & 3)]) = b[j];
+        }
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            // B row kr of the block: chunk kr / 16, slab row kr % 16, column
+            // slab c / 4, columns 8 (c % 4) .. +7 of the slab
+            const int p = tid + 256 * j, kr = p / BPR, c = p % BPR;
+            *reinterpret_cast<u32x4*>(&Bs[buf][kr >> 4][c >> 2][(kr & 15) * 32 + 8 * (c & 3)]) = b[j];
         }
     };
 
@@ -347,8 +371,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
             }
         }
     };
-    u32x4 ra[2][2], rb[2][2];  // register sets of the two blocks in flight
-    int rn[2][2];
+    u32x4 ra[2][PA], rb[2][PB];  // register sets of the two blocks in flight
+    int rn[2][PA];
     // prologue: block 0 into LDS buffer 0, block 1 into registers
     load_block(ld, 0, ra[0], rb[0], rn[0]);
     store_block(0, ra[0], rb[0], rn[0]);
@@ -357,7 +381,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
     advance_load();
     grouped_barrier();
 
-    f32x16 hi = {}, lo = {}, rr = {};
+    f32x16 hi[FM][FN], lo[FM][FN], rr[FM][FN];
+    auto clear = [&]() {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) hi[i][j] = f32x16{}, lo[i][j] = f32x16{}, rr[i][j] = f32x16{};
+    };
+    clear();
     // one block of the stream; BUF: its LDS buffer and register set (block
     // parity).  Returns true after the last item's last block.
     auto step = [&](auto bufc) -> bool {
@@ -370,25 +401,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (kb0 + 16 * c >= cur.K) break;
-            const int row = wm * 32 + (lane & 31), piece = 2 * c + (lane >> 5);
-            u32x4 aa[2] = {*reinterpret_cast<const u32x4*>(&As[buf][row * 64 + ((piece ^ swz<8>(row)) * 8)]), zero4()};
-            u32x4 bb[2] = {slab_read_b(Bs[buf][c][wn], lane), zero4()};
-            mma_step<KIND>(aa, bb, hi, lo, rr);
+            u32x4 aa[FM][2], bb[FN][2];
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) {
+                const int row = wm * TH + fm * 32 + (lane & 31), piece = 2 * c + (lane >> 5);
+                aa[fm][0] = *reinterpret_cast<const u32x4*>(&As[buf][row * 64 + ((piece ^ swz<8>(row)) * 8)]);
+                aa[fm][1] = zero4();
+            }
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) bb[fn][0] = slab_read_b(Bs[buf][c][wn * FN + fn], lane), bb[fn][1] = zero4();
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn) mma_step<KIND>(aa[fm], bb[fn], hi[fm][fn], lo[fm][fn], rr[fm][fn]);
         }
         // block s + 1 (loaded during block s - 1) into the other buffer
         store_block(buf ^ 1, ra[buf ^ 1], rb[buf ^ 1], rn[buf ^ 1]);
         advance_load();
         bool done = false;
         if (cbk + 1 >= grouped_blocks(cur.K)) {  // the item's last block: its C, then the next item
-            auto val = [&](int, int e) { return combine_at<KIND>(hi, lo, rr, e); };
-            g_f32* cq = cur.C + (int64_t)(wm * 32) * cur.ldc + wn * 32;
-            // the VEC list holds only ldc < kBufferLdcLimit: no 64-bit path
-            // (whose C reads may stay unconsumed on masked lanes)
-            if constexpr (VEC)
-                store_blocks_buf<1>(cq, cur.ldc, cur.rows - wm * 32, cur.cols - wn * 32, 0, 0, lane, alpha, beta, val);
-            else
-                store_blocks<1>(cq, cur.ldc, cur.rows - wm * 32, cur.cols - wn * 32, 0, 0, lane, alpha, beta, val);
-            hi = f32x16{}, lo = f32x16{}, rr = f32x16{};
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) {
+                const int r0 = wm * TH + fm * 32;
+                g_f32* cq = cur.C + (int64_t)r0 * cur.ldc + wn * TH;
+                auto val = [&](int fn, int e) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], e); };
+                // the VEC list holds only ldc < kBufferLdcLimit: no 64-bit path
+                // (whose C reads may stay unconsumed on masked lanes)
+                if constexpr (VEC) {
+                    store_blocks_buf<FN>(cq, cur.ldc, cur.rows - r0, cur.cols - wn * TH, 0, 0, lane, alpha, beta, val);
+                } else {
+#pragma unroll
+                    for (int fn = 0; fn < FN; ++fn)
+                        store_blocks<1>(cq + fn * 32, cur.ldc, cur.rows - r0, cur.cols - wn * TH - fn * 32, 0, 0, lane,
+                                        alpha, beta, [&](int, int e) { return val(fn, e); });
+                }
+            }
+            clear();
             cbk = 0;
             if (++ci >= count) {
                 done = true;

@@ -128,7 +128,7 @@ struct GroupedDesc {  // one problem (host side; the kernel reads GroupedWork)
 constexpr int64_t kBufferLdcLimit = int64_t(1) << 24;
 inline bool buffer_ldc_ok(int64_t ldc) { return ldc < kBufferLdcLimit; }
 
-constexpr int kGroupedTile = 64;  // output tile of a grouped work item (one workgroup)
+constexpr int kGroupedTile = 128;  // output tile of a grouped work item (one workgroup)
 // One kGroupedTile x kGroupedTile output tile with everything its workgroup
 // reads (16 dwords, so that 16 lanes fetch one record with one load each).
 struct GroupedWork {
@@ -136,7 +136,7 @@ struct GroupedWork {
     const uint16_t* B;  // column n0 of its B
     float* C;           // element (m0, n0) of its C
     int64_t lda, ldb, ldc;
-    int32_t rows, cols;  // of the tile inside the problem: min(64, M - m0), min(64, N - n0)
+    int32_t rows, cols;  // of the tile inside the problem: min(128, M - m0), min(128, N - n0)
     int32_t K, vec;
 };
 static_assert(sizeof(GroupedWork) == 64, "a work record is 16 dwords");

@@ -94,8 +94,8 @@ def test_grouped_equals_solo_and_graph_replays():
     probs, host_ops = _grouped_problems(300, 16, 200, 6, unaligned_every=7)
     plan = mfg.GroupedPlan(probs, "f16")
     info = plan.info()
-    # one work item per 64 x 64 output tile
-    assert info["work_items"] == sum(-(-p[0].shape[0] // 64) * -(-p[1].shape[1] // 64) for p in probs)
+    # one work item per 128 x 128 output tile
+    assert info["work_items"] == sum(-(-p[0].shape[0] // 128) * -(-p[1].shape[1] // 128) for p in probs)
     plan.run(1.0, 0.0)
     first = [host(p[2]).copy() for p in probs]
     for i in range(300):
