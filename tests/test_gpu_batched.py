@@ -29,7 +29,8 @@ def _solo(mode, A, B, C0, alpha, beta, preconverted):
 
 @pytest.mark.parametrize("mode,shape,count", [
     ("f16", (16, 16, 16), 1000), ("bf16", (16, 16, 16), 333), ("f16", (17, 9, 100), 257), ("f16", (9, 13, 20), 101),
-    ("f16", (64, 64, 64), 300), ("f16", (33, 70, 48), 65), ("f32", (16, 16, 16), 200), ("f32", (64, 64, 64), 50),
+    ("f16", (64, 64, 64), 300), ("f16", (33, 70, 48), 65), ("bf16", (128, 100, 72), 37), ("f16", (129, 64, 64), 9),
+    ("f32", (16, 16, 16), 200), ("f32", (64, 64, 64), 50),
 ])
 def test_batched_equals_solo_and_oracle(mode, shape, count):
     M, N, K = shape
@@ -43,9 +44,8 @@ def test_batched_equals_solo_and_oracle(mode, shape, count):
     mfg.gemm_batched(dA, dB, dC, 1.5, 0.5, mode=mode)
     got = host(dC)
     pre = mode != "f32"
-    # every problem against its solo run (problems M, N <= 16 run two to an MFMA)
-    checked = range(count) if M <= 16 and N <= 16 else list(range(0, count, max(1, count // 12))) + [count - 1]
-    for b in checked:
+    # every problem against its solo run (M, N <= 16 run two to an MFMA)
+    for b in range(count):
         solo = host(_solo(mode, dA[b], dB[b], dev(C0[b]), 1.5, 0.5, pre))
         assert np.array_equal(got[b].view(np.uint32), solo.view(np.uint32)), f"problem {b} differs from solo"
         if b % 50 == 0 or b == count - 1:
