@@ -357,6 +357,26 @@ def main() -> int:
             ms = timed(lambda: mfg.gemm(a, b, c, 1.0, 1.0, mode="f16", preconverted=True), 20)
             sweep[str(n)] = round(2.0 * n ** 3 / ms / 1e9, 1)
         ex["f16_sweep_tflops"] = sweep
+        # the HBM-bound steps at N x N: operand rounding, split with FP64 norms,
+        # FP8 tile quantisation, FP64 error norms (algorithmic bytes per element:
+        # 4 + 2, 4 + 2 + 2, 4 + 1, 4 + 8)
+        h16 = torch.empty((N, N), dtype=torch.float16, device=dev)
+        r16 = torch.empty((N, N), dtype=torch.float16, device=dev)
+        q8 = torch.empty((N, N), dtype=torch.uint8, device=dev)
+        sc = torch.empty((N // 128 + 1) * (N // 128 + 1), dtype=torch.float32, device=dev)
+        nrm = torch.zeros(4, dtype=torch.float64, device=dev)
+        cref = dC0.double()
+        hbm = {}
+        for name, fn, per_elem in (
+                ("round_f16", lambda: mfg.round_f16(dA32, h16), 6),
+                ("split_f16_norms", lambda: mfg.split_f16(dA32, h16, r16, nrm), 8),
+                ("quantize_fp8", lambda: mfg.quantize_fp8(dA32, q8, sc), 5),
+                ("error_norms", lambda: mfg.error_norms(dC0, cref, nrm), 12)):
+            ms = timed(fn, 10)
+            gbs = per_elem * N * N / ms / 1e6
+            hbm[name] = {"us": round(ms * 1e3, 1), "gb_s": round(gbs, 1), "pct_hbm": round(100 * gbs / HBM_GBS, 1)}
+        ex["hbm_steps_n8192"] = hbm
+        del h16, r16, q8, sc, cref
         # batched 65536 x 16^3 and 16384 x 64^3 (FP16 in, FP32 out, alpha=1, beta=0)
         for cnt, s in ((65536, 16), (16384, 64)):
             a16, b16 = (torch.empty((cnt, s, s), dtype=torch.float16, device=dev).uniform_(-1, 1) for _ in range(2))

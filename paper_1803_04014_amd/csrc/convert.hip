@@ -213,7 +213,10 @@ __global__ __launch_bounds__(kEltThreads) void split16_kernel(int64_t rows, int6
 
 int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head, uint16_t* resid,
                      int64_t ldo, double* norms, hipStream_t s) {
+    // with norms, at most 1024 row groups: a block reduces several rows, so the
+    // per-block tree and the single-block second stage stay small
     dim3 grid = elt_grid(rows, cols);
+    if (norms != nullptr) grid.y = (unsigned)(rows < 1024 ? (rows > 0 ? rows : 1) : 1024);
     Red4* part = nullptr;
     const int64_t nparts = (int64_t)grid.x * grid.y;
     if (norms != nullptr) {

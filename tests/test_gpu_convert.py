@@ -59,9 +59,10 @@ def test_round_bf16_bit_exact():
     assert np.all((got[nan] & 0x7F80) == 0x7F80) and np.all((got[nan] & 0x7F) != 0)
 
 
-def test_split_bit_exact_and_norms():
+@pytest.mark.parametrize("shape", [(512, 640), (3000, 2500)])
+def test_split_bit_exact_and_norms(shape):
     rng = np.random.default_rng(1)
-    X = (np.where(rng.random((512, 640)) < 0.5, -1, 1) * np.exp2(rng.uniform(-30, 15.9, (512, 640)))).astype(np.float32)
+    X = (np.where(rng.random(shape) < 0.5, -1, 1) * np.exp2(rng.uniform(-30, 15.9, shape))).astype(np.float32)
     h = torch.empty(X.shape, dtype=torch.int16, device=DEV)
     r = torch.empty(X.shape, dtype=torch.int16, device=DEV)
     norms = torch.zeros(4, dtype=torch.float64, device=DEV)
