@@ -387,6 +387,22 @@ def main() -> int:
                                           "hbm_gbs": round(byts / ms / 1e6, 1),
                                           "pct_hbm": round(100 * byts / ms / 1e6 / HBM_GBS, 1), "us": round(ms * 1e3, 2)}
             del a16, b16, c
+        # autotuner: default configuration against the tuned one on a few shapes
+        tune = {}
+        mfg.lib().mfg_tune_clear()
+        for (m_, n_, k_) in ((4096, 4096, 4096), (8192, 2048, 4096), (2048, 2048, 8192), (1536, 1536, 1536)):
+            a = dA[:m_, :k_].contiguous()
+            b = dB[:k_, :n_].contiguous()
+            c = torch.empty((m_, n_), dtype=torch.float32, device=dev)
+            ms_def = timed(lambda: mfg.gemm(a, b, c, 1.0, 0.0, mode="f16", preconverted=True), 10)
+            best, _ = mfg.autotune(a, b, c, "f16", reps=3, preconverted=True)
+            ms_tuned = timed(lambda: mfg.gemm(a, b, c, 1.0, 0.0, mode="f16", preconverted=True), 10)
+            fl = 2.0 * m_ * n_ * k_
+            tune[f"{m_}x{n_}x{k_}"] = {"default_tflops": round(fl / ms_def / 1e9, 1),
+                                       "tuned_tflops": round(fl / ms_tuned / 1e9, 1),
+                                       "tuned_config": mfg.config_name("f16", best)}
+        mfg.lib().mfg_tune_clear()
+        ex["autotune_f16"] = tune
         # grouped: 4096 problems, M, N, K log-uniform in [16, 512]
         dims = workloads.loguniform_dims(6, 4096, 16, 512)
         probs = []
