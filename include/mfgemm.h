@@ -150,10 +150,14 @@ int mfg_gemm_batched(int64_t count, int64_t M, int64_t N, int64_t K,
 
 /* --------------------------------------------------------- grouped GEMM
  * Thousands of GEMMs of different shapes in one persistent launch (paper
- * Sec. IV.B, batched GEMM, generalised to uneven shapes).  Modes MFG_F16 and
- * MFG_BF16 with preconverted 16-bit operands; other modes are
- * MFG_ERR_UNSUPPORTED.  Each problem's result is bitwise that of mfg_gemm on
- * the problem alone.  The descriptor array is host memory; the plan copies it
+ * Sec. IV.B, batched GEMM, generalised to uneven shapes).  Operands are
+ * always in the mode's preconverted storage form (the MFG_IN_PRECONVERTED
+ * flag is implied): MFG_F16 and MFG_BF16 16-bit matrices, and for the
+ * refined modes (paper Sec. V, Eq. 1 and Eq. 2: MFG_F16_REFINE_A,
+ * MFG_F16_SPLIT3, MFG_F16_SPLIT4) head plane then residual plane, at
+ * A + M*lda and (two-sided splits) B + K*ldb elements.  MFG_F32 and
+ * MFG_FP8_E4M3 are MFG_ERR_UNSUPPORTED.  Each problem's result is bitwise
+ * that of mfg_gemm (same mode, preconverted) on the problem alone.  The descriptor array is host memory; the plan copies it
  * to the device, so it may be freed after mfg_grouped_plan_create.
  */
 typedef struct mfg_problem {

@@ -219,9 +219,13 @@ typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
 typedef __attribute__((address_space(1))) const uint32_t g_u32;
 typedef __attribute__((address_space(1))) float g_f32;
 // Occupancy of the grouped kernel: workgroups per CU (kGroupedTile 64: 32 KB
-// of LDS each, <= 168 VGPRs; 128: 64 KB, <= 256 VGPRs).
+// of LDS each, <= 168 VGPRs; 128: 64 KB, <= 256 VGPRs).  The refined kinds
+// stage a second operand plane (96 or 128 KB of LDS at 128): one per CU.
 constexpr int kGroupedWGPerCU = kGroupedTile == 64 ? 3 : 2;
-constexpr int kGroupedWavesPerEU = kGroupedWGPerCU;
+template <int KIND>
+constexpr int grouped_wg_per_cu() {
+    return (KT<KIND>::NPA > 1 || KT<KIND>::NPB > 1) ? 1 : kGroupedWGPerCU;
+}
 static_assert(kGroupedTile == 64 || kGroupedTile == 128, "wavefront tiles of 1 or 2 MFMA blocks a side");
 
 // One work record in scalar registers.
@@ -257,17 +261,20 @@ __device__ __forceinline__ void grouped_barrier() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// `planes` (refined kinds only): per work item, the element offsets of the
+// residual planes of A and B from their head planes.
 template <int KIND, bool VEC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGroupedWavesPerEU))) void gemm16_grouped(
-    const GroupedWork* work, GroupedSplit split, float alpha, float beta) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_per_cu<KIND>()))) void gemm16_grouped(
+    const GroupedWork* work, const int64_t* planes, GroupedSplit split, float alpha, float beta) {
     constexpr int TT = kGroupedTile, TH = TT / 2;  // workgroup tile, wavefront tile
     constexpr int FM = TH / 32, FN = TH / 32;       // 32 x 32 MFMA blocks per wavefront
     constexpr int PA = TT / 32, PB = TT / 32;       // 16-byte pieces per thread and block: A, B
     constexpr int BPR = TT / 8;                     // pieces per B row
+    constexpr int NA = KT<KIND>::NPA, NB = KT<KIND>::NPB;  // operand planes (head, residual)
     const int64_t* off = split.off[VEC ? 0 : 1];
-    // per buffer: A TT rows x 64, B 4 chunks x TT/32 column slabs x (16 x 32)
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][TT * 64];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][4][TT / 32][16 * 32];
+    // per plane and buffer: A TT rows x 64, B 4 chunks x TT/32 column slabs x (16 x 32)
+    __shared__ __attribute__((aligned(16))) uint16_t As[NA][2][TT * 64];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[NB][2][4][TT / 32][16 * 32];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), wm = wid >> 1, wn = wid & 1;
     const int xcd = blockIdx.x % kXcds;
@@ -299,59 +306,89 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGroupedWav
     // discarded outputs, and B rows at or beyond K, like A rows beyond the
     // tile, read 16 zero bytes.  So every block issues the same loads and no
     // branch.  Unaligned items load element by element.
-    auto load_block = [&](const GItem& t, int kb0, u32x4 (&a)[PA], u32x4 (&b)[PB], int (&nv)[PA]) {
+    // Residual planes sit at element offsets pa (A) and pb (B) from the head
+    // planes of the item being loaded (refined kinds; read with the item).
+    int64_t pa = 0, pb = 0;
+    auto load_block = [&](const GItem& t, int kb0, u32x4 (&a)[NA][PA], u32x4 (&b)[NB][PB], int (&nv)[PA]) {
         if constexpr (VEC) {
 #pragma unroll
             for (int j = 0; j < PA; ++j) {
                 const int p = tid + 256 * j, row = p >> 3, ka = kb0 + 8 * (p & 7);
                 const bool fa = row < t.rows && ka < t.K;
-                a[j] = *(const g_u32x4*)(fa ? t.A + row * t.lda + ka : (const g_u16*)kZero16);
+                const int64_t o = row * t.lda + ka;
+#pragma unroll
+                for (int q = 0; q < NA; ++q)
+                    a[q][j] = *(const g_u32x4*)(fa ? t.A + (q ? pa : 0) + o : (const g_u16*)kZero16);
                 nv[j] = t.K - ka;  // valid elements of the A piece (masked when it is stored)
             }
 #pragma unroll
             for (int j = 0; j < PB; ++j) {
                 const int p = tid + 256 * j, kr = kb0 + p / BPR, cb = 8 * (p % BPR);
                 const bool fb = kr < t.K && cb < t.cols;
-                b[j] = *(const g_u32x4*)(fb ? t.B + kr * t.ldb + cb : (const g_u16*)kZero16);
+                const int64_t o = kr * t.ldb + cb;
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    b[q][j] = *(const g_u32x4*)(fb ? t.B + (q ? pb : 0) + o : (const g_u16*)kZero16);
             }
         } else {
 #pragma unroll
             for (int j = 0; j < PA; ++j) {
                 const int p = tid + 256 * j, row = p >> 3, ka = kb0 + 8 * (p & 7);
-                uint16_t e[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    e[q] = (row < t.rows && ka + q < t.K) ? t.A[row * t.lda + ka + q] : (uint16_t)0;
-                a[j] = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
+                for (int q = 0; q < NA; ++q) {
+                    const g_u16* src = t.A + (q ? pa : 0);
+                    uint16_t e[8];
+#pragma unroll
+                    for (int x = 0; x < 8; ++x)
+                        e[x] = (row < t.rows && ka + x < t.K) ? src[row * t.lda + ka + x] : (uint16_t)0;
+                    a[q][j] = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
+                }
                 nv[j] = 8;
             }
 #pragma unroll
             for (int j = 0; j < PB; ++j) {
                 const int p = tid + 256 * j, kr = kb0 + p / BPR, cb = 8 * (p % BPR);
-                uint16_t f[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    f[q] = (kr < t.K && cb + q < t.cols) ? t.B[kr * t.ldb + cb + q] : (uint16_t)0;
-                b[j] = u32x4{pack2(f[0], f[1]), pack2(f[2], f[3]), pack2(f[4], f[5]), pack2(f[6], f[7])};
+                for (int q = 0; q < NB; ++q) {
+                    const g_u16* src = t.B + (q ? pb : 0);
+                    uint16_t f[8];
+#pragma unroll
+                    for (int x = 0; x < 8; ++x)
+                        f[x] = (kr < t.K && cb + x < t.cols) ? src[kr * t.ldb + cb + x] : (uint16_t)0;
+                    b[q][j] = u32x4{pack2(f[0], f[1]), pack2(f[2], f[3]), pack2(f[4], f[5]), pack2(f[6], f[7])};
+                }
             }
         }
     };
-    auto store_block = [&](int buf, const u32x4 (&a)[PA], const u32x4 (&b)[PB], const int (&nv)[PA]) {
+    auto store_block = [&](int buf, const u32x4 (&a)[NA][PA], const u32x4 (&b)[NB][PB], const int (&nv)[PA]) {
 #pragma unroll
         for (int j = 0; j < PA; ++j) {
             const int p = tid + 256 * j, row = p >> 3, c = p & 7;
-            u32x4 am = a[j];
+            uint32_t m[4];
 #pragma unroll
-            for (int d = 0; d < 4; ++d)
-                am[d] &= (2 * d < nv[j] ? 0xFFFFu : 0u) | (2 * d + 1 < nv[j] ? 0xFFFF0000u : 0u);
-            *reinterpret_cast<u32x4*>(&As[buf][row * 64 + ((c ^ swz<8>(row)) * 8)]) = am;
+            for (int d = 0; d < 4; ++d) m[d] = (2 * d < nv[j] ? 0xFFFFu : 0u) | (2 * d + 1 < nv[j] ? 0xFFFF0000u : 0u);
+#pragma unroll
+            for (int q = 0; q < NA; ++q) {
+                u32x4 am = a[q][j];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) am[d] &= m[d];
+                *reinterpret_cast<u32x4*>(&As[q][buf][row * 64 + ((c ^ swz<8>(row)) * 8)]) = am;
+            }
         }
 #pragma unroll
         for (int j = 0; j < PB; ++j) {
             // B row kr of the block: chunk kr / 16, slab row kr % 16, column
             // slab c / 4, columns 8 (c % 4) .. +7 of the slab
             const int p = tid + 256 * j, kr = p / BPR, c = p % BPR;
-            *reinterpret_cast<u32x4*>(&Bs[buf][kr >> 4][c >> 2][(kr & 15) * 32 + 8 * (c & 3)]) = b[j];
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                *reinterpret_cast<u32x4*>(&Bs[q][buf][kr >> 4][c >> 2][(kr & 15) * 32 + 8 * (c & 3)]) = b[q][j];
+        }
+    };
+    auto item_planes = [&](int64_t i) {  // residual-plane offsets of this workgroup's item i
+        if constexpr (NA > 1 || NB > 1) {
+            const int64_t it = first + i * stride;
+            pa = planes[2 * it], pb = planes[2 * it + 1];
         }
     };
 
@@ -360,18 +397,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGroupedWav
     int64_t ci = 0, li = 0;
     int cbk = 0, lbk = 0;
     GItem cur = item_at(0), ld = cur;
+    item_planes(0);
     auto advance_load = [&]() {
         if (++lbk >= grouped_blocks(ld.K)) {
             lbk = 0;
             if (++li < count) {
                 ld = item_at(li);
+                item_planes(li);
             } else {  // past the stream: an empty item (every piece reads zeros)
                 ld.rows = ld.cols = ld.K = 0;
                 li = count;
             }
         }
     };
-    u32x4 ra[2][PA], rb[2][PB];  // register sets of the two blocks in flight
+    u32x4 ra[2][NA][PA], rb[2][NB][PB];  // register sets of the two blocks in flight
     int rn[2][PA];
     // prologue: block 0 into LDS buffer 0, block 1 into registers
     load_block(ld, 0, ra[0], rb[0], rn[0]);
@@ -405,11 +444,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGroupedWav
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm) {
                 const int row = wm * TH + fm * 32 + (lane & 31), piece = 2 * c + (lane >> 5);
-                aa[fm][0] = *reinterpret_cast<const u32x4*>(&As[buf][row * 64 + ((piece ^ swz<8>(row)) * 8)]);
-                aa[fm][1] = zero4();
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    aa[fm][q] = q < NA ? *reinterpret_cast<const u32x4*>(
+                                             &As[q < NA ? q : 0][buf][row * 64 + ((piece ^ swz<8>(row)) * 8)])
+                                       : zero4();
             }
 #pragma unroll
-            for (int fn = 0; fn < FN; ++fn) bb[fn][0] = slab_read_b(Bs[buf][c][wn * FN + fn], lane), bb[fn][1] = zero4();
+            for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    bb[fn][q] = q < NB ? slab_read_b(Bs[q < NB ? q : 0][buf][c][wn * FN + fn], lane) : zero4();
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
@@ -465,7 +510,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGroupedWav
 // rows) go to the XCD with the least work so far, largest first (LPT on
 // flops); each XCD's items are then ordered by decreasing K, their cost, and
 // written out as self-contained records.
-void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split) {
+void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split,
+                        std::vector<int64_t>* planes) {
     struct Unit {
         int64_t prob, tm0, tm1;
         double flops;
@@ -474,6 +520,7 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
         int32_t prob, tm, tn;
     };
     work.clear();
+    if (planes) planes->clear();
     for (int list = 0; list < 2; ++list) {  // 0: aligned problems with ldc < kBufferLdcLimit, 1: the rest
         auto in_list = [&](const GroupedDesc& d) { return (d.vec != 0 && buffer_ldc_ok(d.ldc)) == (list == 0); };
         double total = 0.0;
@@ -518,34 +565,53 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
                 w.cols = (int32_t)std::min<int64_t>(kGroupedTile, d.N - n0);
                 w.K = (int32_t)d.K, w.vec = d.vec;
                 work.push_back(w);
+                if (planes) planes->push_back(d.pa), planes->push_back(d.pb);
             }
             split.off[list][x + 1] = (int64_t)work.size();
         }
     }
 }
 
-int grouped_grid(const GroupedSplit& split, int list) {
+static int wg_per_cu(int kind) {
+    switch (kind) {
+        case K_REFINE_A: return grouped_wg_per_cu<K_REFINE_A>();
+        case K_SPLIT3: return grouped_wg_per_cu<K_SPLIT3>();
+        case K_SPLIT4: return grouped_wg_per_cu<K_SPLIT4>();
+        default: return kGroupedWGPerCU;
+    }
+}
+
+int grouped_grid(const GroupedSplit& split, int list, int kind) {
     int64_t most = 0;  // the largest per-XCD range sets how many workgroups each XCD needs
     for (int x = 0; x < kXcds; ++x) most = std::max<int64_t>(most, split.off[list][x + 1] - split.off[list][x]);
     const int64_t per_xcd =
-        std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)device_cu_count() / kXcds * kGroupedWGPerCU));
+        std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)device_cu_count() / kXcds * wg_per_cu(kind)));
     return (int)(per_xcd * kXcds);
 }
 
-int grouped_launch(int kind, const GroupedWork* work, const GroupedSplit& split, float alpha, float beta,
-                   hipStream_t s) {
-    if (kind != K_F16 && kind != K_BF16) return MFG_ERR_UNSUPPORTED;
+template <int KIND>
+static void launch_grouped_kind(int list, dim3 grid, const GroupedWork* work, const int64_t* planes,
+                                const GroupedSplit& split, float alpha, float beta, hipStream_t s) {
+    if (list == 0)
+        hipLaunchKernelGGL((gemm16_grouped<KIND, true>), grid, dim3(256), 0, s, work, planes, split, alpha, beta);
+    else
+        hipLaunchKernelGGL((gemm16_grouped<KIND, false>), grid, dim3(256), 0, s, work, planes, split, alpha, beta);
+}
+
+int grouped_launch(int kind, const GroupedWork* work, const int64_t* planes, const GroupedSplit& split, float alpha,
+                   float beta, hipStream_t s) {
+    if (kind < K_F16 || kind > K_SPLIT4) return MFG_ERR_UNSUPPORTED;
+    if (kind >= K_REFINE_A && !planes) return MFG_ERR_INTERNAL;  // the refined kinds read residual planes
     for (int list = 0; list < 2; ++list) {
         if (split.off[list][kXcds] == split.off[list][0]) continue;  // empty list
-        const dim3 grid((unsigned)grouped_grid(split, list));
-        if (kind == K_F16 && list == 0)
-            hipLaunchKernelGGL((gemm16_grouped<K_F16, true>), grid, dim3(256), 0, s, work, split, alpha, beta);
-        else if (kind == K_F16)
-            hipLaunchKernelGGL((gemm16_grouped<K_F16, false>), grid, dim3(256), 0, s, work, split, alpha, beta);
-        else if (list == 0)
-            hipLaunchKernelGGL((gemm16_grouped<K_BF16, true>), grid, dim3(256), 0, s, work, split, alpha, beta);
-        else
-            hipLaunchKernelGGL((gemm16_grouped<K_BF16, false>), grid, dim3(256), 0, s, work, split, alpha, beta);
+        const dim3 grid((unsigned)grouped_grid(split, list, kind));
+        switch (kind) {
+            case K_F16: launch_grouped_kind<K_F16>(list, grid, work, planes, split, alpha, beta, s); break;
+            case K_BF16: launch_grouped_kind<K_BF16>(list, grid, work, planes, split, alpha, beta, s); break;
+            case K_REFINE_A: launch_grouped_kind<K_REFINE_A>(list, grid, work, planes, split, alpha, beta, s); break;
+            case K_SPLIT3: launch_grouped_kind<K_SPLIT3>(list, grid, work, planes, split, alpha, beta, s); break;
+            default: launch_grouped_kind<K_SPLIT4>(list, grid, work, planes, split, alpha, beta, s); break;
+        }
         MFG_LAUNCH_CHECK();
     }
     return MFG_OK;

@@ -322,6 +322,7 @@ struct mfg_grouped_plan {
     int64_t count = 0, nwork = 0;
     GroupedSplit split{};
     GroupedWork* d_work = nullptr;
+    int64_t* d_planes = nullptr;  // refined modes: residual-plane offsets per work item
     double flops = 0.0, bytes = 0.0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -334,8 +335,13 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
     *out = nullptr;
     const int m = mode & MFG_MODE_MASK;
     if ((mode & ~(MFG_MODE_MASK | MFG_IN_PRECONVERTED)) != 0 || m < 0 || m >= MFG_NUM_MODES) return MFG_ERR_INVALID_ARG;
-    if (m != MFG_F16 && m != MFG_BF16) return MFG_ERR_UNSUPPORTED;
+    if (m == MFG_F32 || m == MFG_FP8_E4M3) return MFG_ERR_UNSUPPORTED;
     if (count > ((int64_t)1 << 31) - 1) return MFG_ERR_UNSUPPORTED;
+    // Refined modes read their operands in the preconverted storage form:
+    // A's residual plane at A + M*lda, and for the two-sided splits B's at
+    // B + K*ldb.
+    const bool two_a = m == MFG_F16_REFINE_A || m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4;
+    const bool two_b = m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4;
     std::vector<GroupedDesc> descs((size_t)count);
     std::vector<GroupedWork> work;
     double flops = 0.0, bytes = 0.0;
@@ -349,11 +355,15 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
         d.A = static_cast<const uint16_t*>(p.A), d.B = static_cast<const uint16_t*>(p.B), d.C = p.C;
         d.vec = (al16(p.A) && al16(p.B) && p.lda % 8 == 0 && p.ldb % 8 == 0) ? 1 : 0;
         d.pad = 0;
+        d.pa = two_a ? p.M * p.lda : 0;
+        d.pb = two_b ? p.K * p.ldb : 0;
         flops += 2.0 * (double)p.M * (double)p.N * (double)p.K;
-        bytes += 2.0 * (double)(p.M * p.K + p.K * p.N) + 4.0 * (double)(p.M * p.N);
+        bytes += 2.0 * ((two_a ? 2.0 : 1.0) * (double)(p.M * p.K) + (two_b ? 2.0 : 1.0) * (double)(p.K * p.N)) +
+                 4.0 * (double)(p.M * p.N);
     }
     GroupedSplit split{};
-    build_grouped_work(descs.data(), count, work, split);
+    std::vector<int64_t> planes;
+    build_grouped_work(descs.data(), count, work, split, two_a ? &planes : nullptr);
     std::unique_ptr<mfg_grouped_plan> plan(new mfg_grouped_plan());
     plan->split = split;
     plan->mode = m, plan->kind = kind_of(m), plan->count = count, plan->nwork = (int64_t)work.size();
@@ -361,9 +371,17 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
     MFG_HIP_CHECK(hipGetDevice(&plan->device));
     if (!work.empty()) {
         if (hipMalloc(&plan->d_work, work.size() * sizeof(GroupedWork)) != hipSuccess) return MFG_ERR_NO_MEMORY;
-        const hipError_t e = hipMemcpy(plan->d_work, work.data(), work.size() * sizeof(GroupedWork), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpy(plan->d_work, work.data(), work.size() * sizeof(GroupedWork), hipMemcpyHostToDevice);
+        if (e == hipSuccess && two_a) {
+            if (hipMalloc(&plan->d_planes, planes.size() * sizeof(int64_t)) != hipSuccess) {
+                (void)hipFree(plan->d_work);
+                return MFG_ERR_NO_MEMORY;
+            }
+            e = hipMemcpy(plan->d_planes, planes.data(), planes.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+        }
         if (e != hipSuccess) {
             (void)hipFree(plan->d_work);
+            if (plan->d_planes) (void)hipFree(plan->d_planes);
             return hip_fail(e);
         }
     }
@@ -378,7 +396,7 @@ extern "C" int mfg_grouped_plan_create(int64_t count, const mfg_problem* problem
 
 extern "C" int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, void* stream) {
     if (!plan) return MFG_ERR_INVALID_ARG;
-    MFG_GUARD(grouped_launch(plan->kind, plan->d_work, plan->split, alpha, beta, (hipStream_t)stream));
+    MFG_GUARD(grouped_launch(plan->kind, plan->d_work, plan->d_planes, plan->split, alpha, beta, (hipStream_t)stream));
 }
 
 static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hipStream_t s) {
@@ -391,7 +409,7 @@ static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hi
     if (!plan->exec) {
         if (!plan->cap_stream) MFG_HIP_CHECK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
         MFG_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
-        int st = grouped_launch(plan->kind, plan->d_work, plan->split, alpha, beta, plan->cap_stream);
+        int st = grouped_launch(plan->kind, plan->d_work, plan->d_planes, plan->split, alpha, beta, plan->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
         if (st != MFG_OK) {
@@ -429,6 +447,7 @@ extern "C" int mfg_grouped_plan_destroy(mfg_grouped_plan* plan) {
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->d_work) (void)hipFree(plan->d_work);
+    if (plan->d_planes) (void)hipFree(plan->d_planes);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
     return MFG_OK;

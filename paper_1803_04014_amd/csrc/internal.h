@@ -121,6 +121,7 @@ struct GroupedDesc {  // one problem (host side; the kernel reads GroupedWork)
     float* C;
     int32_t vec;  // 1: 16-byte aligned rows and ld a multiple of 8 (whole 16-byte loads)
     int32_t pad;
+    int64_t pa, pb;  // refined kinds: element offsets of the residual planes of A and B (else 0)
 };
 // Tiled kernels address C with 32-bit buffer offsets within a 32-row block:
 // ldc must stay below this bound for them; larger ldc uses the simple
@@ -149,11 +150,17 @@ constexpr int kXcds = 8;
 struct GroupedSplit {
     int64_t off[2][kXcds + 1];  // list 0: aligned rows (vec) and ldc < kBufferLdcLimit, list 1: the rest
 };
-void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split);
-// One launch per non-empty list (the grid of each from grouped_grid).
-int grouped_launch(int kind, const GroupedWork* work, const GroupedSplit& split, float alpha, float beta,
-                   hipStream_t s);
-int grouped_grid(const GroupedSplit& split, int list);  // workgroups of a list's launch (a multiple of kXcds)
+// `planes` (if not null) receives two int64 per work item, in work order:
+// the problem's residual-plane offsets pa, pb.
+void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split,
+                        std::vector<int64_t>* planes = nullptr);
+// One launch per non-empty list (the grid of each from grouped_grid).  The
+// refined kinds (REFINE_A, SPLIT3, SPLIT4) need `planes` in device memory,
+// as build_grouped_work wrote it; F16 / BF16 ignore it (may be null).
+int grouped_launch(int kind, const GroupedWork* work, const int64_t* planes, const GroupedSplit& split, float alpha,
+                   float beta, hipStream_t s);
+// Workgroups of a list's launch (a multiple of kXcds).
+int grouped_grid(const GroupedSplit& split, int list, int kind);
 
 // Validation (validate.cpp; pure host code).
 int validate_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,

@@ -283,6 +283,7 @@ int mfg_server::run_grouped(Slot& sl, const std::vector<Req*>& g) {
         d.C = r.C;
         d.vec = 1;  // workspace planes: 256-byte aligned, ld a multiple of 8
         d.pad = 0;
+        d.pa = d.pb = 0;
     }
     GroupedSplit split{};
     std::vector<GroupedWork> work;
@@ -291,7 +292,7 @@ int mfg_server::run_grouped(Slot& sl, const std::vector<Req*>& g) {
     std::copy(work.begin(), work.end(), sl.h_work);
     MFG_HIP_CHECK(hipMemcpyAsync(sl.d_work, sl.h_work, sizeof(GroupedWork) * nw, hipMemcpyHostToDevice, sl.stream));
     const int kind = g.front()->r.mode == MFG_BF16 ? K_BF16 : K_F16;
-    return grouped_launch(kind, sl.d_work, split, g.front()->r.alpha, g.front()->r.beta, sl.stream);
+    return grouped_launch(kind, sl.d_work, nullptr, split, g.front()->r.alpha, g.front()->r.beta, sl.stream);
 }
 
 void mfg_server::launch_group(int si, std::vector<Req*>& g) {

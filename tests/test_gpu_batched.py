@@ -132,5 +132,61 @@ def test_grouped_equals_solo_and_graph_replays():
 
 def test_grouped_rejects_unsupported_mode():
     probs, _ = _grouped_problems(4, 16, 64, 9)
-    with pytest.raises(mfg.MfgError):
-        mfg.GroupedPlan(probs, "split3")
+    for mode in ("f32", "fp8"):
+        with pytest.raises(mfg.MfgError):
+            mfg.GroupedPlan(probs, mode)
+
+
+def _planes(X32, ld, two):
+    """X (FP32, rows x cols) in the refined storage form: head plane, then
+    (two) the scaled residual plane at +rows*ld; padding columns are NaN."""
+    rows, cols = X32.shape
+    P = torch.full((2 * rows if two else rows, ld), float("nan"), dtype=torch.float16, device=DEV)
+    X = dev(X32)
+    if two:
+        mfg.split_f16(X, P[:rows, :cols], P[rows:, :cols])
+    else:
+        mfg.round_f16(X, P[:rows, :cols])
+    return P[:rows, :cols]
+
+
+@pytest.mark.parametrize("mode", ["refine_a", "split3", "split4"])
+def test_grouped_refined_equals_solo_and_oracle(mode):
+    """The refined modes (Eq. 1, Eq. 2) in the grouped persistent kernel: every
+    problem bitwise equal to mfg_gemm on it alone (preconverted planes), sampled
+    problems within the parity bar of the oracle's mode-faithful reference."""
+    count = 120
+    dims = workloads.loguniform_dims(31, count, 16, 300)
+    probs, ops = [], []
+    for i, (m, n, k) in enumerate(dims):
+        m, n, k = int(m), int(n), int(k)
+        lda, ldb = (k, n) if i % 9 == 0 else (-(-k // 8) * 8, -(-n // 8) * 8)
+        A, B, C0 = workloads.normal(2000 + i, [(m, k), (k, n), (m, n)])
+        dA = _planes(A, lda, True)
+        dB = _planes(B, ldb, mode != "refine_a")
+        probs.append((dA, dB, dev(C0)))
+        ops.append((A, B, C0))
+    plan = mfg.GroupedPlan(probs, mode)
+    info = plan.info()
+    npa, npb = 2, (1 if mode == "refine_a" else 2)
+    exp_bytes = sum(2 * (npa * a.shape[0] * a.shape[1] + npb * b.shape[0] * b.shape[1]) + 4 * a.shape[0] * b.shape[1]
+                    for a, b, _ in ops)
+    assert info["bytes"] == pytest.approx(exp_bytes)
+    plan.run(1.25, -0.5)
+    for i, (dA, dB, dC) in enumerate(probs):
+        A, B, C0 = ops[i]
+        solo = dev(C0)
+        mfg.gemm(dA, dB, solo, 1.25, -0.5, mode=mode, preconverted=True)
+        assert np.array_equal(host(dC).view(np.uint32), host(solo).view(np.uint32)), f"{mode} problem {i}"
+        if i % 17 == 0:
+            assert_parity(host(dC), oracle.reference(mode, A, B, 1.25, -0.5, C0), f"{mode} grouped problem {i}")
+    # graph replays, each equal to the eager run
+    first = [host(p[2]).copy() for p in probs]
+    for rep in range(2):
+        for (dA, dB, dC), (_, _, C0) in zip(probs, ops):
+            dC.copy_(dev(C0))
+        plan.graph_launch(1.25, -0.5)
+        torch.cuda.synchronize()
+        for i in range(0, count, 7):
+            assert np.array_equal(host(probs[i][2]).view(np.uint32), first[i].view(np.uint32)), f"replay {rep} {i}"
+    plan.close()
