@@ -171,7 +171,8 @@ typedef struct mfg_problem {
 typedef struct mfg_grouped_plan mfg_grouped_plan;
 
 /* Build a plan: validates every problem (M, N <= 2^24, K < 2^31), splits it
- * into 128 x 128 output tiles (work items, one workgroup each), orders them by
+ * into 128 x 128 output tiles (64 x 64 in the refined modes; work items, one
+ * workgroup each), orders them by
  * decreasing K, and uploads the work list: one self-contained record per
  * item (device memory owned by the plan).  Rows of A and B that are 16-byte
  * aligned with ld a multiple of 8 are read in whole 16-byte pieces, which may

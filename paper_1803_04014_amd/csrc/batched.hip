@@ -192,9 +192,10 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
 }
 
 // ------------------------------------------------------------------ grouped
-// Each workgroup (four wavefronts) takes work items -- one kGroupedTile
-// square output tile of one problem (128: measured 13% faster than 64 on
-// 4096 uneven problems, with two workgroups per CU instead of three) --
+// Each workgroup (four wavefronts) takes work items -- one square output
+// tile of one problem (F16 / BF16: 128, measured 13% faster than 64 on 4096
+// uneven problems, with two workgroups per CU instead of three; the refined
+// kinds: 64) --
 // with a stride over its XCD's range of the work list; wavefront (wm, wn)
 // computes the quarter (wm, wn).  The work
 // list is denormalised: each record carries the tile's operand pointers,
@@ -218,15 +219,21 @@ typedef __attribute__((address_space(1))) const uint16_t g_u16;
 typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
 typedef __attribute__((address_space(1))) const uint32_t g_u32;
 typedef __attribute__((address_space(1))) float g_f32;
-// Occupancy of the grouped kernel: workgroups per CU (kGroupedTile 64: 32 KB
-// of LDS each, <= 168 VGPRs; 128: 64 KB, <= 256 VGPRs).  The refined kinds
-// stage a second operand plane (96 or 128 KB of LDS at 128): one per CU.
-constexpr int kGroupedWGPerCU = kGroupedTile == 64 ? 3 : 2;
+// Tile side and occupancy (workgroups per CU) of the grouped kernel per
+// kind.  LDS per workgroup is 256 * tile * (planes of A + planes of B) bytes:
+// F16 / BF16 at 128: 64 KB, <= 256 VGPRs, two per CU.  The refined kinds
+// stage a second plane, which at 128 would leave one workgroup per CU
+// (measured 2.9x the F16 time for SPLIT3, latency-bound); at 64 REFINE_A
+// takes 48 KB (three per CU, <= 168 VGPRs), SPLIT3 / SPLIT4 64 KB (two).
+template <int KIND>
+constexpr int grouped_tile_of() {
+    return KT<KIND>::NPA > 1 ? kGroupedTileRefined : kGroupedTile;
+}
 template <int KIND>
 constexpr int grouped_wg_per_cu() {
-    return (KT<KIND>::NPA > 1 || KT<KIND>::NPB > 1) ? 1 : kGroupedWGPerCU;
+    return grouped_tile_of<KIND>() == 128 ? 2 : (KT<KIND>::NPA + KT<KIND>::NPB == 3 ? 3 : 2);
 }
-static_assert(kGroupedTile == 64 || kGroupedTile == 128, "wavefront tiles of 1 or 2 MFMA blocks a side");
+static_assert(kGroupedTile == 128 && kGroupedTileRefined == 64, "wavefront tiles of 2 (F16) or 1 MFMA blocks a side");
 
 // One work record in scalar registers.
 struct GItem {
@@ -266,7 +273,7 @@ __device__ __forceinline__ void grouped_barrier() {
 template <int KIND, bool VEC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_per_cu<KIND>()))) void gemm16_grouped(
     const GroupedWork* work, const int64_t* planes, GroupedSplit split, float alpha, float beta) {
-    constexpr int TT = kGroupedTile, TH = TT / 2;  // workgroup tile, wavefront tile
+    constexpr int TT = grouped_tile_of<KIND>(), TH = TT / 2;  // workgroup tile, wavefront tile
     constexpr int FM = TH / 32, FN = TH / 32;       // 32 x 32 MFMA blocks per wavefront
     constexpr int PA = TT / 32, PB = TT / 32;       // 16-byte pieces per thread and block: A, B
     constexpr int BPR = TT / 8;                     // pieces per B row
@@ -511,7 +518,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
 // flops); each XCD's items are then ordered by decreasing K, their cost, and
 // written out as self-contained records.
 void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split,
-                        std::vector<int64_t>* planes) {
+                        std::vector<int64_t>* planes, int tile) {
     struct Unit {
         int64_t prob, tm0, tm1;
         double flops;
@@ -530,7 +537,7 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
         std::vector<Unit> units;
         for (int64_t i = 0; i < n; ++i) {
             const GroupedDesc& d = descs[i];
-            const int64_t tm = cdiv(d.M, kGroupedTile), tn = cdiv(d.N, kGroupedTile);
+            const int64_t tm = cdiv(d.M, tile), tn = cdiv(d.N, tile);
             if (!in_list(d) || tm == 0 || tn == 0) continue;
             const double f = 2.0 * (double)d.M * (double)d.N * (double)d.K;
             const int64_t parts = std::min<int64_t>(tm, cap > 0.0 ? std::max<int64_t>(1, (int64_t)(f / cap)) : 1);
@@ -545,7 +552,7 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
         for (const Unit& u : units) {
             const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             load[x] += u.flops;
-            const int64_t tn = cdiv(descs[u.prob].N, kGroupedTile);
+            const int64_t tn = cdiv(descs[u.prob].N, tile);
             for (int64_t a = u.tm0; a < u.tm1; ++a)
                 for (int64_t b = 0; b < tn; ++b) per[x].push_back(Tile{(int32_t)u.prob, (int32_t)a, (int32_t)b});
         }
@@ -555,14 +562,14 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
                              [&](const Tile& p, const Tile& q) { return descs[p.prob].K > descs[q.prob].K; });
             for (const Tile& t : per[x]) {
                 const GroupedDesc& d = descs[t.prob];
-                const int64_t m0 = (int64_t)t.tm * kGroupedTile, n0 = (int64_t)t.tn * kGroupedTile;
+                const int64_t m0 = (int64_t)t.tm * tile, n0 = (int64_t)t.tn * tile;
                 GroupedWork w;
                 w.A = d.A + m0 * d.lda;
                 w.B = d.B + n0;
                 w.C = d.C + m0 * d.ldc + n0;
                 w.lda = d.lda, w.ldb = d.ldb, w.ldc = d.ldc;
-                w.rows = (int32_t)std::min<int64_t>(kGroupedTile, d.M - m0);
-                w.cols = (int32_t)std::min<int64_t>(kGroupedTile, d.N - n0);
+                w.rows = (int32_t)std::min<int64_t>(tile, d.M - m0);
+                w.cols = (int32_t)std::min<int64_t>(tile, d.N - n0);
                 w.K = (int32_t)d.K, w.vec = d.vec;
                 work.push_back(w);
                 if (planes) planes->push_back(d.pa), planes->push_back(d.pb);
@@ -577,7 +584,8 @@ static int wg_per_cu(int kind) {
         case K_REFINE_A: return grouped_wg_per_cu<K_REFINE_A>();
         case K_SPLIT3: return grouped_wg_per_cu<K_SPLIT3>();
         case K_SPLIT4: return grouped_wg_per_cu<K_SPLIT4>();
-        default: return kGroupedWGPerCU;
+        case K_BF16: return grouped_wg_per_cu<K_BF16>();
+        default: return grouped_wg_per_cu<K_F16>();
     }
 }
 

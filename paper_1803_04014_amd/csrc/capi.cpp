@@ -363,7 +363,7 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
     }
     GroupedSplit split{};
     std::vector<int64_t> planes;
-    build_grouped_work(descs.data(), count, work, split, two_a ? &planes : nullptr);
+    build_grouped_work(descs.data(), count, work, split, two_a ? &planes : nullptr, grouped_tile(kind_of(m)));
     std::unique_ptr<mfg_grouped_plan> plan(new mfg_grouped_plan());
     plan->split = split;
     plan->mode = m, plan->kind = kind_of(m), plan->count = count, plan->nwork = (int64_t)work.size();

@@ -129,7 +129,9 @@ struct GroupedDesc {  // one problem (host side; the kernel reads GroupedWork)
 constexpr int64_t kBufferLdcLimit = int64_t(1) << 24;
 inline bool buffer_ldc_ok(int64_t ldc) { return ldc < kBufferLdcLimit; }
 
-constexpr int kGroupedTile = 128;  // output tile of a grouped work item (one workgroup)
+constexpr int kGroupedTile = 128;        // output tile of a grouped work item (one workgroup): F16, BF16
+constexpr int kGroupedTileRefined = 64;  // REFINE_A, SPLIT3, SPLIT4 (two operand planes in LDS)
+inline int grouped_tile(int kind) { return kind >= K_REFINE_A ? kGroupedTileRefined : kGroupedTile; }
 // One kGroupedTile x kGroupedTile output tile with everything its workgroup
 // reads (16 dwords, so that 16 lanes fetch one record with one load each).
 struct GroupedWork {
@@ -137,7 +139,7 @@ struct GroupedWork {
     const uint16_t* B;  // column n0 of its B
     float* C;           // element (m0, n0) of its C
     int64_t lda, ldb, ldc;
-    int32_t rows, cols;  // of the tile inside the problem: min(128, M - m0), min(128, N - n0)
+    int32_t rows, cols;  // of the tile inside the problem: min(tile, M - m0), min(tile, N - n0)
     int32_t K, vec;
 };
 static_assert(sizeof(GroupedWork) == 64, "a work record is 16 dwords");
@@ -152,8 +154,9 @@ struct GroupedSplit {
 };
 // `planes` (if not null) receives two int64 per work item, in work order:
 // the problem's residual-plane offsets pa, pb.
+// `tile`: the output tile side of the kind that will run the list (grouped_tile).
 void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split,
-                        std::vector<int64_t>* planes = nullptr);
+                        std::vector<int64_t>* planes = nullptr, int tile = kGroupedTile);
 // One launch per non-empty list (the grid of each from grouped_grid).  The
 // refined kinds (REFINE_A, SPLIT3, SPLIT4) need `planes` in device memory,
 // as build_grouped_work wrote it; F16 / BF16 ignore it (may be null).
