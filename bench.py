@@ -419,6 +419,22 @@ def main() -> int:
                               "pct_hbm": round(100 * info["bytes"] / ms / 1e6 / HBM_GBS, 1), "us": round(ms * 1e3, 1),
                               "work_items": info["work_items"]}
         plan.close()
+        # the same problems refined (Eq. 2 without R_A R_B): head and residual planes
+        probs = []
+        for (m_, n_, k_) in dims:
+            lda, ldb = -(-int(k_) // 8) * 8, -(-int(n_) // 8) * 8
+            a = torch.empty((2 * m_, lda), dtype=torch.float16, device=dev).uniform_(-1, 1)[:m_, :k_]
+            b = torch.empty((2 * k_, ldb), dtype=torch.float16, device=dev).uniform_(-1, 1)[:k_, :n_]
+            probs.append((a, b, torch.empty((m_, n_), dtype=torch.float32, device=dev)))
+        plan = mfg.GroupedPlan(probs, "split3")
+        info = plan.info()
+        ms = timed(lambda: plan.graph_launch(1.0, 0.0), 20)
+        ex["grouped_4096_split3"] = {"useful_tflops": round(info["flops"] / ms / 1e9, 2),
+                                     "hbm_gbs": round(info["bytes"] / ms / 1e6, 1),
+                                     "pct_hbm": round(100 * info["bytes"] / ms / 1e6 / HBM_GBS, 1),
+                                     "us": round(ms * 1e3, 1), "work_items": info["work_items"]}
+        plan.close()
+        del probs
         # serving: Poisson arrivals at two rates
         gen = torch.Generator(device=dev)
         gen.manual_seed(7)
