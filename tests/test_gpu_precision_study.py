@@ -127,3 +127,55 @@ def test_uniform16_n4096_matches_the_printed_error():
     mfg.gemm(dev(A), dev(B), C, 1.0, 0.0, mode="split4")
     e2 = float(np.max(np.abs(host(C)[rows].astype(np.float64) - ex)))
     assert e2 < c["uniform16_n4096_maxerr_eq2"], e2
+
+
+def _literal_planes(X):
+    """The paper's literal residual (Eq. R, unscaled): head rne16(X) and
+    rne16(X - head), stored times 2^11 so that the library's refined kernel
+    (which divides the residual products by 2^11) multiplies the unscaled
+    residual.  The product by 2^11 is exact: an FP16 residual has at most 11
+    significant bits and |rne16(X - head)| * 2^11 stays below 2^16."""
+    h = oracle.f16_round(X)
+    r = oracle.f16_round((X.astype(np.float64) - h.astype(np.float64)).astype(np.float32))
+    R = (r.astype(np.float64) * 2.0 ** 11).astype(np.float16)
+    assert np.array_equal(R.astype(np.float64), r.astype(np.float64) * 2.0 ** 11)
+    return np.concatenate([h.astype(np.float16), R], axis=0)
+
+
+@pytest.mark.parametrize("log2_range", [
+    0,    # unit magnitude: the residual is a normal FP16 number, nothing lost
+    -10,  # residuals in FP16's subnormal range: about one order of magnitude
+    -14,  # residuals mostly below FP16's smallest subnormal: no gain at all
+])
+def test_unscaled_residual_ablation(log2_range):
+    """Eq. 2 with the literal residual against the scaled one (reading of Sec. V):
+    the same kernel (SPLIT3 on preconverted planes), inputs uniform in
+    [-2^e, 2^e].  Scaling the residual by 2^11 keeps its bits out of FP16's
+    subnormal range; the literal form loses them as the inputs shrink."""
+    n = 1024
+    lim = 2.0 ** log2_range
+    A, B = workloads.uniform(41, [(n, n), (n, n)], -lim, lim)
+    rows = oracle.sample_rows(n, n=64, seed=3)
+    ex = oracle.exact(A, B, rows=rows)
+    scale = float(np.max(np.abs(ex)))
+
+    def err(C):
+        return float(np.max(np.abs(host(C)[rows].astype(np.float64) - ex))) / scale
+
+    C = torch.zeros((n, n), dtype=torch.float32, device=DEV)
+    mfg.gemm(dev(A), dev(B), C, 1.0, 0.0, mode="f16")
+    e16 = err(C)
+    mfg.gemm(dev(A), dev(B), C, 1.0, 0.0, mode="split3")
+    e_scaled = err(C)
+    pa, pb = torch.from_numpy(_literal_planes(A)).to(DEV), torch.from_numpy(_literal_planes(B)).to(DEV)
+    mfg.gemm(pa[:n], pb[:n], C, 1.0, 0.0, mode="split3", preconverted=True)
+    e_lit = err(C)
+    print(f"\n[-2^{log2_range}, 2^{log2_range}]: F16 {e16:.2e}  literal Eq. R {e_lit:.2e}  scaled {e_scaled:.2e}")
+    assert e16 / e_scaled >= 100.0
+    gain = e16 / e_lit
+    if log2_range == 0:
+        assert e_lit <= 1.5 * e_scaled
+    elif log2_range == -10:
+        assert 3.0 <= gain <= 30.0, gain
+    else:
+        assert gain <= 2.0, gain
