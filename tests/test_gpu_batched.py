@@ -190,3 +190,25 @@ def test_grouped_refined_equals_solo_and_oracle(mode):
         for i in range(0, count, 7):
             assert np.array_equal(host(probs[i][2]).view(np.uint32), first[i].view(np.uint32)), f"replay {rep} {i}"
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["refine_a", "split4"])
+def test_grouped_refined_degenerate_shapes(mode):
+    """Empty, single-row/column, K = 0 and tile-edge problems in one refined
+    grouped plan, each bitwise equal to its solo run."""
+    shapes = [(1, 1, 1), (0, 5, 7), (5, 0, 7), (5, 7, 0), (1, 130, 3), (130, 1, 65), (64, 64, 64), (65, 65, 129),
+              (3, 200, 8), (200, 3, 9)]
+    probs, c0 = [], []
+    for i, (m, n, k) in enumerate(shapes):
+        A, B, C0 = workloads.normal(3000 + i, [(m, k), (k, n), (m, n)])
+        dA = _planes(A, max(8, -(-k // 8) * 8), True)
+        dB = _planes(B, max(8, -(-n // 8) * 8), mode != "refine_a")
+        probs.append((dA, dB, dev(C0)))
+        c0.append(C0)
+    plan = mfg.GroupedPlan(probs, mode)
+    plan.run(0.5, 2.0)
+    for i, (dA, dB, dC) in enumerate(probs):
+        solo = dev(c0[i])
+        mfg.gemm(dA, dB, solo, 0.5, 2.0, mode=mode, preconverted=True)
+        assert np.array_equal(host(dC).view(np.uint32), host(solo).view(np.uint32)), f"{mode} shape {shapes[i]}"
+    plan.close()

@@ -211,4 +211,14 @@ def test_huge_leading_dimension_of_c():
     ref = oracle.reference("f32", host(dA.float()), host(dB.float()), 1.0, 1.0, C0)
     assert_parity(host(C.contiguous()), ref, "grouped f16 ldc=2^24+16", mode="f16")
     plan.close()
+    # the refined grouped kernel on the same C (head and residual planes)
+    pa = torch.empty((2 * M, K), dtype=torch.float16, device=DEV)
+    pb = torch.empty((2 * K, N), dtype=torch.float16, device=DEV)
+    mfg.split_f16(dev(A), pa[:M], pa[M:])
+    mfg.split_f16(dev(B), pb[:K], pb[K:])
+    C.copy_(dev(C0))
+    plan = mfg.GroupedPlan([(pa[:M], pb[:K], C)], mode="split3")
+    plan.run(1.0, 1.0)
+    assert_parity(host(C.contiguous()), oracle.reference("split3", A, B, 1.0, 1.0, C0), "grouped split3 ldc=2^24+16")
+    plan.close()
     del C, buf
