@@ -256,9 +256,10 @@ int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode);
  * fit waits, and so do the ones behind it).  When a slot (one HIP stream) is
  * free, the oldest admitted request takes up to max_group admitted requests
  * of its mode, alpha and beta into one group: operands are converted on the
- * slot's stream, small FP16/BF16 problems (M*N < 512*512, at most 256 tiles
- * of 128 x 128) run as one persistent grouped launch, the others one by one; one
- * completion event per group.  Footprint: the mode's converted A (ld = K
+ * slot's stream, small FP16 / BF16 / refined problems (M*N < 512*512, at
+ * most 256 output tiles of the grouped kernel: 128 x 128, or 64 x 64 for
+ * REFINE_A / SPLIT3 / SPLIT4) run as one persistent grouped launch, the
+ * others one by one; one completion event per group.  Footprint: the mode's converted A (ld = K
  * rounded up to 8, or to 16 for FP8) and B (ld = N rounded likewise), each
  * rounded up to 256 bytes; 0 for MFG_F32 and for empty problems.  The fixed
  * per-slot descriptor staging is not counted.  Results are bitwise those of

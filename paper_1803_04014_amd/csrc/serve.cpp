@@ -16,8 +16,9 @@
 //      which a grouped launch shares).  On the slot's stream
 //      each request's FP32 operands are converted into stream-ordered
 //      allocations (the paper's rounding / Eq. R split / FP8 quantisation),
-//      then the GEMMs run: small FP16 / BF16 problems of the group as ONE
-//      persistent grouped launch, every other problem through mfg_gemm on
+//      then the GEMMs run: small FP16 / BF16 / refined (Eq. 1, Eq. 2)
+//      problems of the group as ONE persistent grouped launch, every other
+//      problem through mfg_gemm on
 //      the converted operands; one event marks the group's end.
 // Every kernel the server runs is one that mfg_gemm / the grouped plan would
 // run for the same problem, and all 16-bit kernels share one accumulation
@@ -83,11 +84,25 @@ void plan_footprint(Req& q) {
     q.footprint = q.off_b + up(bb, 256);
 }
 
-// A problem the grouped kernel takes (few 32 x 32 work items).
+// The grouped kernel's kind for a request mode (-1: not a grouped mode).
+int grouped_kind(int mode) {
+    switch (mode) {
+        case MFG_F16: return K_F16;
+        case MFG_BF16: return K_BF16;
+        case MFG_F16_REFINE_A: return K_REFINE_A;
+        case MFG_F16_SPLIT3: return K_SPLIT3;
+        case MFG_F16_SPLIT4: return K_SPLIT4;
+        default: return -1;
+    }
+}
+
+// A problem the grouped kernel takes (few work items).
 constexpr int64_t kSmallTiles = 256;
 bool grouped_small(const mfg_request& r) {
-    return (r.mode == MFG_F16 || r.mode == MFG_BF16) && r.M * r.N < (int64_t)512 * 512 &&
-           cdiv(r.M, kGroupedTile) * cdiv(r.N, kGroupedTile) <= kSmallTiles;
+    const int kind = grouped_kind(r.mode);
+    if (kind < 0 || r.M * r.N >= (int64_t)512 * 512) return false;
+    const int t = grouped_tile(kind);
+    return cdiv(r.M, t) * cdiv(r.N, t) <= kSmallTiles;
 }
 
 struct Slot {
@@ -100,6 +115,8 @@ struct Slot {
     std::vector<GroupedDesc> h_desc;  // the group's problems (host side)
     GroupedWork* h_work = nullptr;
     GroupedWork* d_work = nullptr;
+    int64_t* h_planes = nullptr;  // refined modes: residual-plane offsets, two per work item
+    int64_t* d_planes = nullptr;
 };
 
 }  // namespace
@@ -147,6 +164,8 @@ int mfg_server::init_device() {
         sl.h_desc.resize((size_t)cfg.max_group);
         MFG_HIP_CHECK(hipHostMalloc((void**)&sl.h_work, sizeof(GroupedWork) * work_cap, 0));
         MFG_HIP_CHECK(hipMalloc((void**)&sl.d_work, sizeof(GroupedWork) * work_cap));
+        MFG_HIP_CHECK(hipHostMalloc((void**)&sl.h_planes, sizeof(int64_t) * 2 * work_cap, 0));
+        MFG_HIP_CHECK(hipMalloc((void**)&sl.d_planes, sizeof(int64_t) * 2 * work_cap));
     }
     return MFG_OK;
 }
@@ -158,6 +177,8 @@ void mfg_server::release_device() {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.h_work) (void)hipHostFree(sl.h_work);
         if (sl.d_work) (void)hipFree(sl.d_work);
+        if (sl.h_planes) (void)hipHostFree(sl.h_planes);
+        if (sl.d_planes) (void)hipFree(sl.d_planes);
         sl = Slot{};
     }
 }
@@ -270,9 +291,13 @@ int mfg_server::run_request(Slot& sl, Req* q, bool& grouped) {
                     r.mode | MFG_IN_PRECONVERTED, sl.stream);
 }
 
-// One persistent grouped launch over the group's small FP16 / BF16 problems
-// (the same descriptors and work order as a grouped plan; one alpha, beta).
+// One persistent grouped launch over the group's small problems (one mode;
+// the same descriptors and work order as a grouped plan; one alpha, beta).
 int mfg_server::run_grouped(Slot& sl, const std::vector<Req*>& g) {
+    const int mode = g.front()->r.mode, kind = grouped_kind(mode);
+    // converted refined operands: head plane, then residual plane (B: only
+    // for the two-sided splits; Eq. 1 keeps B's head alone)
+    const bool two_a = kind >= K_REFINE_A, two_b = kind >= K_SPLIT3;
     int64_t nd = 0;
     for (Req* q : g) {
         const mfg_request& r = q->r;
@@ -283,16 +308,24 @@ int mfg_server::run_grouped(Slot& sl, const std::vector<Req*>& g) {
         d.C = r.C;
         d.vec = 1;  // workspace planes: 256-byte aligned, ld a multiple of 8
         d.pad = 0;
-        d.pa = d.pb = 0;
+        d.pa = two_a ? r.M * q->lda_c : 0;
+        d.pb = two_b ? r.K * q->ldb_c : 0;
     }
     GroupedSplit split{};
     std::vector<GroupedWork> work;
-    build_grouped_work(sl.h_desc.data(), nd, work, split);
+    std::vector<int64_t> planes;
+    build_grouped_work(sl.h_desc.data(), nd, work, split, two_a ? &planes : nullptr, grouped_tile(kind));
     const int64_t nw = (int64_t)work.size();  // <= max_group * kSmallTiles (grouped_small)
+    if (nw > work_cap) return MFG_ERR_INTERNAL;
     std::copy(work.begin(), work.end(), sl.h_work);
     MFG_HIP_CHECK(hipMemcpyAsync(sl.d_work, sl.h_work, sizeof(GroupedWork) * nw, hipMemcpyHostToDevice, sl.stream));
-    const int kind = g.front()->r.mode == MFG_BF16 ? K_BF16 : K_F16;
-    return grouped_launch(kind, sl.d_work, nullptr, split, g.front()->r.alpha, g.front()->r.beta, sl.stream);
+    if (two_a) {
+        std::copy(planes.begin(), planes.end(), sl.h_planes);
+        MFG_HIP_CHECK(hipMemcpyAsync(sl.d_planes, sl.h_planes, sizeof(int64_t) * 2 * nw, hipMemcpyHostToDevice,
+                                     sl.stream));
+    }
+    return grouped_launch(kind, sl.d_work, two_a ? sl.d_planes : nullptr, split, g.front()->r.alpha,
+                          g.front()->r.beta, sl.stream);
 }
 
 void mfg_server::launch_group(int si, std::vector<Req*>& g) {
