@@ -403,7 +403,8 @@ def main() -> int:
                                        "tuned_config": mfg.config_name("f16", best)}
         mfg.lib().mfg_tune_clear()
         ex["autotune_f16"] = tune
-        # grouped: 4096 problems, M, N, K log-uniform in [16, 512]
+        # grouped: 4096 problems, M, N, K log-uniform in [16, 512]; the first few
+        # dozen launches over fresh operands run up to 1.3x slower, so warm up first
         dims = workloads.loguniform_dims(6, 4096, 16, 512)
         probs = []
         for (m_, n_, k_) in dims:
@@ -413,7 +414,7 @@ def main() -> int:
             probs.append((a, b, torch.empty((m_, n_), dtype=torch.float32, device=dev)))
         plan = mfg.GroupedPlan(probs, "f16")
         info = plan.info()
-        ms = timed(lambda: plan.graph_launch(1.0, 0.0), 20)
+        ms = timed(lambda: plan.graph_launch(1.0, 0.0), 20, warm=60)
         ex["grouped_4096"] = {"gemm_per_s": round(4096 / ms * 1e3, 1), "tflops": round(info["flops"] / ms / 1e9, 2),
                               "hbm_gbs": round(info["bytes"] / ms / 1e6, 1),
                               "pct_hbm": round(100 * info["bytes"] / ms / 1e6 / HBM_GBS, 1), "us": round(ms * 1e3, 1),
@@ -428,7 +429,7 @@ def main() -> int:
             probs.append((a, b, torch.empty((m_, n_), dtype=torch.float32, device=dev)))
         plan = mfg.GroupedPlan(probs, "split3")
         info = plan.info()
-        ms = timed(lambda: plan.graph_launch(1.0, 0.0), 20)
+        ms = timed(lambda: plan.graph_launch(1.0, 0.0), 20, warm=60)
         ex["grouped_4096_split3"] = {"useful_tflops": round(info["flops"] / ms / 1e9, 2),
                                      "hbm_gbs": round(info["bytes"] / ms / 1e6, 1),
                                      "pct_hbm": round(100 * info["bytes"] / ms / 1e6 / HBM_GBS, 1),
