@@ -381,7 +381,7 @@ def main() -> int:
         for cnt, s in ((65536, 16), (16384, 64)):
             a16, b16 = (torch.empty((cnt, s, s), dtype=torch.float16, device=dev).uniform_(-1, 1) for _ in range(2))
             c = torch.empty((cnt, s, s), dtype=torch.float32, device=dev)
-            ms = timed(lambda: mfg.gemm_batched(a16, b16, c, 1.0, 0.0, mode="f16"), 20)
+            ms = timed(lambda: mfg.gemm_batched(a16, b16, c, 1.0, 0.0, mode="f16"), 20, warm=100)
             byts = cnt * (2 * 2 * s * s + 4 * s * s)
             ex[f"batched_{cnt}x{s}^3"] = {"gemm_per_s": round(cnt / ms * 1e3, 1), "tflops": round(2 * cnt * s ** 3 / ms / 1e9, 2),
                                           "hbm_gbs": round(byts / ms / 1e6, 1),
