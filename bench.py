@@ -69,6 +69,40 @@ def timed(fn, reps, warm=2):
     return s.elapsed_time(e) / reps
 
 
+def grouped_legs(timed, dev) -> dict:
+    """Grouped plans over 4096 problems, M, N, K log-uniform in [16, 512] (seed 6),
+    FP16 uniform[-1, 1] operands (ld rounded up to 8), alpha = 1, beta = 0, run
+    as HIP graphs; F16 and the refined modes (head and residual planes of the
+    same shapes).  The first few dozen launches over fresh operands run up to
+    1.3x slower, so each plan is warmed with 60 launches before 20 timed ones."""
+    import torch
+
+    import paper_1803_04014_amd as mfg
+    import workloads
+
+    dims = workloads.loguniform_dims(6, 4096, 16, 512)
+    out = {}
+    for mode in ("f16", "refine_a", "split3", "split4"):
+        two_a, two_b = mode != "f16", mode in ("split3", "split4")
+        probs = []
+        for (m_, n_, k_) in dims:
+            lda, ldb = -(-int(k_) // 8) * 8, -(-int(n_) // 8) * 8
+            a = torch.empty(((2 if two_a else 1) * m_, lda), dtype=torch.float16, device=dev).uniform_(-1, 1)
+            b = torch.empty(((2 if two_b else 1) * k_, ldb), dtype=torch.float16, device=dev).uniform_(-1, 1)
+            probs.append((a[:m_, :k_], b[:k_, :n_], torch.empty((m_, n_), dtype=torch.float32, device=dev)))
+        plan = mfg.GroupedPlan(probs, mode)
+        info = plan.info()
+        ms = timed(lambda: plan.graph_launch(1.0, 0.0), 20, warm=60)
+        key = "grouped_4096" if mode == "f16" else f"grouped_4096_{mode}"
+        out[key] = {"gemm_per_s": round(4096 / ms * 1e3, 1), "useful_tflops": round(info["flops"] / ms / 1e9, 2),
+                    "hbm_gbs": round(info["bytes"] / ms / 1e6, 1),
+                    "pct_hbm": round(100 * info["bytes"] / ms / 1e6 / HBM_GBS, 1), "us": round(ms * 1e3, 1),
+                    "work_items": info["work_items"]}
+        plan.close()
+        del probs
+    return out
+
+
 def _csv_rows(d: str, suffix: str):
     import csv
     import glob
@@ -207,6 +241,7 @@ def main() -> int:
     ap.add_argument("--pmc-summarize", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="only turn four rocprofv3 --pmc output folders into the traffic record")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--grouped-only", action="store_true", help="only the grouped-plan legs (one JSON line)")
     args = ap.parse_args()
     if args.copy_probe:
         return copy_probe(args.copy_probe)
@@ -216,6 +251,11 @@ def main() -> int:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build is single-GPU)",
               file=sys.stderr)
         return 2
+    if args.grouped_only:
+        import torch
+
+        print(json.dumps(grouped_legs(timed, torch.device("cuda", 0))), flush=True)
+        return 0
 
     import numpy as np
     import torch
@@ -403,39 +443,7 @@ def main() -> int:
                                        "tuned_config": mfg.config_name("f16", best)}
         mfg.lib().mfg_tune_clear()
         ex["autotune_f16"] = tune
-        # grouped: 4096 problems, M, N, K log-uniform in [16, 512]; the first few
-        # dozen launches over fresh operands run up to 1.3x slower, so warm up first
-        dims = workloads.loguniform_dims(6, 4096, 16, 512)
-        probs = []
-        for (m_, n_, k_) in dims:
-            lda, ldb = -(-int(k_) // 8) * 8, -(-int(n_) // 8) * 8
-            a = torch.empty((m_, lda), dtype=torch.float16, device=dev).uniform_(-1, 1)[:, :k_]
-            b = torch.empty((k_, ldb), dtype=torch.float16, device=dev).uniform_(-1, 1)[:, :n_]
-            probs.append((a, b, torch.empty((m_, n_), dtype=torch.float32, device=dev)))
-        plan = mfg.GroupedPlan(probs, "f16")
-        info = plan.info()
-        ms = timed(lambda: plan.graph_launch(1.0, 0.0), 20, warm=60)
-        ex["grouped_4096"] = {"gemm_per_s": round(4096 / ms * 1e3, 1), "tflops": round(info["flops"] / ms / 1e9, 2),
-                              "hbm_gbs": round(info["bytes"] / ms / 1e6, 1),
-                              "pct_hbm": round(100 * info["bytes"] / ms / 1e6 / HBM_GBS, 1), "us": round(ms * 1e3, 1),
-                              "work_items": info["work_items"]}
-        plan.close()
-        # the same problems refined (Eq. 2 without R_A R_B): head and residual planes
-        probs = []
-        for (m_, n_, k_) in dims:
-            lda, ldb = -(-int(k_) // 8) * 8, -(-int(n_) // 8) * 8
-            a = torch.empty((2 * m_, lda), dtype=torch.float16, device=dev).uniform_(-1, 1)[:m_, :k_]
-            b = torch.empty((2 * k_, ldb), dtype=torch.float16, device=dev).uniform_(-1, 1)[:k_, :n_]
-            probs.append((a, b, torch.empty((m_, n_), dtype=torch.float32, device=dev)))
-        plan = mfg.GroupedPlan(probs, "split3")
-        info = plan.info()
-        ms = timed(lambda: plan.graph_launch(1.0, 0.0), 20, warm=60)
-        ex["grouped_4096_split3"] = {"useful_tflops": round(info["flops"] / ms / 1e9, 2),
-                                     "hbm_gbs": round(info["bytes"] / ms / 1e6, 1),
-                                     "pct_hbm": round(100 * info["bytes"] / ms / 1e6 / HBM_GBS, 1),
-                                     "us": round(ms * 1e3, 1), "work_items": info["work_items"]}
-        plan.close()
-        del probs
+        ex.update(grouped_legs(timed, dev))
         # serving: Poisson arrivals at two rates
         gen = torch.Generator(device=dev)
         gen.manual_seed(7)
