@@ -30,6 +30,7 @@ def _solo(mode, A, B, C0, alpha, beta, preconverted):
 @pytest.mark.parametrize("mode,shape,count", [
     ("f16", (16, 16, 16), 1000), ("bf16", (16, 16, 16), 333), ("f16", (17, 9, 100), 257), ("f16", (9, 13, 20), 101),
     ("f16", (64, 64, 64), 300), ("f16", (33, 70, 48), 65), ("bf16", (128, 100, 72), 37), ("f16", (129, 64, 64), 9),
+    ("f16", (40, 50, 72), 77), ("bf16", (64, 20, 33), 45), ("f16", (20, 64, 200), 19), ("f16", (33, 33, 16), 8),
     ("f32", (16, 16, 16), 200), ("f32", (64, 64, 64), 50),
 ])
 def test_batched_equals_solo_and_oracle(mode, shape, count):
@@ -55,9 +56,10 @@ def test_batched_equals_solo_and_oracle(mode, shape, count):
             assert_parity(got[b], ref, f"{mode} problem {b}")
 
 
-@pytest.mark.parametrize("mode", ["split3", "refine_a", "split4"])
-def test_batched_refined_equals_solo(mode):
-    count, M, N, K = 96, 16, 16, 40
+@pytest.mark.parametrize("mode,shape", [("split3", (16, 16, 40)), ("refine_a", (16, 16, 40)), ("split4", (16, 16, 40)),
+                                        ("split3", (48, 64, 40)), ("split4", (64, 40, 72))])
+def test_batched_refined_equals_solo(mode, shape):
+    count, (M, N, K) = 96, shape
     A, B, C0 = workloads.normal(22, [(count, M, K), (count, K, N), (count, M, N)])
     dC = dev(C0)
     mfg.gemm_batched(dev(A), dev(B), dC, 1.0, 1.0, mode=mode)
