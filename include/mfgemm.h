@@ -91,6 +91,8 @@ enum {
     MFG_NUM_MODES = 7
 };
 #define MFG_IN_PRECONVERTED 0x100
+/* mfg_grouped_plan_create only: A and B are FP32 (see "grouped GEMM"). */
+#define MFG_IN_FP32 0x200
 #define MFG_MODE_MASK 0xFF
 #define MFG_RESID_SCALE_LOG2 11
 #define MFG_FP8_TILE 128
@@ -150,14 +152,20 @@ int mfg_gemm_batched(int64_t count, int64_t M, int64_t N, int64_t K,
 
 /* --------------------------------------------------------- grouped GEMM
  * Thousands of GEMMs of different shapes in one persistent launch (paper
- * Sec. IV.B, batched GEMM, generalised to uneven shapes).  Operands are
- * always in the mode's preconverted storage form (the MFG_IN_PRECONVERTED
- * flag is implied): MFG_F16 and MFG_BF16 16-bit matrices, and for the
- * refined modes (paper Sec. V, Eq. 1 and Eq. 2: MFG_F16_REFINE_A,
- * MFG_F16_SPLIT3, MFG_F16_SPLIT4) head plane then residual plane, at
- * A + M*lda and (two-sided splits) B + K*ldb elements.  MFG_F32 and
- * MFG_FP8_E4M3 are MFG_ERR_UNSUPPORTED.  Each problem's result is bitwise
- * that of mfg_gemm (same mode, preconverted) on the problem alone.  The descriptor array is host memory; the plan copies it
+ * Sec. IV.B, batched GEMM, generalised to uneven shapes).  Modes MFG_F16,
+ * MFG_BF16 and the refined modes (paper Sec. V, Eq. 1 and Eq. 2:
+ * MFG_F16_REFINE_A, MFG_F16_SPLIT3, MFG_F16_SPLIT4); MFG_F32 and
+ * MFG_FP8_E4M3 are MFG_ERR_UNSUPPORTED.  Operands are either
+ *   - in the mode's preconverted storage form (the default; the flag
+ *     MFG_IN_PRECONVERTED is implied): 16-bit matrices, and for the refined
+ *     modes head plane then residual plane, at A + M*lda and (two-sided
+ *     splits) B + K*ldb elements; or
+ *   - FP32 (mode | MFG_IN_FP32): the plan owns converted copies (ld rounded
+ *     up to 8) and every run first converts all problems' A and B in one
+ *     launch (the paper's rounding, or the Eq. R split), then runs the
+ *     grouped kernel; a graph replay holds both launches.
+ * Each problem's result is bitwise that of mfg_gemm on the problem alone in
+ * the same mode (preconverted, or from FP32 respectively).  The descriptor array is host memory; the plan copies it
  * to the device, so it may be freed after mfg_grouped_plan_create.
  */
 typedef struct mfg_problem {
@@ -186,7 +194,10 @@ int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, void* strea
 /* Run the plan through a HIP graph: captured on first use for (alpha, beta,
  * stream), replayed afterwards.  The graph holds the plan's launch only. */
 int mfg_grouped_graph_launch(mfg_grouped_plan* plan, float alpha, float beta, void* stream);
-/* Total useful flops 2*sum(M*N*K) and algorithmic bytes of the plan. */
+/* Total useful flops 2*sum(M*N*K) and algorithmic bytes of one run: the
+ * operands read by the grouped kernel (both planes of the refined modes) and
+ * C written, plus with MFG_IN_FP32 the conversion pass (FP32 read, 16-bit
+ * planes written). */
 int mfg_grouped_plan_info(const mfg_grouped_plan* plan, double* flops, double* bytes,
                           int64_t* work_items);
 int mfg_grouped_plan_destroy(mfg_grouped_plan* plan);

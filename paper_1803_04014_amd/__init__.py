@@ -83,8 +83,9 @@ def gemm_batched(A, B, C, alpha: float = 1.0, beta: float = 0.0, mode="f16", str
 class GroupedPlan:
     """mfg_grouped_plan_*: many GEMMs of different shapes in one persistent launch."""
 
-    def __init__(self, problems, mode="f16"):
-        """`problems`: list of (A, B, C) 2-D device tensors (A: M x K, B: K x N, C: M x N)."""
+    def __init__(self, problems, mode="f16", fp32_in=False):
+        """`problems`: list of (A, B, C) 2-D device tensors (A: M x K, B: K x N, C: M x N); A and B
+        in the mode's preconverted form, or FP32 with `fp32_in` (MFG_IN_FP32)."""
         arr = (capi.mfg_problem * len(problems))()
         self._keep = []
         for i, (A, B, C) in enumerate(problems):
@@ -93,8 +94,8 @@ class GroupedPlan:
             arr[i] = capi.mfg_problem(M, N, K, _ld(A), _ld(B), _ld(C), A.data_ptr(), B.data_ptr(), C.data_ptr())
             self._keep.append((A, B, C))
         h = ctypes.c_void_p()
-        check("mfg_grouped_plan_create", lib().mfg_grouped_plan_create(len(problems), arr, mode_of(mode),
-                                                                        ctypes.byref(h)))
+        m = mode_of(mode) | (capi.MFG_IN_FP32 if fp32_in else 0)
+        check("mfg_grouped_plan_create", lib().mfg_grouped_plan_create(len(problems), arr, m, ctypes.byref(h)))
         self.handle = h
 
     def run(self, alpha=1.0, beta=0.0, stream=None):

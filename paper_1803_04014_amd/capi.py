@@ -31,6 +31,7 @@ MFG_F16_SPLIT4 = 5
 MFG_FP8_E4M3 = 6
 MFG_NUM_MODES = 7
 MFG_IN_PRECONVERTED = 0x100
+MFG_IN_FP32 = 0x200  # grouped plans: FP32 operands, converted on every run
 MFG_MODE_MASK = 0xFF
 MFG_RESID_SCALE_LOG2 = 11
 MFG_FP8_TILE = 128

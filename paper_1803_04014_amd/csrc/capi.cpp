@@ -323,6 +323,11 @@ struct mfg_grouped_plan {
     GroupedSplit split{};
     GroupedWork* d_work = nullptr;
     int64_t* d_planes = nullptr;  // refined modes: residual-plane offsets per work item
+    // MFG_IN_FP32: converted operands (plan-owned) and the conversion job list
+    void* d_conv = nullptr;
+    ConvJob* d_jobs = nullptr;
+    ConvTask* d_tasks = nullptr;
+    int64_t ntasks = 0;
     double flops = 0.0, bytes = 0.0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -330,11 +335,40 @@ struct mfg_grouped_plan {
     hipStream_t cap_stream = nullptr;  // capture happens here: the legacy NULL stream cannot be captured
 };
 
+static void plan_free(mfg_grouped_plan* plan) {
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->d_work) (void)hipFree(plan->d_work);
+    if (plan->d_planes) (void)hipFree(plan->d_planes);
+    if (plan->d_conv) (void)hipFree(plan->d_conv);
+    if (plan->d_jobs) (void)hipFree(plan->d_jobs);
+    if (plan->d_tasks) (void)hipFree(plan->d_tasks);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    delete plan;
+}
+
+// Host array -> new device allocation (nullptr for an empty array).
+template <class T>
+static int upload(const std::vector<T>& h, T** d) {
+    *d = nullptr;
+    if (h.empty()) return MFG_OK;
+    if (hipMalloc((void**)d, h.size() * sizeof(T)) != hipSuccess) {
+        *d = nullptr;
+        (void)hipGetLastError();
+        return MFG_ERR_NO_MEMORY;
+    }
+    MFG_HIP_CHECK(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return MFG_OK;
+}
+
 static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, mfg_grouped_plan** out) {
     if (!out || count < 0 || (count > 0 && !probs)) return MFG_ERR_INVALID_ARG;
     *out = nullptr;
     const int m = mode & MFG_MODE_MASK;
-    if ((mode & ~(MFG_MODE_MASK | MFG_IN_PRECONVERTED)) != 0 || m < 0 || m >= MFG_NUM_MODES) return MFG_ERR_INVALID_ARG;
+    if ((mode & ~(MFG_MODE_MASK | MFG_IN_PRECONVERTED | MFG_IN_FP32)) != 0 || m < 0 || m >= MFG_NUM_MODES)
+        return MFG_ERR_INVALID_ARG;
+    const bool fp32_in = (mode & MFG_IN_FP32) != 0;
+    if (fp32_in && (mode & MFG_IN_PRECONVERTED)) return MFG_ERR_INVALID_ARG;
     if (m == MFG_F32 || m == MFG_FP8_E4M3) return MFG_ERR_UNSUPPORTED;
     if (count > ((int64_t)1 << 31) - 1) return MFG_ERR_UNSUPPORTED;
     // Refined modes read their operands in the preconverted storage form:
@@ -345,48 +379,92 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
     std::vector<GroupedDesc> descs((size_t)count);
     std::vector<GroupedWork> work;
     double flops = 0.0, bytes = 0.0;
+    // MFG_IN_FP32: byte offsets of each problem's converted A and B in the
+    // plan's storage (256-byte aligned, ld rounded up to 8 elements)
+    std::vector<int64_t> conv_off(fp32_in ? (size_t)count * 2 : 0);
+    int64_t conv_bytes = 0;
     for (int64_t i = 0; i < count; ++i) {
         const mfg_problem& p = probs[i];
         int st = validate_gemm(p.M, p.N, p.K, p.A, p.lda, p.B, p.ldb, p.C, p.ldc, m);
         if (st != MFG_OK) return st;
         if (p.M > ((int64_t)1 << 24) || p.N > ((int64_t)1 << 24) || p.K > INT32_MAX) return MFG_ERR_UNSUPPORTED;
         GroupedDesc& d = descs[(size_t)i];
-        d.M = p.M, d.N = p.N, d.K = p.K, d.lda = p.lda, d.ldb = p.ldb, d.ldc = p.ldc;
-        d.A = static_cast<const uint16_t*>(p.A), d.B = static_cast<const uint16_t*>(p.B), d.C = p.C;
-        d.vec = (al16(p.A) && al16(p.B) && p.lda % 8 == 0 && p.ldb % 8 == 0) ? 1 : 0;
-        d.pad = 0;
-        d.pa = two_a ? p.M * p.lda : 0;
-        d.pb = two_b ? p.K * p.ldb : 0;
+        d.M = p.M, d.N = p.N, d.K = p.K, d.ldc = p.ldc, d.C = p.C, d.pad = 0;
+        if (fp32_in) {  // A and B point into the plan's storage once it exists
+            d.lda = up(p.K, 8), d.ldb = up(p.N, 8), d.vec = 1;
+            conv_off[2 * i] = conv_bytes;
+            conv_bytes += up((two_a ? 2 : 1) * p.M * d.lda * 2, 256);
+            conv_off[2 * i + 1] = conv_bytes;
+            conv_bytes += up((two_b ? 2 : 1) * p.K * d.ldb * 2, 256);
+            bytes += 4.0 * (double)(p.M * p.K + p.K * p.N) +
+                     2.0 * ((two_a ? 2.0 : 1.0) * (double)(p.M * p.K) + (two_b ? 2.0 : 1.0) * (double)(p.K * p.N));
+        } else {
+            d.lda = p.lda, d.ldb = p.ldb;
+            d.A = static_cast<const uint16_t*>(p.A), d.B = static_cast<const uint16_t*>(p.B);
+            d.vec = (al16(p.A) && al16(p.B) && p.lda % 8 == 0 && p.ldb % 8 == 0) ? 1 : 0;
+        }
+        d.pa = two_a ? p.M * d.lda : 0;
+        d.pb = two_b ? p.K * d.ldb : 0;
         flops += 2.0 * (double)p.M * (double)p.N * (double)p.K;
         bytes += 2.0 * ((two_a ? 2.0 : 1.0) * (double)(p.M * p.K) + (two_b ? 2.0 : 1.0) * (double)(p.K * p.N)) +
                  4.0 * (double)(p.M * p.N);
     }
+    std::unique_ptr<mfg_grouped_plan, void (*)(mfg_grouped_plan*)> plan(new mfg_grouped_plan(), plan_free);
+    plan->mode = m, plan->kind = kind_of(m), plan->count = count;
+    plan->flops = flops, plan->bytes = bytes;
+    MFG_HIP_CHECK(hipGetDevice(&plan->device));
+    if (fp32_in && conv_bytes > 0) {
+        if (hipMalloc(&plan->d_conv, (size_t)conv_bytes) != hipSuccess) {
+            plan->d_conv = nullptr;
+            (void)hipGetLastError();
+            return MFG_ERR_NO_MEMORY;
+        }
+        // conversion jobs (A then B of every problem) and their row tasks
+        std::vector<ConvJob> jobs;
+        std::vector<ConvTask> tasks;
+        char* base = static_cast<char*>(plan->d_conv);
+        for (int64_t i = 0; i < count; ++i) {
+            const mfg_problem& p = probs[i];
+            GroupedDesc& d = descs[(size_t)i];
+            d.A = reinterpret_cast<const uint16_t*>(base + conv_off[2 * i]);
+            d.B = reinterpret_cast<const uint16_t*>(base + conv_off[2 * i + 1]);
+            const int ka = m == MFG_BF16 ? 1 : (two_a ? 2 : 0), kb = m == MFG_BF16 ? 1 : (two_b ? 2 : 0);
+            const ConvJob ja{static_cast<const float*>(p.A), const_cast<uint16_t*>(d.A), p.lda, d.lda, p.M, p.K,
+                             d.pa, ka, (al16(p.A) && p.lda % 4 == 0) ? 1 : 0};
+            const ConvJob jb{static_cast<const float*>(p.B), const_cast<uint16_t*>(d.B), p.ldb, d.ldb, p.K, p.N,
+                             d.pb, kb, (al16(p.B) && p.ldb % 4 == 0) ? 1 : 0};
+            for (const ConvJob& j : {ja, jb}) {
+                if (j.rows == 0 || j.cols == 0) continue;
+                if ((int64_t)jobs.size() >= INT32_MAX) return MFG_ERR_UNSUPPORTED;
+                const int32_t ji = (int32_t)jobs.size();
+                jobs.push_back(j);
+                for (int64_t r = 0; r < j.rows; r += kJobRows) tasks.push_back(ConvTask{ji, (int32_t)r});
+            }
+        }
+        int st = upload(jobs, &plan->d_jobs);
+        if (st == MFG_OK) st = upload(tasks, &plan->d_tasks);
+        if (st != MFG_OK) return st;
+        plan->ntasks = (int64_t)tasks.size();
+    }
     GroupedSplit split{};
     std::vector<int64_t> planes;
     build_grouped_work(descs.data(), count, work, split, two_a ? &planes : nullptr, grouped_tile(kind_of(m)));
-    std::unique_ptr<mfg_grouped_plan> plan(new mfg_grouped_plan());
-    plan->split = split;
-    plan->mode = m, plan->kind = kind_of(m), plan->count = count, plan->nwork = (int64_t)work.size();
-    plan->flops = flops, plan->bytes = bytes;
-    MFG_HIP_CHECK(hipGetDevice(&plan->device));
-    if (!work.empty()) {
-        if (hipMalloc(&plan->d_work, work.size() * sizeof(GroupedWork)) != hipSuccess) return MFG_ERR_NO_MEMORY;
-        hipError_t e = hipMemcpy(plan->d_work, work.data(), work.size() * sizeof(GroupedWork), hipMemcpyHostToDevice);
-        if (e == hipSuccess && two_a) {
-            if (hipMalloc(&plan->d_planes, planes.size() * sizeof(int64_t)) != hipSuccess) {
-                (void)hipFree(plan->d_work);
-                return MFG_ERR_NO_MEMORY;
-            }
-            e = hipMemcpy(plan->d_planes, planes.data(), planes.size() * sizeof(int64_t), hipMemcpyHostToDevice);
-        }
-        if (e != hipSuccess) {
-            (void)hipFree(plan->d_work);
-            if (plan->d_planes) (void)hipFree(plan->d_planes);
-            return hip_fail(e);
-        }
-    }
+    plan->split = split, plan->nwork = (int64_t)work.size();
+    int st = upload(work, &plan->d_work);
+    if (st == MFG_OK && two_a) st = upload(planes, &plan->d_planes);
+    if (st != MFG_OK) return st;
     *out = plan.release();
     return MFG_OK;
+}
+
+// One run of a plan on stream s: the conversion pass (MFG_IN_FP32), then the
+// grouped kernel launch(es).
+static int plan_launch(mfg_grouped_plan* plan, float alpha, float beta, hipStream_t s) {
+    if (plan->ntasks > 0) {
+        const int st = launch_convert_jobs(plan->d_jobs, plan->d_tasks, plan->ntasks, s);
+        if (st != MFG_OK) return st;
+    }
+    return grouped_launch(plan->kind, plan->d_work, plan->d_planes, plan->split, alpha, beta, s);
 }
 
 extern "C" int mfg_grouped_plan_create(int64_t count, const mfg_problem* problems, int mode,
@@ -396,7 +474,7 @@ extern "C" int mfg_grouped_plan_create(int64_t count, const mfg_problem* problem
 
 extern "C" int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, void* stream) {
     if (!plan) return MFG_ERR_INVALID_ARG;
-    MFG_GUARD(grouped_launch(plan->kind, plan->d_work, plan->d_planes, plan->split, alpha, beta, (hipStream_t)stream));
+    MFG_GUARD(plan_launch(plan, alpha, beta, (hipStream_t)stream));
 }
 
 static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hipStream_t s) {
@@ -409,7 +487,7 @@ static int graph_launch_impl(mfg_grouped_plan* plan, float alpha, float beta, hi
     if (!plan->exec) {
         if (!plan->cap_stream) MFG_HIP_CHECK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
         MFG_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
-        int st = grouped_launch(plan->kind, plan->d_work, plan->d_planes, plan->split, alpha, beta, plan->cap_stream);
+        int st = plan_launch(plan, alpha, beta, plan->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
         if (st != MFG_OK) {
@@ -444,12 +522,7 @@ extern "C" int mfg_grouped_plan_info(const mfg_grouped_plan* plan, double* flops
 
 extern "C" int mfg_grouped_plan_destroy(mfg_grouped_plan* plan) {
     if (!plan) return MFG_ERR_INVALID_ARG;
-    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
-    if (plan->graph) (void)hipGraphDestroy(plan->graph);
-    if (plan->d_work) (void)hipFree(plan->d_work);
-    if (plan->d_planes) (void)hipFree(plan->d_planes);
-    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
-    delete plan;
+    plan_free(plan);
     return MFG_OK;
 }
 

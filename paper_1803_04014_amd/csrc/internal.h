@@ -106,6 +106,21 @@ int launch_quantize_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx,
 // scales in the untransposed tile order.
 int launch_quantize_fp8_t(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint8_t* codes_t, int64_t ldt,
                           float* scales, hipStream_t s);
+// Conversion job lists (grouped plans over FP32 operands): job = one matrix,
+// rows x cols FP32 at src (ld lds) into 16-bit dst (ld ldo); kind 0 rne16,
+// 1 rnebf16, 2 split (head at dst, scaled residual at dst + plane).  Task =
+// kJobRows rows of one job (one workgroup).
+constexpr int kJobRows = 8;
+struct ConvJob {
+    const float* src;
+    uint16_t* dst;
+    int64_t lds, ldo, rows, cols, plane;
+    int32_t kind, vec;  // vec: src rows 16-byte aligned (whole four-float loads)
+};
+struct ConvTask {
+    int32_t job, row0;
+};
+int launch_convert_jobs(const ConvJob* jobs, const ConvTask* tasks, int64_t ntasks, hipStream_t s);
 int launch_error_norms(int64_t M, int64_t N, const float* C, int64_t ldc, const double* R,
                        int64_t ldr, double* out4, hipStream_t s);
 int launch_count_mismatch(int64_t M, int64_t N, const float* C, int64_t ldc, const float* R,

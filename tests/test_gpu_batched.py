@@ -214,3 +214,44 @@ def test_grouped_refined_degenerate_shapes(mode):
         mfg.gemm(dA, dB, solo, 0.5, 2.0, mode=mode, preconverted=True)
         assert np.array_equal(host(dC).view(np.uint32), host(solo).view(np.uint32)), f"{mode} shape {shapes[i]}"
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["f16", "bf16", "refine_a", "split3", "split4"])
+def test_grouped_fp32_input_equals_solo(mode):
+    """MFG_IN_FP32 plans: one conversion launch over every problem's FP32 A and
+    B into plan-owned storage, then the grouped kernel.  Every problem bitwise
+    equal to mfg_gemm on its FP32 operands alone (unaligned and padded
+    operands, tiny and empty problems included), graph replays equal to the
+    eager run, and the plan's byte count including the conversion pass."""
+    dims = [tuple(int(x) for x in d) for d in workloads.loguniform_dims(43, 90, 1, 300)]
+    dims += [(0, 5, 7), (5, 0, 7), (5, 7, 0), (1, 1, 1)]
+    probs, c0 = [], []
+    for i, (m, n, k) in enumerate(dims):
+        A, B, C0 = workloads.normal(4000 + i, [(m, k + 3), (k, n + 5), (m, n)])
+        dA, dB = dev(A), dev(B)
+        if i % 4 == 0:  # one element into the buffer: rows not 16-byte aligned
+            dA, dB = dA[:, 1:k + 1], dB[:, 2:n + 2]
+        else:
+            dA, dB = dA[:, :k], dB[:, :n]
+        probs.append((dA, dB, dev(C0)))
+        c0.append(C0)
+    plan = mfg.GroupedPlan(probs, mode, fp32_in=True)
+    npa = 1 if mode in ("f16", "bf16") else 2
+    npb = 2 if mode in ("split3", "split4") else 1
+    exp = sum(4 * (m * k + k * n) + 2 * (npa * m * k + npb * k * n) + 2 * (npa * m * k + npb * k * n) + 4 * m * n
+              for (m, n, k) in dims)
+    assert plan.info()["bytes"] == pytest.approx(exp)
+    plan.run(0.75, 0.5)
+    first = [host(p[2]).copy() for p in probs]
+    for i, (dA, dB, dC) in enumerate(probs):
+        solo = dev(c0[i])
+        mfg.gemm(dA, dB, solo, 0.75, 0.5, mode=mode)
+        assert np.array_equal(first[i].view(np.uint32), host(solo).view(np.uint32)), f"{mode} problem {i} {dims[i]}"
+    for rep in range(2):
+        for (dA, dB, dC), C0 in zip(probs, c0):
+            dC.copy_(dev(C0))
+        plan.graph_launch(0.75, 0.5)
+        torch.cuda.synchronize()
+        for i in range(0, len(probs), 5):
+            assert np.array_equal(host(probs[i][2]).view(np.uint32), first[i].view(np.uint32)), f"replay {rep} {i}"
+    plan.close()
