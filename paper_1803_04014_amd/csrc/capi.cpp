@@ -430,15 +430,15 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
             d.B = reinterpret_cast<const uint16_t*>(base + conv_off[2 * i + 1]);
             const int ka = m == MFG_BF16 ? 1 : (two_a ? 2 : 0), kb = m == MFG_BF16 ? 1 : (two_b ? 2 : 0);
             const ConvJob ja{static_cast<const float*>(p.A), const_cast<uint16_t*>(d.A), p.lda, d.lda, p.M, p.K,
-                             d.pa, ka, (al16(p.A) && p.lda % 4 == 0) ? 1 : 0};
+                             d.pa, ka, (al16(p.A) && p.lda % 4 == 0) ? 1 : 0, conv_rows_per_task(p.M, p.K), 0};
             const ConvJob jb{static_cast<const float*>(p.B), const_cast<uint16_t*>(d.B), p.ldb, d.ldb, p.K, p.N,
-                             d.pb, kb, (al16(p.B) && p.ldb % 4 == 0) ? 1 : 0};
+                             d.pb, kb, (al16(p.B) && p.ldb % 4 == 0) ? 1 : 0, conv_rows_per_task(p.K, p.N), 0};
             for (const ConvJob& j : {ja, jb}) {
                 if (j.rows == 0 || j.cols == 0) continue;
                 if ((int64_t)jobs.size() >= INT32_MAX) return MFG_ERR_UNSUPPORTED;
                 const int32_t ji = (int32_t)jobs.size();
                 jobs.push_back(j);
-                for (int64_t r = 0; r < j.rows; r += kJobRows) tasks.push_back(ConvTask{ji, (int32_t)r});
+                for (int64_t r = 0; r < j.rows; r += j.rpt) tasks.push_back(ConvTask{ji, (int32_t)r});
             }
         }
         int st = upload(jobs, &plan->d_jobs);

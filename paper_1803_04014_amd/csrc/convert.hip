@@ -240,46 +240,50 @@ int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, ui
 
 // ---------------------------------------------------- conversion job lists
 // Many (rows x cols) FP32 matrices rounded or split in one launch: one
-// workgroup per task of kJobRows rows of one job, columns four per thread.
-// dst (and dst + plane) rows must be 16-byte aligned with ldo a multiple of 8.
-// The element formulas are round16_kernel's and split16_kernel's, so every
-// value comes out bitwise as the per-matrix conversions write it.
+// workgroup per task of j.rpt rows of one job, whose four-element pieces
+// (row-major over the task's rows) are dealt to the threads in turn, so
+// narrow matrices keep every thread busy.  The element formulas are
+// round16_kernel's and split16_kernel's, so every value comes out bitwise as
+// the per-matrix conversions write it.  dst (and dst + plane) rows must be
+// 16-byte aligned with ldo a multiple of 8.
 __global__ __launch_bounds__(kEltThreads) void convert_jobs_kernel(const ConvJob* jobs, const ConvTask* tasks) {
     const ConvTask t = tasks[blockIdx.x];
     const ConvJob j = jobs[t.job];
-    const int64_t r1 = (int64_t)t.row0 + kJobRows < j.rows ? (int64_t)t.row0 + kJobRows : j.rows;
-    for (int64_t r = t.row0; r < r1; ++r) {
+    const uint32_t cpr = (uint32_t)((j.cols + 3) / 4);  // pieces per row
+    const int64_t nr = j.rows - t.row0 < j.rpt ? j.rows - t.row0 : j.rpt;
+    const uint32_t total = (uint32_t)nr * cpr;  // <= max(kJobChunks, cpr)
+    for (uint32_t e = threadIdx.x; e < total; e += kEltThreads) {
+        const uint32_t rr = e / cpr;
+        const int64_t r = t.row0 + rr, c0 = (int64_t)(e - rr * cpr) * 4;
         const float* x = j.src + r * j.lds;
         uint16_t* ho = j.dst + r * j.ldo;
         uint16_t* qo = ho + j.plane;  // residual plane (split jobs)
-        for (int64_t c0 = (int64_t)threadIdx.x * kColsPerThread; c0 < j.cols; c0 += kColsPerBlock) {
-            float v[4] = {0.f, 0.f, 0.f, 0.f};
-            int cnt = 0;
-            if (j.vec && c0 + kColsPerThread <= j.cols) {
-                const f32x4 w = *reinterpret_cast<const f32x4*>(x + c0);
-                v[0] = w[0], v[1] = w[1], v[2] = w[2], v[3] = w[3];
-                cnt = 4;
-            } else {
-                for (int e = 0; e < kColsPerThread; ++e)
-                    if (c0 + e < j.cols) v[e] = x[c0 + e], cnt = e + 1;
-            }
-            uint16_t h[4], q[4];
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        int cnt = 0;
+        if (j.vec && c0 + kColsPerThread <= j.cols) {
+            const f32x4 w = *reinterpret_cast<const f32x4*>(x + c0);
+            v[0] = w[0], v[1] = w[1], v[2] = w[2], v[3] = w[3];
+            cnt = 4;
+        } else {
+            for (int q = 0; q < kColsPerThread; ++q)
+                if (c0 + q < j.cols) v[q] = x[c0 + q], cnt = q + 1;
+        }
+        uint16_t h[4], q[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                h[e] = j.kind == 1 ? f32_to_bf16_bits(v[e]) : f32_to_f16_bits(v[e]);
-                q[e] = f32_to_f16_bits((v[e] - f16_bits_to_f32(h[e])) * 2048.0f);  // as split16_kernel
-            }
-            if (cnt == 4) {  // dst rows are 16-byte aligned (ldo a multiple of 8): 8-byte pieces
-                *reinterpret_cast<u32x2*>(ho + c0) =
-                    u32x2{(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
-                if (j.kind == 2)
-                    *reinterpret_cast<u32x2*>(qo + c0) =
-                        u32x2{(uint32_t)q[0] | ((uint32_t)q[1] << 16), (uint32_t)q[2] | ((uint32_t)q[3] << 16)};
-            } else {
-                for (int e = 0; e < cnt; ++e) {
-                    ho[c0 + e] = h[e];
-                    if (j.kind == 2) qo[c0 + e] = q[e];
-                }
+        for (int i = 0; i < 4; ++i) {
+            h[i] = j.kind == 1 ? f32_to_bf16_bits(v[i]) : f32_to_f16_bits(v[i]);
+            q[i] = f32_to_f16_bits((v[i] - f16_bits_to_f32(h[i])) * 2048.0f);  // as split16_kernel
+        }
+        if (cnt == 4) {  // dst rows are 16-byte aligned (ldo a multiple of 8): 8-byte pieces
+            *reinterpret_cast<u32x2*>(ho + c0) =
+                u32x2{(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
+            if (j.kind == 2)
+                *reinterpret_cast<u32x2*>(qo + c0) =
+                    u32x2{(uint32_t)q[0] | ((uint32_t)q[1] << 16), (uint32_t)q[2] | ((uint32_t)q[3] << 16)};
+        } else {
+            for (int i = 0; i < cnt; ++i) {
+                ho[c0 + i] = h[i];
+                if (j.kind == 2) qo[c0 + i] = q[i];
             }
         }
     }

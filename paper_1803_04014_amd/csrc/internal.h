@@ -109,14 +109,19 @@ int launch_quantize_fp8_t(int64_t rows, int64_t cols, const float* X, int64_t ld
 // Conversion job lists (grouped plans over FP32 operands): job = one matrix,
 // rows x cols FP32 at src (ld lds) into 16-bit dst (ld ldo); kind 0 rne16,
 // 1 rnebf16, 2 split (head at dst, scaled residual at dst + plane).  Task =
-// kJobRows rows of one job (one workgroup).
-constexpr int kJobRows = 8;
+// rpt rows of one job (one workgroup): about kJobChunks four-element pieces.
+constexpr int kJobChunks = 512;
 struct ConvJob {
     const float* src;
     uint16_t* dst;
     int64_t lds, ldo, rows, cols, plane;
     int32_t kind, vec;  // vec: src rows 16-byte aligned (whole four-float loads)
+    int32_t rpt, pad;   // rows per task
 };
+inline int32_t conv_rows_per_task(int64_t rows, int64_t cols) {
+    const int64_t cpr = (cols + 3) / 4, r = kJobChunks / (cpr > 0 ? cpr : 1);
+    return (int32_t)(r < 1 ? 1 : (r < rows ? r : rows));
+}
 struct ConvTask {
     int32_t job, row0;
 };
