@@ -130,3 +130,27 @@ def test_tuned_table_round_trip(tmp_path):
     assert rows == [f"{capi.MFG_F16} 12 12 12 3".split()]
     L.mfg_tune_clear()
     assert L.mfg_tune_lookup(4096, 4096, 4096, capi.MFG_F16) == base
+
+
+def test_grouped_plan_rejects_bad_modes_before_any_device_call():
+    """Mode and flag checks of mfg_grouped_plan_create come before any HIP call:
+    unknown flags and MFG_IN_FP32 together with MFG_IN_PRECONVERTED are
+    invalid, FP32 and FP8 plans unsupported, and `out` is cleared."""
+    L = mfg.lib()
+    probs = (capi.mfg_problem * 1)()
+    probs[0] = capi.mfg_problem(8, 8, 8, 8, 8, 8, P, P, P)
+    h = ctypes.c_void_p(1234)
+    cases = [
+        (capi.MFG_F16 | capi.MFG_IN_FP32 | capi.MFG_IN_PRECONVERTED, capi.MFG_ERR_INVALID_ARG),
+        (capi.MFG_F16 | 0x400, capi.MFG_ERR_INVALID_ARG),
+        (99, capi.MFG_ERR_INVALID_ARG),
+        (capi.MFG_F32, capi.MFG_ERR_UNSUPPORTED),
+        (capi.MFG_FP8_E4M3 | capi.MFG_IN_FP32, capi.MFG_ERR_UNSUPPORTED),
+    ]
+    for mode, expect in cases:
+        h.value = 1234
+        assert L.mfg_grouped_plan_create(1, probs, mode, ctypes.byref(h)) == expect, hex(mode)
+        assert not h.value
+    assert L.mfg_grouped_plan_create(-1, probs, capi.MFG_F16, ctypes.byref(h)) == capi.MFG_ERR_INVALID_ARG
+    # MFG_IN_FP32 is a grouped-plan flag only: the single GEMM's validation rejects it
+    assert L.mfg_validate_gemm(8, 8, 8, P, 8, P, 8, P, 8, capi.MFG_F16 | capi.MFG_IN_FP32) == capi.MFG_ERR_INVALID_ARG
