@@ -401,6 +401,11 @@ def main() -> int:
         dCx = dC0.clone()
         ms = timed(lambda: mfg.gemm(dAb, dBb, dCx, 1.0, 1.0, mode="bf16", preconverted=True), reps)
         ex["bf16_n8192"] = {"tflops": round(flops / ms / 1e9, 1), "pct_peak": round(flops / ms / 1e9 / 25.0, 1)}
+        # context only (not this library): the vendor GEMM behind torch.matmul on the
+        # same FP16 operands, FP16 output and no C read -- less traffic than the headline
+        ms = timed(lambda: torch.matmul(dA, dB), reps)
+        ex["context_torch_matmul_f16_n8192"] = {"tflops": round(flops / ms / 1e9, 1),
+                                                "note": "vendor library via torch.matmul, FP16 out, beta = 0"}
         ms = timed(lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode="f32"), 3, warm=1)
         ex["f32_n8192"] = {"tflops": round(flops / ms / 1e9, 1), "pct_peak": round(flops / ms / 1e9 / 1.573, 1)}
         for mode in ("refine_a", "split3", "split4", "fp8"):
