@@ -156,6 +156,17 @@ def split_f16(x, s: float = S_RESID) -> Split:
     return Split(hb, rb, h, f16_decode(rb), s)
 
 
+def split_bf16(x) -> Split:
+    """Eq. R on bfloat16 planes: head rnebf16(x), residual rnebf16(x - head), unscaled
+    (bfloat16 has FP32's exponent range, so the residual needs no scaling to stay
+    out of the subnormals); x - head is exact in FP32 and FP64."""
+    x64 = np.asarray(x, dtype=np.float64)
+    hb = bf16_encode(x64)
+    h = bf16_decode(hb)
+    rb = bf16_encode(x64 - h)
+    return Split(hb, rb, h, bf16_decode(rb), 1.0)
+
+
 @dataclass
 class Fp8Tiles:
     """Per-tile FP8-E4M3 quantisation of a matrix."""
@@ -244,6 +255,7 @@ def mode_terms(mode: str, A, B):
     refine_a : Eq. 1 -- A_h B_h + (R_A/s) B_h, B not split
     split3   : Eq. 2 without the R_A R_B product -- A_h B_h + (A_h R_B + R_A B_h)/s
     split4   : Eq. 2 -- split3 + R_A R_B / s^2
+    bf16_split3 : Eq. 2 without R_A R_B on bfloat16 head and unscaled residual planes
     fp8      : per-tile dequantised codes, deq(A) deq(B)
     """
     A = np.asarray(A, dtype=np.float64)
@@ -264,6 +276,9 @@ def mode_terms(mode: str, A, B):
         if mode == "split4":
             t.append((1.0 / (sa.s * sb.s), sa.resid, sb.resid))
         return t
+    if mode == "bf16_split3":
+        sa, sb = split_bf16(A), split_bf16(B)
+        return [(1.0, sa.head, sb.head), (1.0, sa.head, sb.resid), (1.0, sa.resid, sb.head)]
     if mode == "fp8":
         return [(1.0, fp8_quantize(A).deq, fp8_quantize(B).deq)]
     raise ValueError(f"unknown mode {mode!r}")
@@ -340,10 +355,10 @@ def representation_bound(mode: str, A, B, alpha: float = 1.0, rows=None) -> np.n
         Bt = f16_round(B)
         extra = None
     else:
-        sa, sb = split_f16(A), split_f16(B)
+        sa, sb = (split_bf16(A), split_bf16(B)) if mode == "bf16_split3" else (split_f16(A), split_f16(B))
         At = sa.head + sa.resid / sa.s
         Bt = sb.head + sb.resid / sb.s
-        extra = (np.abs(sa.resid) / sa.s, np.abs(sb.resid) / sb.s) if mode == "split3" else None
+        extra = (np.abs(sa.resid) / sa.s, np.abs(sb.resid) / sb.s) if mode in ("split3", "bf16_split3") else None
     dA, dB = np.abs(A - At), np.abs(B - Bt)
     bnd = gemm(dA, np.abs(B), rows=rows) + gemm(np.abs(At), dB, rows=rows)
     if extra is not None:

@@ -77,7 +77,7 @@ def test_refined_modes_equal_f16_on_fp16_exact_inputs(mode):
 
 
 @pytest.mark.parametrize("dist", ["uniform", "normal", "pow2"])
-@pytest.mark.parametrize("mode", ["f16", "bf16", "refine_a", "split3", "split4", "fp8"])
+@pytest.mark.parametrize("mode", ["f16", "bf16", "refine_a", "split3", "split4", "fp8", "bf16_split3"])
 def test_mode_reference_within_representation_bound(mode, dist):
     A, B = workloads.by_name(dist, 12, [(48, 160), (160, 40)])
     ex = oracle.exact(A, B)
@@ -157,3 +157,69 @@ def test_fp8_quantize_uses_each_tile_scale():
     d = np.abs(q.deq - A.astype(np.float64))
     big = np.abs(A.astype(np.float64)) >= 2.0 ** -6 * np.repeat(np.repeat(q.scales, 128, 0), 128, 1)
     assert np.all(d[big] <= 2.0 ** -4 * np.abs(A.astype(np.float64))[big])
+
+
+# ------------------------------------------------------------- BF16 split
+def test_bf16_split_residual_exact_and_16_bit_bound():
+    """Head rnebf16(x) and residual rnebf16(x - head), unscaled: x - head is exact in
+    FP32, and head + residual is within 2^-16 |x| (two 8-bit significands) while the
+    residual stays a normal number (|x| >= 2^-110), up to FP32's largest binade --
+    where the FP16 split overflows.  Below that the residual loses bits in the
+    subnormals, as the unscaled FP16 residual does below 2^-3."""
+    rng = np.random.default_rng(3)
+    e = rng.uniform(-110, 127.9, 200_000)
+    x = (np.where(rng.random(e.size) < 0.5, -1, 1) * np.exp2(e)).astype(np.float32)
+    x = x[np.isfinite(x)]
+    sp = oracle.split_bf16(x)
+    x64 = x.astype(np.float64)
+    r = x64 - sp.head
+    assert np.array_equal(r.astype(np.float32).astype(np.float64), r)
+    assert sp.s == 1.0
+    err = np.abs(x64 - (sp.head + sp.resid))
+    assert np.all(err <= 2.0 ** -16 * np.abs(x64))
+    # without the residual: bfloat16 rounding alone, up to 2^-8 relative
+    assert np.max(np.abs(r) / np.abs(x64)) > 2.0 ** -10
+    # the FP16 split cannot hold these magnitudes at all
+    big = np.float32(1e30)
+    assert np.isinf(oracle.split_f16(np.array([big])).head[0])
+    assert oracle.split_bf16(np.array([big])).head[0] + oracle.split_bf16(np.array([big])).resid[0] == \
+        pytest.approx(1e30, rel=2.0 ** -16)
+
+
+def test_bf16_split_is_exact_on_16_bit_values():
+    """A value that is the sum of two bfloat16 numbers, the second below half an
+    ulp of the first and within FP32's 24 bits of it, is head + residual exactly."""
+    rng = np.random.default_rng(4)
+    a = oracle.bf16_round(rng.uniform(1, 2, 5000) * np.exp2(rng.integers(-20, 20, 5000)))
+    sign = np.where(rng.random(5000) < 0.5, -1.0, 1.0)
+    b = oracle.bf16_round(a * sign * np.exp2(-rng.uniform(9.1, 15.5, 5000)))
+    x = (a + b).astype(np.float32)
+    assert np.array_equal(x.astype(np.float64), a + b)  # fits FP32
+    sp = oracle.split_bf16(x)
+    assert np.array_equal(sp.head + sp.resid, a + b)
+
+
+def test_bf16_split3_equals_bf16_on_bf16_exact_inputs_and_ordering():
+    A, B = workloads.small_ints(15, [(40, 96), (96, 24)], -100, 100)
+    assert np.array_equal(oracle.reference("bf16_split3", A, B).value, oracle.reference("bf16", A, B).value)
+    A, B = workloads.uniform(16, [(64, 512), (512, 64)])
+    ex = oracle.exact(A, B)
+    err = {m: np.max(np.abs(oracle.reference(m, A, B).value - ex)) for m in ("bf16", "bf16_split3", "split3")}
+    assert err["bf16_split3"] < 2.0 ** -6 * err["bf16"]   # ~2^-8 gain per operand
+    assert err["split3"] < err["bf16_split3"]             # 22 bits beat 16
+
+
+@pytest.mark.parametrize("flavour", ["dropped", "scaled", "wrong_sign"])
+def test_bf16_bound_catches_planted_mistakes(flavour):
+    A, B = workloads.normal(17, [(64, 64), (64, 64)])
+    ex = oracle.exact(A, B)
+    bnd = oracle.representation_bound("bf16_split3", A, B)
+    sa, sb = oracle.split_bf16(A), oracle.split_bf16(B)
+    g = oracle.gemm
+    if flavour == "dropped":
+        bad = g(sa.head, sb.head) + g(sa.head, sb.resid)
+    elif flavour == "scaled":  # the FP16 split's 2^-11 applied to unscaled residuals
+        bad = g(sa.head, sb.head) + (g(sa.head, sb.resid) + g(sa.resid, sb.head)) / 2048.0
+    else:
+        bad = g(sa.head, sb.head) - (g(sa.head, sb.resid) + g(sa.resid, sb.head))
+    assert np.any(np.abs(bad - ex) > bnd * 4)
