@@ -65,6 +65,11 @@ enum {
  *   MFG_F16_SPLIT3    two-sided refinement, paper Eq. 2 without R_A R_B:
  *                     A_h B_h + (A_h R_B + R_A B_h) / s.
  *   MFG_F16_SPLIT4    paper Eq. 2 in full: SPLIT3 + R_A R_B / s^2.
+ *   MFG_BF16_SPLIT3   Eq. 2 without R_A R_B on bfloat16 planes: head
+ *                     A_h = rnebf16(A), residual R_A = rnebf16(A - A_h),
+ *                     unscaled (bfloat16 keeps FP32's exponent range):
+ *                     A_h B_h + A_h R_B + R_A B_h.  About 16 significant
+ *                     bits per operand over FP32's whole range.
  *   MFG_FP8_E4M3      OCP E4M3 codes with one power-of-two FP32 scale per
  *                     128 x 128 tile of A (M x K) and of B (K x N).
  * The residual scale is s = 2^11 (MFG_RESID_SCALE_LOG2).
@@ -75,6 +80,7 @@ enum {
  *   REFINE_A          A: head plane then residual plane at A + rows*lda
  *                     elements; B: FP16 head plane only.
  *   SPLIT3 / SPLIT4   A and B: head plane then residual plane.
+ *   BF16_SPLIT3       likewise, bfloat16 planes.
  *   FP8_E4M3          byte codes (ld in bytes) followed, at byte offset
  *                     mfg_fp8_scale_offset(rows, ld), by ceil(rows/128) x
  *                     ceil(cols/128) FP32 tile scales, row-major.
@@ -88,7 +94,8 @@ enum {
     MFG_F16_SPLIT3 = 4,
     MFG_F16_SPLIT4 = 5,
     MFG_FP8_E4M3 = 6,
-    MFG_NUM_MODES = 7
+    MFG_BF16_SPLIT3 = 7,
+    MFG_NUM_MODES = 8
 };
 #define MFG_IN_PRECONVERTED 0x100
 /* mfg_grouped_plan_create only: A and B are FP32 (see "grouped GEMM"). */

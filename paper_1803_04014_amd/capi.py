@@ -29,7 +29,8 @@ MFG_F16_REFINE_A = 3
 MFG_F16_SPLIT3 = 4
 MFG_F16_SPLIT4 = 5
 MFG_FP8_E4M3 = 6
-MFG_NUM_MODES = 7
+MFG_BF16_SPLIT3 = 7
+MFG_NUM_MODES = 8
 MFG_IN_PRECONVERTED = 0x100
 MFG_IN_FP32 = 0x200  # grouped plans: FP32 operands, converted on every run
 MFG_MODE_MASK = 0xFF
@@ -38,7 +39,7 @@ MFG_FP8_TILE = 128
 
 MODE_BY_NAME = {
     "f32": MFG_F32, "f16": MFG_F16, "bf16": MFG_BF16, "refine_a": MFG_F16_REFINE_A,
-    "split3": MFG_F16_SPLIT3, "split4": MFG_F16_SPLIT4, "fp8": MFG_FP8_E4M3,
+    "split3": MFG_F16_SPLIT3, "split4": MFG_F16_SPLIT4, "fp8": MFG_FP8_E4M3, "bf16_split3": MFG_BF16_SPLIT3,
 }
 
 i64, i32, f32, f64, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_double, ctypes.c_void_p

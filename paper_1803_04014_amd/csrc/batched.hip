@@ -167,6 +167,7 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
             case K_REFINE_A: MFG_BATCHED_LDS(K_REFINE_A) break;
             case K_SPLIT3: MFG_BATCHED_LDS(K_SPLIT3) break;
             case K_SPLIT4: MFG_BATCHED_LDS(K_SPLIT4) break;
+            case K_BF16_SPLIT3: MFG_BATCHED_LDS(K_BF16_SPLIT3) break;
             default: return MFG_ERR_INVALID_ARG;
         }
 #undef MFG_BATCHED_LDS
@@ -184,6 +185,9 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
             break;
         case K_SPLIT4:
             hipLaunchKernelGGL(gemm16_batched_small<K_SPLIT4>, dim3(grid), dim3(256), 0, s, a, count, v);
+            break;
+        case K_BF16_SPLIT3:
+            hipLaunchKernelGGL(gemm16_batched_small<K_BF16_SPLIT3>, dim3(grid), dim3(256), 0, s, a, count, v);
             break;
         default: return MFG_ERR_INVALID_ARG;
     }
@@ -584,6 +588,7 @@ static int wg_per_cu(int kind) {
         case K_REFINE_A: return grouped_wg_per_cu<K_REFINE_A>();
         case K_SPLIT3: return grouped_wg_per_cu<K_SPLIT3>();
         case K_SPLIT4: return grouped_wg_per_cu<K_SPLIT4>();
+        case K_BF16_SPLIT3: return grouped_wg_per_cu<K_BF16_SPLIT3>();
         case K_BF16: return grouped_wg_per_cu<K_BF16>();
         default: return grouped_wg_per_cu<K_F16>();
     }
@@ -608,7 +613,7 @@ static void launch_grouped_kind(int list, dim3 grid, const GroupedWork* work, co
 
 int grouped_launch(int kind, const GroupedWork* work, const int64_t* planes, const GroupedSplit& split, float alpha,
                    float beta, hipStream_t s) {
-    if (kind < K_F16 || kind > K_SPLIT4) return MFG_ERR_UNSUPPORTED;
+    if (kind < K_F16 || kind > K_BF16_SPLIT3) return MFG_ERR_UNSUPPORTED;
     if (kind >= K_REFINE_A && !planes) return MFG_ERR_INTERNAL;  // the refined kinds read residual planes
     for (int list = 0; list < 2; ++list) {
         if (split.off[list][kXcds] == split.off[list][0]) continue;  // empty list
@@ -618,6 +623,9 @@ int grouped_launch(int kind, const GroupedWork* work, const int64_t* planes, con
             case K_BF16: launch_grouped_kind<K_BF16>(list, grid, work, planes, split, alpha, beta, s); break;
             case K_REFINE_A: launch_grouped_kind<K_REFINE_A>(list, grid, work, planes, split, alpha, beta, s); break;
             case K_SPLIT3: launch_grouped_kind<K_SPLIT3>(list, grid, work, planes, split, alpha, beta, s); break;
+            case K_BF16_SPLIT3:
+                launch_grouped_kind<K_BF16_SPLIT3>(list, grid, work, planes, split, alpha, beta, s);
+                break;
             default: launch_grouped_kind<K_SPLIT4>(list, grid, work, planes, split, alpha, beta, s); break;
         }
         MFG_LAUNCH_CHECK();

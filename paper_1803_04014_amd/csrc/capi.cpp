@@ -24,17 +24,23 @@ static int kind_of(int m) {
         case MFG_F16_REFINE_A: return K_REFINE_A;
         case MFG_F16_SPLIT3: return K_SPLIT3;
         case MFG_F16_SPLIT4: return K_SPLIT4;
+        case MFG_BF16_SPLIT3: return K_BF16_SPLIT3;
         default: return -1;
     }
 }
 
-static int npa(int m) { return (m == MFG_F16_REFINE_A || m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4) ? 2 : 1; }
-static int npb(int m) { return (m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4) ? 2 : 1; }
+static bool two_planes_a(int m) {
+    return m == MFG_F16_REFINE_A || m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4 || m == MFG_BF16_SPLIT3;
+}
+static bool two_planes_b(int m) { return m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4 || m == MFG_BF16_SPLIT3; }
+static int npa(int m) { return two_planes_a(m) ? 2 : 1; }
+static int npb(int m) { return two_planes_b(m) ? 2 : 1; }
 
 // Write the 16-bit planes of `mode` for an FP32 matrix X (rows x cols).
 static int convert16(int m, int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* p0, uint16_t* p1,
                      int64_t ldo, bool split, hipStream_t s) {
     if (m == MFG_BF16) return launch_round_bf16(rows, cols, X, ldx, p0, ldo, s);
+    if (split && m == MFG_BF16_SPLIT3) return launch_split_bf16(rows, cols, X, ldx, p0, p1, ldo, nullptr, s);
     if (split) return launch_split_f16(rows, cols, X, ldx, p0, p1, ldo, nullptr, s);
     return launch_round_f16(rows, cols, X, ldx, p0, ldo, s);
 }
@@ -249,7 +255,7 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
     Gemm16Args a{};
     a.M = M, a.N = N, a.K = K, a.C = C, a.ldc = ldc, a.sC = strideC, a.alpha = alpha, a.beta = beta;
     bool vec;
-    const bool split_mode = (m == MFG_F16_REFINE_A || m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4);
+    const bool split_mode = two_planes_a(m);
     std::unique_ptr<WsLease> ws;
     if (!split_mode) {
         a.A[0] = static_cast<const uint16_t*>(A), a.B[0] = static_cast<const uint16_t*>(B);
@@ -272,24 +278,20 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
         const float* Bf = static_cast<const float*>(B);
         // A contiguous batch (stride == rows * ld) is one tall matrix.
         if (strideA == M * lda && pa == M * ldk) {
-            if ((st = launch_split_f16(count * M, K, Af, lda, a0, a1, ldk, nullptr, s)) != MFG_OK) return st;
+            if ((st = convert16(m, count * M, K, Af, lda, a0, a1, ldk, true, s)) != MFG_OK) return st;
         } else {
             for (int64_t b = 0; b < count; ++b)
-                if ((st = launch_split_f16(M, K, Af + b * strideA, lda, a0 + b * pa, a1 + b * pa, ldk, nullptr, s)) !=
-                    MFG_OK)
+                if ((st = convert16(m, M, K, Af + b * strideA, lda, a0 + b * pa, a1 + b * pa, ldk, true, s)) != MFG_OK)
                     return st;
         }
-        const bool bsplit = npb(m) == 2;
-        for (int64_t b = 0; b < count; ++b) {
-            if (strideB == K * ldb && pb == K * ldn) {
-                st = bsplit ? launch_split_f16(count * K, N, Bf, ldb, b0, b1, ldn, nullptr, s)
-                            : launch_round_f16(count * K, N, Bf, ldb, b0, ldn, s);
-                if (st != MFG_OK) return st;
-                break;
-            }
-            st = bsplit ? launch_split_f16(K, N, Bf + b * strideB, ldb, b0 + b * pb, b1 + b * pb, ldn, nullptr, s)
-                        : launch_round_f16(K, N, Bf + b * strideB, ldb, b0 + b * pb, ldn, s);
-            if (st != MFG_OK) return st;
+        const bool bsplit = npb(m) == 2;  // REFINE_A: B rounded to its FP16 head only
+        if (strideB == K * ldb && pb == K * ldn) {
+            if ((st = convert16(m, count * K, N, Bf, ldb, b0, b1, ldn, bsplit, s)) != MFG_OK) return st;
+        } else {
+            for (int64_t b = 0; b < count; ++b)
+                if ((st = convert16(m, K, N, Bf + b * strideB, ldb, b0 + b * pb, bsplit ? b1 + b * pb : nullptr, ldn,
+                                    bsplit, s)) != MFG_OK)
+                    return st;
         }
         a.A[0] = a0, a.A[1] = a1, a.B[0] = b0, a.B[1] = b1;
         a.lda = ldk, a.ldb = ldn, a.sA = pa, a.sB = pb;
@@ -374,8 +376,7 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
     // Refined modes read their operands in the preconverted storage form:
     // A's residual plane at A + M*lda, and for the two-sided splits B's at
     // B + K*ldb.
-    const bool two_a = m == MFG_F16_REFINE_A || m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4;
-    const bool two_b = m == MFG_F16_SPLIT3 || m == MFG_F16_SPLIT4;
+    const bool two_a = two_planes_a(m), two_b = two_planes_b(m);
     std::vector<GroupedDesc> descs((size_t)count);
     std::vector<GroupedWork> work;
     double flops = 0.0, bytes = 0.0;
@@ -428,7 +429,8 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
             GroupedDesc& d = descs[(size_t)i];
             d.A = reinterpret_cast<const uint16_t*>(base + conv_off[2 * i]);
             d.B = reinterpret_cast<const uint16_t*>(base + conv_off[2 * i + 1]);
-            const int ka = m == MFG_BF16 ? 1 : (two_a ? 2 : 0), kb = m == MFG_BF16 ? 1 : (two_b ? 2 : 0);
+            const bool bf = m == MFG_BF16 || m == MFG_BF16_SPLIT3;
+            const int ka = two_a ? (bf ? 3 : 2) : (bf ? 1 : 0), kb = two_b ? (bf ? 3 : 2) : (bf ? 1 : 0);
             const ConvJob ja{static_cast<const float*>(p.A), const_cast<uint16_t*>(d.A), p.lda, d.lda, p.M, p.K,
                              d.pa, ka, (al16(p.A) && p.lda % 4 == 0) ? 1 : 0, conv_rows_per_task(p.M, p.K), 0};
             const ConvJob jb{static_cast<const float*>(p.B), const_cast<uint16_t*>(d.B), p.ldb, d.ldb, p.K, p.N,
@@ -580,6 +582,7 @@ static int convert_impl(int64_t rows, int64_t cols, const float* X, int64_t ldx,
         case MFG_F16_REFINE_A:
         case MFG_F16_SPLIT3:
         case MFG_F16_SPLIT4: return launch_split_f16(rows, cols, X, ldx, o16, o16 + rows * ldo, ldo, nullptr, s);
+        case MFG_BF16_SPLIT3: return launch_split_bf16(rows, cols, X, ldx, o16, o16 + rows * ldo, ldo, nullptr, s);
         case MFG_FP8_E4M3: {
             uint8_t* c = static_cast<uint8_t*>(out);
             return launch_quantize_fp8(rows, cols, X, ldx, c, ldo,

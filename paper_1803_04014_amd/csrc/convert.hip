@@ -8,6 +8,9 @@
 //                 exact in FP32 (head is a multiple of ulp16(x), itself a
 //                 multiple of ulp32(x), and |x - head| <= ulp16(x)/2).
 //                 Optionally FP64 sums of x^2 and r^2 and maxima of |x|, |r|.
+//   split_bf16  : the same with bfloat16 planes and an unscaled residual
+//                 (bfloat16 has FP32's exponent range): head = rnebf16(x),
+//                 resid = rnebf16(x - head), x - head exact in FP32 as above.
 //   quantize_fp8: one power-of-two scale per 128 x 128 tile, OCP E4M3 codes,
 //                 round-to-nearest-even, saturating at +-448.
 //   error_norms : max|C - R|, ||C - R||_F, ||R||_F, max|R| in FP64 (the
@@ -37,6 +40,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
 }
 
 __device__ __forceinline__ float f16_bits_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 
 // OCP E4M3 ("fn": no infinity, S.1111.111 = NaN, max 448), RNE, saturating.
 __device__ __forceinline__ uint8_t f32_to_e4m3_sat(float v) {
@@ -163,6 +167,7 @@ __global__ __launch_bounds__(kEltThreads) void reduce_partials(const Red4* part,
 }
 
 // ------------------------------------------------------------------- split
+template <bool BF>
 __global__ __launch_bounds__(kEltThreads) void split16_kernel(int64_t rows, int64_t cols, const float* X,
                                                               int64_t ldx, uint16_t* head, uint16_t* resid,
                                                               int64_t ldo, int vec, Red4* part) {
@@ -183,9 +188,16 @@ __global__ __launch_bounds__(kEltThreads) void split16_kernel(int64_t rows, int6
         uint16_t h[4], q[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            h[j] = f32_to_f16_bits(v[j]);
-            const float rr = v[j] - f16_bits_to_f32(h[j]);  // exact
-            q[j] = f32_to_f16_bits(rr * 2048.0f);            // exact scaling, then RNE
+            float rr;
+            if constexpr (BF) {
+                h[j] = f32_to_bf16_bits(v[j]);
+                rr = v[j] - bf16_bits_to_f32(h[j]);  // exact
+                q[j] = f32_to_bf16_bits(rr);
+            } else {
+                h[j] = f32_to_f16_bits(v[j]);
+                rr = v[j] - f16_bits_to_f32(h[j]);  // exact
+                q[j] = f32_to_f16_bits(rr * 2048.0f);  // exact scaling, then RNE
+            }
             if (part != nullptr && j < cnt) {
                 const double dx = v[j], dr = rr;
                 acc.s0 += dx * dx;
@@ -211,8 +223,9 @@ __global__ __launch_bounds__(kEltThreads) void split16_kernel(int64_t rows, int6
     }
 }
 
-int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head, uint16_t* resid,
-                     int64_t ldo, double* norms, hipStream_t s) {
+template <bool BF>
+static int launch_split(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head, uint16_t* resid,
+                        int64_t ldo, double* norms, hipStream_t s) {
     // with norms, at most 1024 row groups: a block reduces several rows, so the
     // per-block tree and the single-block second stage stay small
     dim3 grid = elt_grid(rows, cols);
@@ -226,8 +239,8 @@ int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, ui
     }
     if (rows > 0 && cols > 0) {
         const int vec = aligned(X, ldx, 16, 4) && aligned(head, ldo, 8, 4) && aligned(resid, ldo, 8, 4);
-        hipLaunchKernelGGL(split16_kernel, grid, dim3(kEltThreads), 0, s, rows, cols, X, ldx, head, resid, ldo, vec,
-                           part);
+        hipLaunchKernelGGL(split16_kernel<BF>, grid, dim3(kEltThreads), 0, s, rows, cols, X, ldx, head, resid, ldo,
+                           vec, part);
         MFG_LAUNCH_CHECK();
     }
     if (norms != nullptr) {
@@ -236,6 +249,16 @@ int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, ui
         MFG_LAUNCH_CHECK();
     }
     return MFG_OK;
+}
+
+int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head, uint16_t* resid,
+                     int64_t ldo, double* norms, hipStream_t s) {
+    return launch_split<false>(rows, cols, X, ldx, head, resid, ldo, norms, s);
+}
+
+int launch_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head, uint16_t* resid,
+                      int64_t ldo, double* norms, hipStream_t s) {
+    return launch_split<true>(rows, cols, X, ldx, head, resid, ldo, norms, s);
 }
 
 // ---------------------------------------------------- conversion job lists
@@ -271,19 +294,24 @@ __global__ __launch_bounds__(kEltThreads) void convert_jobs_kernel(const ConvJob
         uint16_t h[4], q[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            h[i] = j.kind == 1 ? f32_to_bf16_bits(v[i]) : f32_to_f16_bits(v[i]);
-            q[i] = f32_to_f16_bits((v[i] - f16_bits_to_f32(h[i])) * 2048.0f);  // as split16_kernel
+            if (j.kind == 1 || j.kind == 3) {  // as split16_kernel<true>
+                h[i] = f32_to_bf16_bits(v[i]);
+                q[i] = f32_to_bf16_bits(v[i] - bf16_bits_to_f32(h[i]));
+            } else {  // as split16_kernel<false>
+                h[i] = f32_to_f16_bits(v[i]);
+                q[i] = f32_to_f16_bits((v[i] - f16_bits_to_f32(h[i])) * 2048.0f);
+            }
         }
         if (cnt == 4) {  // dst rows are 16-byte aligned (ldo a multiple of 8): 8-byte pieces
             *reinterpret_cast<u32x2*>(ho + c0) =
                 u32x2{(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
-            if (j.kind == 2)
+            if (j.kind >= 2)
                 *reinterpret_cast<u32x2*>(qo + c0) =
                     u32x2{(uint32_t)q[0] | ((uint32_t)q[1] << 16), (uint32_t)q[2] | ((uint32_t)q[3] << 16)};
         } else {
             for (int i = 0; i < cnt; ++i) {
                 ho[c0 + i] = h[i];
-                if (j.kind == 2) qo[c0 + i] = q[i];
+                if (j.kind >= 2) qo[c0 + i] = q[i];
             }
         }
     }

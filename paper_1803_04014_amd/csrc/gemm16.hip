@@ -285,6 +285,7 @@ int launch_gemm16(int kind, int cfg, const Gemm16Args& a, int64_t batch, bool ve
         case K_REFINE_A: return launch_kind<K_REFINE_A>(cfg, a, batch, vec_ok, s);
         case K_SPLIT3: return launch_kind<K_SPLIT3>(cfg, a, batch, vec_ok, s);
         case K_SPLIT4: return launch_kind<K_SPLIT4>(cfg, a, batch, vec_ok, s);
+        case K_BF16_SPLIT3: return launch_kind<K_BF16_SPLIT3>(cfg, a, batch, vec_ok, s);
         default: return MFG_ERR_INVALID_ARG;
     }
 }

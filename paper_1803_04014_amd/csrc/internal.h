@@ -72,7 +72,8 @@ struct GemmF8Args {
 };
 
 // Kernel families.  `kind` selects the operand format and products:
-enum Kind16 { K_F16 = 0, K_BF16 = 1, K_REFINE_A = 2, K_SPLIT3 = 3, K_SPLIT4 = 4 };
+// K_BF16_SPLIT3: Eq. 2 without R_A R_B on BF16 head and unscaled BF16 residual planes.
+enum Kind16 { K_F16 = 0, K_BF16 = 1, K_REFINE_A = 2, K_SPLIT3 = 3, K_SPLIT4 = 4, K_BF16_SPLIT3 = 5 };
 
 // Tile configurations (index 0 is always the simple one-wave-per-32x32 kernel).
 int num_configs16(int kind);
@@ -100,6 +101,8 @@ int launch_round_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, u
                       int64_t ldo, hipStream_t s);
 int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head,
                      uint16_t* resid, int64_t ldo, double* norms, hipStream_t s);
+int launch_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head,
+                      uint16_t* resid, int64_t ldo, double* norms, hipStream_t s);
 int launch_quantize_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint8_t* codes,
                         int64_t ldo, float* scales, hipStream_t s);
 // The same codes written transposed (code of X[r][c] at codes_t[c * ldt + r]),
@@ -108,7 +111,8 @@ int launch_quantize_fp8_t(int64_t rows, int64_t cols, const float* X, int64_t ld
                           float* scales, hipStream_t s);
 // Conversion job lists (grouped plans over FP32 operands): job = one matrix,
 // rows x cols FP32 at src (ld lds) into 16-bit dst (ld ldo); kind 0 rne16,
-// 1 rnebf16, 2 split (head at dst, scaled residual at dst + plane).  Task =
+// 1 rnebf16, 2 FP16 split (head at dst, scaled residual at dst + plane),
+// 3 BF16 split (unscaled residual).  Task =
 // rpt rows of one job (one workgroup): about kJobChunks four-element pieces.
 constexpr int kJobChunks = 512;
 struct ConvJob {

@@ -40,7 +40,7 @@ struct PipeCfg {
     static constexpr int LOADS = NPA * A_INSTR + NPB * B_INSTR;  // per wave per stage
     static constexpr int B_ROWS_PER_INSTR = 512 / BN, B_CPR = BN / 8;
     static constexpr int READS = 2 * (FM * NPA + 2 * FN * NPB);  // LDS reads per wave per step
-    static constexpr int PRODUCTS = KIND == K_REFINE_A ? 2 : KIND == K_SPLIT3 ? 3 : KIND == K_SPLIT4 ? 4 : 1;
+    static constexpr int PRODUCTS = KIND == K_REFINE_A ? 2 : (KIND == K_SPLIT3 || KIND == K_BF16_SPLIT3) ? 3 : KIND == K_SPLIT4 ? 4 : 1;
     static constexpr int MFMAS = 2 * FM * FN * PRODUCTS;  // per wave per step
     static_assert(A_PLANE % (512 * NW) == 0 && B_PLANE % (512 * NW) == 0, "tile must split into 1 KB loads");
     static_assert(BN == 128 || BN == 256, "B rows of 256 or 512 bytes");
@@ -324,7 +324,7 @@ struct Pipe64Cfg {
     static constexpr int LOADS = NPA * A_INSTR + NPB * B_INSTR;  // per wave per stage
     static constexpr int B_ROWS_PER_INSTR = 512 / BN, B_CPR = BN / 8;
     static constexpr int READS = KK * (FM * NPA + 2 * FN * NPB);  // LDS reads per wave per fragment step
-    static constexpr int PRODUCTS = KIND == K_REFINE_A ? 2 : KIND == K_SPLIT3 ? 3 : KIND == K_SPLIT4 ? 4 : 1;
+    static constexpr int PRODUCTS = KIND == K_REFINE_A ? 2 : (KIND == K_SPLIT3 || KIND == K_BF16_SPLIT3) ? 3 : KIND == K_SPLIT4 ? 4 : 1;
     static constexpr int MFMAS = KK * FM * FN * PRODUCTS;  // per wave per fragment step
     static_assert(A_PLANE % (512 * NW) == 0 && B_PLANE % (512 * NW) == 0, "tile must split into 1 KB loads");
     static_assert(BN == 128 || BN == 256, "B rows of 256 or 512 bytes");

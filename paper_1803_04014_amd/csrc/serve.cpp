@@ -92,6 +92,7 @@ int grouped_kind(int mode) {
         case MFG_F16_REFINE_A: return K_REFINE_A;
         case MFG_F16_SPLIT3: return K_SPLIT3;
         case MFG_F16_SPLIT4: return K_SPLIT4;
+        case MFG_BF16_SPLIT3: return K_BF16_SPLIT3;
         default: return -1;
     }
 }

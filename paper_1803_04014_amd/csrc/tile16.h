@@ -12,7 +12,7 @@ namespace mfg {
 
 template <int KIND>
 struct KT {
-    static constexpr bool BF = KIND == K_BF16;
+    static constexpr bool BF = KIND == K_BF16 || KIND == K_BF16_SPLIT3;
     static constexpr int NPA = (KIND >= K_REFINE_A) ? 2 : 1;
     static constexpr int NPB = (KIND >= K_SPLIT3) ? 2 : 1;
     static constexpr bool LO = KIND >= K_REFINE_A;
@@ -27,7 +27,7 @@ __device__ __forceinline__ void mma_step(const u32x4 (&a)[2], const u32x4 (&b)[2
     hi = mma_32x32x16<BF>(a[0], b[0], hi);
     if constexpr (KIND == K_REFINE_A) {
         lo = mma_32x32x16<BF>(a[1], b[0], lo);
-    } else if constexpr (KIND == K_SPLIT3 || KIND == K_SPLIT4) {
+    } else if constexpr (KIND == K_SPLIT3 || KIND == K_SPLIT4 || KIND == K_BF16_SPLIT3) {
         lo = mma_32x32x16<BF>(a[0], b[1], lo);
         lo = mma_32x32x16<BF>(a[1], b[0], lo);
         if constexpr (KIND == K_SPLIT4) rr = mma_32x32x16<BF>(a[1], b[1], rr);
@@ -41,6 +41,7 @@ __device__ __forceinline__ float combine(float hi, float lo, float rr) {
     } else {
         float l = lo;
         if constexpr (KT<KIND>::RR) l = __builtin_fmaf(rr, kResidInv, l);
+        if constexpr (KIND == K_BF16_SPLIT3) return hi + l;  // unscaled residual planes
         return __builtin_fmaf(l, kResidInv, hi);
     }
 }

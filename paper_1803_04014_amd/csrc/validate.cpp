@@ -69,7 +69,8 @@ extern "C" int64_t mfg_convert_bytes(int64_t rows, int64_t cols, int64_t ldo, in
         case MFG_BF16: return rows * ldo * 2;
         case MFG_F16_REFINE_A:
         case MFG_F16_SPLIT3:
-        case MFG_F16_SPLIT4: return 2 * rows * ldo * 2;
+        case MFG_F16_SPLIT4:
+        case MFG_BF16_SPLIT3: return 2 * rows * ldo * 2;
         case MFG_FP8_E4M3: {
             const int64_t tr = (rows + MFG_FP8_TILE - 1) / MFG_FP8_TILE;
             const int64_t tc = (cols + MFG_FP8_TILE - 1) / MFG_FP8_TILE;

@@ -12,7 +12,7 @@ import paper_1803_04014_amd as mfg
 DEV = "cuda:0"
 
 # oracle mode names <-> library modes
-MODES = ["f32", "f16", "bf16", "refine_a", "split3", "split4", "fp8"]
+MODES = ["f32", "f16", "bf16", "refine_a", "split3", "split4", "fp8", "bf16_split3"]
 
 
 def need_gpu():

@@ -87,7 +87,7 @@ P = 0x7F0000000000  # a non-null address: validation never dereferences
     ((8, 8, 8, P, 8, P, 8, P, 7, 1), -1),                   # ldc < N
     ((8, 8, 8, None, 8, P, 8, P, 8, 1), -1),
     ((8, 8, 8, P, 8, P, 8, None, 8, 1), -1),
-    ((8, 8, 8, P, 8, P, 8, P, 8, 7), -1),                   # no such mode
+    ((8, 8, 8, P, 8, P, 8, P, 8, 8), -1),                   # no such mode
     ((8, 8, 8, P, 8, P, 8, P, 8, 0x201), -1),               # unknown flag
     ((8, 8, 8, P, 8, P, 8, P, 8, 0x101), 0),
 ])

@@ -57,7 +57,8 @@ def test_batched_equals_solo_and_oracle(mode, shape, count):
 
 
 @pytest.mark.parametrize("mode,shape", [("split3", (16, 16, 40)), ("refine_a", (16, 16, 40)), ("split4", (16, 16, 40)),
-                                        ("split3", (48, 64, 40)), ("split4", (64, 40, 72))])
+                                        ("split3", (48, 64, 40)), ("split4", (64, 40, 72)),
+                                        ("bf16_split3", (16, 16, 40)), ("bf16_split3", (48, 64, 40))])
 def test_batched_refined_equals_solo(mode, shape):
     count, (M, N, K) = 96, shape
     A, B, C0 = workloads.normal(22, [(count, M, K), (count, K, N), (count, M, N)])
@@ -216,7 +217,7 @@ def test_grouped_refined_degenerate_shapes(mode):
     plan.close()
 
 
-@pytest.mark.parametrize("mode", ["f16", "bf16", "refine_a", "split3", "split4"])
+@pytest.mark.parametrize("mode", ["f16", "bf16", "refine_a", "split3", "split4", "bf16_split3"])
 def test_grouped_fp32_input_equals_solo(mode):
     """MFG_IN_FP32 plans: one conversion launch over every problem's FP32 A and
     B into plan-owned storage, then the grouped kernel.  Every problem bitwise
@@ -237,7 +238,7 @@ def test_grouped_fp32_input_equals_solo(mode):
         c0.append(C0)
     plan = mfg.GroupedPlan(probs, mode, fp32_in=True)
     npa = 1 if mode in ("f16", "bf16") else 2
-    npb = 2 if mode in ("split3", "split4") else 1
+    npb = 2 if mode in ("split3", "split4", "bf16_split3") else 1
     exp = sum(4 * (m * k + k * n) + 2 * (npa * m * k + npb * k * n) + 2 * (npa * m * k + npb * k * n) + 4 * m * n
               for (m, n, k) in dims)
     assert plan.info()["bytes"] == pytest.approx(exp)

@@ -156,7 +156,7 @@ def test_invalid_arguments_enqueue_nothing():
 
 
 # -------------------------------------------------- preconverted operands
-@pytest.mark.parametrize("mode", ["f16", "bf16", "refine_a", "split3", "split4", "fp8"])
+@pytest.mark.parametrize("mode", ["f16", "bf16", "refine_a", "split3", "split4", "fp8", "bf16_split3"])
 def test_preconverted_equals_fp32_input(mode):
     M, N, K = 260, 200, 300
     A, B = workloads.normal(10, [(M, K), (K, N)])

@@ -28,7 +28,7 @@ from gpu_util import DEV, dev, host, need_gpu
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-MODES = ["f16", "refine_a", "split3", "split4", "f32"]
+MODES = ["f16", "refine_a", "split3", "split4", "f32", "bf16", "bf16_split3"]
 NS = (1024, 2048, 4096, 8192, 16384)  # 8192: the size the paper quotes its refinement gains at
 
 
@@ -104,6 +104,18 @@ def test_split_error_within_2x_of_fp32_gemm(study, dist):
         e, _ = study[(dist, n)]
         assert e["split3"] <= 2.0 * e["f32"], (dist, n, e["split3"], e["f32"])
         assert e["split4"] <= 2.0 * e["f32"], (dist, n, e["split4"], e["f32"])
+
+
+@pytest.mark.parametrize("dist", ["uniform", "normal", "pow2"])
+def test_bf16_split_sits_between_fp16_and_the_fp16_split(study, dist):
+    """BF16 head + unscaled residual: 16 significant bits per operand (oracle pin
+    2^-16), so far below plain BF16 and FP16, above the 22-bit FP16 split, and
+    near the FP32 GEMM."""
+    for n in NS:
+        e, _ = study[(dist, n)]
+        assert e["bf16"] / e["bf16_split3"] >= 100.0, (dist, n)
+        assert e["bf16_split3"] <= e["f16"] / 20.0, (dist, n)
+        assert e["split3"] < e["bf16_split3"] <= 10.0 * e["f32"], (dist, n)
 
 
 def test_unrefined_error_grows_with_n(study):
