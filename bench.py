@@ -408,7 +408,7 @@ def main() -> int:
                                                 "note": "vendor library via torch.matmul, FP16 out, beta = 0"}
         ms = timed(lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode="f32"), 3, warm=1)
         ex["f32_n8192"] = {"tflops": round(flops / ms / 1e9, 1), "pct_peak": round(flops / ms / 1e9 / 1.573, 1)}
-        for mode in ("refine_a", "split3", "split4", "fp8"):
+        for mode in ("refine_a", "split3", "split4", "fp8", "bf16_split3"):
             ms = timed(lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode=mode), 3, warm=1)
             ex[f"{mode}_n8192_fp32_in"] = {"useful_tflops": round(flops / ms / 1e9, 1), "ms": round(ms, 3)}
         # N sweep (FP16, preconverted)
