@@ -99,6 +99,8 @@ def test_convert_bytes_and_fp8_scale_offset():
     L = mfg.lib()
     assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_F16) == 10 * 8 * 2
     assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_F16_SPLIT3) == 2 * 10 * 8 * 2
+    assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_BF16_SPLIT3) == 2 * 10 * 8 * 2
+    assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_NUM_MODES) == -1
     assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_F32) == 10 * 8 * 4
     off = L.mfg_fp8_scale_offset(300, 272)
     assert off >= 300 * 272 and off % 16 == 0
