@@ -497,17 +497,36 @@ int launch_transpose_b8(int64_t rows, int64_t cols, const uint8_t* src, int64_t 
 }
 
 // ------------------------------------------------------------- error norms
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// A thread folds four consecutive columns per step (one 16-byte load of C and
+// two of R when rows are aligned: vec), in column order, rows in turn.
 __global__ __launch_bounds__(kEltThreads) void err_kernel(int64_t rows, int64_t cols, const float* C, int64_t ldc,
-                                                          const double* R, int64_t ldr, Red4* part) {
+                                                          const double* R, int64_t ldr, int vec, Red4* part) {
     Red4 acc{0.0, 0.0, 0.0, 0.0};
+    auto fold = [&](float cv, double ref) {
+        const double e = (double)cv - ref;
+        acc.s0 += e * e;
+        acc.m0 = fmax(acc.m0, fabs(e));
+        acc.s1 += ref * ref;
+        acc.m1 = fmax(acc.m1, fabs(ref));
+    };
     for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-        for (int64_t c = threadIdx.x; c < cols; c += kEltThreads) {
-            const double ref = R[r * ldr + c];
-            const double e = (double)C[r * ldc + c] - ref;
-            acc.s0 += e * e;
-            acc.m0 = fmax(acc.m0, fabs(e));
-            acc.s1 += ref * ref;
-            acc.m1 = fmax(acc.m1, fabs(ref));
+        const float* cr = C + r * ldc;
+        const double* rr = R + r * ldr;
+        for (int64_t c0 = (int64_t)threadIdx.x * 4; c0 < cols; c0 += kEltThreads * 4) {
+            if (vec && c0 + 4 <= cols) {
+                const f32x4 cv = *reinterpret_cast<const f32x4*>(cr + c0);
+                const f64x2 r0 = *reinterpret_cast<const f64x2*>(rr + c0);
+                const f64x2 r1 = *reinterpret_cast<const f64x2*>(rr + c0 + 2);
+                fold(cv[0], r0[0]);
+                fold(cv[1], r0[1]);
+                fold(cv[2], r1[0]);
+                fold(cv[3], r1[1]);
+            } else {
+                for (int j = 0; j < 4; ++j)
+                    if (c0 + j < cols) fold(cr[c0 + j], rr[c0 + j]);
+            }
         }
     }
     acc = block_reduce(acc);
@@ -521,7 +540,8 @@ int launch_error_norms(int64_t M, int64_t N, const float* C, int64_t ldc, const 
     Red4* part = static_cast<Red4*>(scratch(s, (size_t)(G + 1) * sizeof(Red4), &st));
     if (part == nullptr) return st;
     if (G > 0) {
-        hipLaunchKernelGGL(err_kernel, dim3((unsigned)G), dim3(kEltThreads), 0, s, M, N, C, ldc, R, ldr, part);
+        const int vec = aligned(C, ldc, 16, 4) && aligned(R, ldr, 16, 2);
+        hipLaunchKernelGGL(err_kernel, dim3((unsigned)G), dim3(kEltThreads), 0, s, M, N, C, ldc, R, ldr, vec, part);
         MFG_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kEltThreads), 0, s, part, G, out4, 1);
