@@ -410,7 +410,9 @@ def main() -> int:
         ex["f32_n8192"] = {"tflops": round(flops / ms / 1e9, 1), "pct_peak": round(flops / ms / 1e9 / 1.573, 1)}
         for mode in ("refine_a", "split3", "split4", "fp8", "bf16_split3"):
             ms = timed(lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode=mode), 3, warm=1)
-            ex[f"{mode}_n8192_fp32_in"] = {"useful_tflops": round(flops / ms / 1e9, 1), "ms": round(ms, 3)}
+            products = {"refine_a": 2, "split3": 3, "split4": 4, "bf16_split3": 3}.get(mode, 1)
+            ex[f"{mode}_n8192_fp32_in"] = {"useful_tflops": round(flops / ms / 1e9, 1),
+                                           "executed_tflops": round(products * flops / ms / 1e9, 1), "ms": round(ms, 3)}
         # N sweep (FP16, preconverted)
         sweep = {}
         for n in (1024, 2048, 4096):
@@ -419,6 +421,14 @@ def main() -> int:
             c = dC0[:n, :n].contiguous()
             ms = timed(lambda: mfg.gemm(a, b, c, 1.0, 1.0, mode="f16", preconverted=True), 20)
             sweep[str(n)] = round(2.0 * n ** 3 / ms / 1e9, 1)
+        del a, b, c
+        n = 16384  # the largest square size of the sweep, from fresh operands
+        a = torch.empty((n, n), dtype=torch.float16, device=dev).uniform_(-1, 1)
+        b = torch.empty((n, n), dtype=torch.float16, device=dev).uniform_(-1, 1)
+        c = torch.empty((n, n), dtype=torch.float32, device=dev).uniform_(-1, 1)
+        ms = timed(lambda: mfg.gemm(a, b, c, 1.0, 1.0, mode="f16", preconverted=True), 4, warm=1)
+        sweep[str(n)] = round(2.0 * n ** 3 / ms / 1e9, 1)
+        del a, b, c
         ex["f16_sweep_tflops"] = sweep
         # the HBM-bound steps at N x N: operand rounding, split with FP64 norms,
         # FP8 tile quantisation, FP64 error norms (algorithmic bytes per element:
@@ -441,15 +451,31 @@ def main() -> int:
         ex["hbm_steps_n8192"] = hbm
         del h16, r16, q8, sc, cref
         # batched 65536 x 16^3 and 16384 x 64^3 (FP16 in, FP32 out, alpha=1, beta=0)
-        for cnt, s in ((65536, 16), (16384, 64)):
-            a16, b16 = (torch.empty((cnt, s, s), dtype=torch.float16, device=dev).uniform_(-1, 1) for _ in range(2))
-            c = torch.empty((cnt, s, s), dtype=torch.float32, device=dev)
-            ms = timed(lambda: mfg.gemm_batched(a16, b16, c, 1.0, 0.0, mode="f16"), 20, warm=100)
+        # operand sets rotate so that one pass over them (> 256 MB) outgrows the
+        # L2s and the 256 MB MALL: every launch reads its operands from HBM
+        def batched_leg(cnt, s, reps=20, warm=100):
             byts = cnt * (2 * 2 * s * s + 4 * s * s)
-            ex[f"batched_{cnt}x{s}^3"] = {"gemm_per_s": round(cnt / ms * 1e3, 1), "tflops": round(2 * cnt * s ** 3 / ms / 1e9, 2),
-                                          "hbm_gbs": round(byts / ms / 1e6, 1),
-                                          "pct_hbm": round(100 * byts / ms / 1e6 / HBM_GBS, 1), "us": round(ms * 1e3, 2)}
-            del a16, b16, c
+            nsets = max(1, -(-(320 << 20) // byts))
+            sets = []
+            for _ in range(nsets):
+                a16, b16 = (torch.empty((cnt, s, s), dtype=torch.float16, device=dev).uniform_(-1, 1) for _ in range(2))
+                sets.append((a16, b16, torch.empty((cnt, s, s), dtype=torch.float32, device=dev)))
+            it = [0]
+
+            def step():
+                a16, b16, c = sets[it[0] % nsets]
+                it[0] += 1
+                mfg.gemm_batched(a16, b16, c, 1.0, 0.0, mode="f16")
+            ms = timed(step, reps * nsets, warm=warm)
+            del sets
+            return {"gemm_per_s": round(cnt / ms * 1e3, 1), "tflops": round(2 * cnt * s ** 3 / ms / 1e9, 2),
+                    "hbm_gbs": round(byts / ms / 1e6, 1), "pct_hbm": round(100 * byts / ms / 1e6 / HBM_GBS, 1),
+                    "us": round(ms * 1e3, 2), "operand_sets": nsets}
+        for cnt, s in ((65536, 16), (16384, 64)):
+            ex[f"batched_{cnt}x{s}^3"] = batched_leg(cnt, s)
+        # 16^3 batches from 2^10 to 2^18 problems (GEMM/s against the batch size)
+        ex["batched_16^3_sweep_gemm_per_s"] = {str(cnt): batched_leg(cnt, 16, reps=10, warm=20)["gemm_per_s"]
+                                               for cnt in (1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18)}
         # autotuner: default configuration against the tuned one on a few shapes
         tune = {}
         mfg.lib().mfg_tune_clear()
