@@ -178,6 +178,74 @@ def copy_probe(nbytes: int) -> int:
     return 0
 
 
+def kernel_only(mode: str, n: int, steps: int, warmup: int) -> int:
+    """`steps` launches of one mode's GEMM at n^3 on operands already in the
+    mode's preconverted form (C = A B + C, alpha = beta = 1): the run the MFMA
+    counter passes profile.  Prints the kernel's average time and rate."""
+    import torch
+
+    import paper_1803_04014_amd as mfg
+
+    dev = "cuda:0"
+    g = torch.Generator(device=dev)
+    g.manual_seed(2)
+    A32 = torch.rand((n, n), device=dev, generator=g) * 2 - 1
+    B32 = torch.rand((n, n), device=dev, generator=g) * 2 - 1
+    C = torch.rand((n, n), device=dev, generator=g) * 2 - 1
+    if mode == "f32":
+        pa, pb = A32, B32
+    else:
+        ld = n
+        nb = mfg.convert_bytes(n, n, ld, mode)
+        bufa = torch.empty(nb, dtype=torch.uint8, device=dev)
+        bufb = torch.empty(nb, dtype=torch.uint8, device=dev)
+        mfg.convert(A32, bufa, ld, mode)
+        mfg.convert(B32, bufb, ld, mode)
+        if mode == "fp8":
+            pa, pb = bufa[:n * ld].view(n, ld), bufb[:n * ld].view(n, ld)
+        else:
+            pa = bufa.view(torch.float16).view(-1, ld)
+            pb = bufb.view(torch.float16).view(-1, ld)
+    run = lambda: mfg.gemm(pa, pb, C, 1.0, 1.0, mode=mode, preconverted=True, M=n, K=n)
+    ms = timed(run, steps, warm=warmup)
+    products = {"refine_a": 2, "split3": 3, "split4": 4, "bf16_split3": 3}.get(mode, 1)
+    fl = 2.0 * n ** 3
+    print(json.dumps({"kernel_only": mode, "n": n, "ms": round(ms, 4), "useful_tflops": round(fl / ms / 1e9, 1),
+                      "executed_tflops": round(products * fl / ms / 1e9, 1)}), flush=True)
+    return 0
+
+
+def mfma_ceiling(dev, iters: int = 2048, workgroups_per_cu: int = 2) -> dict:
+    """Register-only MFMA loops (mfg_probe_mfma) on random and on all-zero FP16
+    operands, both MFMA shapes: the matrix-core rate the chip sustains with no
+    memory traffic, i.e. the ceiling the GEMM kernels work against."""
+    import ctypes
+
+    import torch
+
+    import paper_1803_04014_amd as mfg
+
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    wg = ncu * workgroups_per_cu
+    rnd = torch.empty(8192, dtype=torch.float16, device=dev).uniform_(-1, 1)
+    zero = torch.zeros(8192, dtype=torch.float16, device=dev)
+    out = torch.empty(wg * 256, dtype=torch.float32, device=dev)
+    res = {}
+    for shape, sname in ((0, "32x32x16"), (1, "16x16x32")):
+        for ops, oname in ((rnd, "random"), (zero, "zero")):
+            fl = ctypes.c_double()
+
+            def launch():
+                mfg.capi.check("mfg_probe_mfma", mfg.lib().mfg_probe_mfma(
+                    shape, ctypes.c_void_p(ops.data_ptr()), wg, iters, ctypes.c_void_p(out.data_ptr()),
+                    ctypes.byref(fl), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+            ms = timed(launch, 5, warm=2)
+            res[f"{sname}_{oname}"] = {"tflops": round(fl.value / ms / 1e9, 1), "ms": round(ms, 3)}
+    res["workgroups"] = wg
+    res["waves_per_simd"] = workgroups_per_cu
+    return res
+
+
 def served_errors(trace, views, per_mode: int = 3, max_flops: float = 2 * 512.0 ** 3):
     """Part of the CPU oracle leg: max relative error vs FP64 of a few served
     requests per mode (the oracle computes their exact products)."""
@@ -260,6 +328,8 @@ def main() -> int:
                     help="only turn four rocprofv3 --pmc output folders into the traffic record")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--grouped-only", action="store_true", help="only the grouped-plan legs (one JSON line)")
+    ap.add_argument("--kernel-only", metavar="MODE", help="only time MODE's GEMM at N^3 on preconverted operands")
+    ap.add_argument("--mfma-ceiling", action="store_true", help="only the register-only MFMA ceiling probe")
     args = ap.parse_args()
     if args.copy_probe:
         return copy_probe(args.copy_probe)
@@ -269,6 +339,13 @@ def main() -> int:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build is single-GPU)",
               file=sys.stderr)
         return 2
+    if args.kernel_only:
+        return kernel_only(args.kernel_only, args.n, args.steps, args.warmup)
+    if args.mfma_ceiling:
+        import torch
+
+        print(json.dumps({"mfma_ceiling": mfma_ceiling(torch.device("cuda", 0))}), flush=True)
+        return 0
     if args.grouped_only:
         import torch
 

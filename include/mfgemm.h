@@ -147,9 +147,13 @@ int mfg_config_name(int mode, int config, char* buf, int n);
  * A_b = A + b*strideA, B_b = B + b*strideB, C_b = C + b*strideC (strides in
  * elements of the stored type), all problems M x N x K (paper Sec. IV.B:
  * many small GEMMs in one launch).  Modes F16, BF16 and F32 take their
- * operands directly (F16/BF16 as 16-bit data; the flag is implied); the
- * refinement modes take FP32 operands and split them into the workspace.
- * FP8 is not served batched (MFG_ERR_UNSUPPORTED).
+ * operands directly (F16/BF16 as 16-bit data; the flag MFG_IN_PRECONVERTED
+ * is implied and may be given); the refinement modes take FP32 operands and
+ * split them into the workspace, or with MFG_IN_PRECONVERTED each entry in
+ * the mode's preconverted storage form (head plane at A + b*strideA, its
+ * residual plane at A + b*strideA + M*lda; likewise B for the two-sided
+ * splits).  Any other flag is MFG_ERR_INVALID_ARG.  FP8 is not served
+ * batched (MFG_ERR_UNSUPPORTED).
  */
 int mfg_gemm_batched(int64_t count, int64_t M, int64_t N, int64_t K,
                      const void* A, int64_t lda, int64_t strideA,
@@ -349,6 +353,29 @@ const char* mfg_version(void);
  * these arguments before enqueueing anything. */
 int mfg_validate_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
                       const void* B, int64_t ldb, const float* C, int64_t ldc, int mode);
+/* Matrix-core ceiling probe (measurement aid for the roofline of the GEMM
+ * kernels, not part of the GEMM path): `workgroups` workgroups of four
+ * wavefronts each issue iters x 8 independent MFMAs from registers, with no
+ * memory traffic.  shape 0: v_mfma_f32_32x32x16_f16, 1: 16x16x32_f16.
+ * operands (device): 4096 dwords of 16-bit values that every wavefront loads
+ * once (random bits or zeros: the sustained clock depends on them).  out
+ * (device): workgroups * 256 floats (the accumulators' sums).  flops (host,
+ * may be NULL) receives the matrix flops of the launch.  Time it with
+ * events on `stream`. */
+int mfg_probe_mfma(int shape, const void* operands, int64_t workgroups, int64_t iters, float* out,
+                   double* flops, void* stream);
+/* Fault injection, for tests of failure handling: after this call the
+ * launch_n-th GEMM kernel launch (mfg_gemm, batched, grouped; conversions
+ * are not counted) fails with MFG_ERR_HIP (hipErrorLaunchFailure) without
+ * launching, and the alloc_n-th device allocation (a workspace growing, a
+ * served request's operand storage) fails with MFG_ERR_NO_MEMORY, each once;
+ * 0 disarms.  Process-wide.  The environment variable
+ * MFG_FAULT=launch:<n>,alloc:<n> arms the same at the library's first call
+ * and at every mfg_server_create.  The dry-run server (device = -1) meets
+ * the same hooks: one allocation per request with a nonzero footprint, one
+ * launch per request run alone or per grouped launch.  Negative counts are
+ * MFG_ERR_INVALID_ARG. */
+int mfg_fault_inject(int64_t launch_n, int64_t alloc_n);
 
 #ifdef __cplusplus
 }

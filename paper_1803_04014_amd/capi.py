@@ -109,6 +109,8 @@ SIGNATURES = {
     "mfg_last_hip_error": (i32, []),
     "mfg_version": (ctypes.c_char_p, []),
     "mfg_validate_gemm": (i32, [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32]),
+    "mfg_fault_inject": (i32, [i64, i64]),
+    "mfg_probe_mfma": (i32, [i32, vp, i64, i64, vp, P(f64), vp]),
 }
 
 _lib = None

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "runtime.h"
 #include "tile16.h"
 
 namespace mfg {
@@ -146,6 +147,7 @@ __global__ __launch_bounds__(256) void gemm16_batched_lds(Gemm16Args p, int64_t 
 }
 
 int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_ok, int num_cu, hipStream_t s) {
+    if (fault_hit(kFaultLaunch)) return hip_fail(hipErrorLaunchFailure);  // injected (tests)
     if (a.M > 32 || a.N > 32) return MFG_ERR_INTERNAL;
     const int64_t want = cdiv(count, 4);
     const int64_t cap = (int64_t)num_cu * 16;  // 16 workgroups (64 waves) per CU
@@ -615,6 +617,7 @@ int grouped_launch(int kind, const GroupedWork* work, const int64_t* planes, con
                    float beta, hipStream_t s) {
     if (kind < K_F16 || kind > K_BF16_SPLIT3) return MFG_ERR_UNSUPPORTED;
     if (kind >= K_REFINE_A && !planes) return MFG_ERR_INTERNAL;  // the refined kinds read residual planes
+    if (fault_hit(kFaultLaunch)) return hip_fail(hipErrorLaunchFailure);  // injected (tests)
     for (int list = 0; list < 2; ++list) {
         if (split.off[list][kXcds] == split.off[list][0]) continue;  // empty list
         const dim3 grid((unsigned)grouped_grid(split, list, kind));

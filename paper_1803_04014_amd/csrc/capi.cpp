@@ -45,10 +45,13 @@ static int convert16(int m, int64_t rows, int64_t cols, const float* X, int64_t 
     return launch_round_f16(rows, cols, X, ldx, p0, ldo, s);
 }
 
-static int choose16(int m, int config, int64_t M, int64_t N, int64_t K, bool vec) {
+// The tuned table is keyed by size buckets, so its entry may name a
+// configuration that does not serve this particular shape (e.g. K % 64 != 0
+// in a bucket tuned on K % 64 == 0): then the default choice is used.
+static int choose16(int m, int config, int64_t M, int64_t N, int64_t K, int64_t ldc, bool vec) {
     if (config >= 0) return config;
     const int t = tuned_lookup(m, M, N, K);
-    if (t >= 0 && t < num_configs16(kind_of(m)) && (vec || t == 0)) return t;
+    if (t >= 0 && config16_ok(kind_of(m), t, M, N, K, ldc, vec)) return t;
     return pick_config16(kind_of(m), M, N, K, vec);
 }
 
@@ -70,7 +73,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         int cfg = config;
         if (cfg < 0) {
             const int t = tuned_lookup(m, M, N, K);
-            cfg = (t >= 0 && t < num_configs_f32() && (vec || t == 0)) ? t : pick_config_f32(M, N, K, vec);
+            cfg = (t >= 0 && config_f32_ok(t, ldc, vec)) ? t : pick_config_f32(M, N, K, vec);
         }
         return launch_gemm_f32(cfg, a, 1, vec, s);
     }
@@ -81,7 +84,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         auto choose = [&](bool vec) {
             if (config >= 0) return config;
             const int t = tuned_lookup(m, M, N, K);
-            if (t >= 0 && t < num_configs_f8() && (vec || t == 0)) return t;
+            if (t >= 0 && config_f8_ok(t, M, N, K, ldc, vec)) return t;
             return pick_config_f8(M, N, K, vec);
         };
         const int64_t ldt = up(K, 16);                      // ld of the transposed B codes
@@ -144,7 +147,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         a.B[0] = pb, a.B[1] = npb(m) == 2 ? pb + K * ldb : nullptr;
         a.lda = lda, a.ldb = ldb;
         const bool vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && buffer_ldc_ok(ldc);
-        return launch_gemm16(kind, choose16(m, config, M, N, K, vec), a, 1, vec, s);
+        return launch_gemm16(kind, choose16(m, config, M, N, K, ldc, vec), a, 1, vec, s);
     }
     const int64_t ldk = up(K, 8), ldn = up(N, 8);
     const int64_t pa_elems = M * ldk, pb_elems = K * ldn;
@@ -160,7 +163,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     if ((st = convert16(m, K, N, static_cast<const float*>(B), ldb, b0, b1, ldn, npb(m) == 2, s)) != MFG_OK) return st;
     a.A[0] = a0, a.A[1] = a1, a.B[0] = b0, a.B[1] = b1, a.lda = ldk, a.ldb = ldn;
     const bool vec = buffer_ldc_ok(ldc);  // workspace planes: aligned, ld a multiple of 8
-    return launch_gemm16(kind, choose16(m, config, M, N, K, vec), a, 1, vec, s);
+    return launch_gemm16(kind, choose16(m, config, M, N, K, ldc, vec), a, 1, vec, s);
 }
 
 }  // namespace mfg
@@ -219,7 +222,7 @@ extern "C" int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode) {
         const int t = tuned_lookup(m, M, N, K);
         return (t >= 0 && t < num_configs_f8()) ? t : pick_config_f8(M, N, K, true);
     }
-    return choose16(m, -1, M, N, K, true);
+    return choose16(m, -1, M, N, K, N, true);
 }
 
 // -------------------------------------------------------------------- batched
@@ -227,8 +230,13 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
                         int64_t strideA, const void* B, int64_t ldb, int64_t strideB, float* C, int64_t ldc,
                         int64_t strideC, float alpha, float beta, int mode, hipStream_t s) {
     const int m = mode & MFG_MODE_MASK;
+    // Only MFG_IN_PRECONVERTED may accompany the mode (validate_gemm checks
+    // the flags).  F16 / BF16 / F32 take their operands as stored, so the
+    // flag is implied there; the refined modes read each entry in its
+    // preconverted form with it, and FP32 operands without it.
+    const bool pre = (mode & MFG_IN_PRECONVERTED) != 0;
     if (count < 0 || strideA < 0 || strideB < 0 || strideC < 0) return MFG_ERR_INVALID_ARG;
-    int st = validate_gemm(M, N, K, A, lda, B, ldb, C, ldc, m);
+    int st = validate_gemm(M, N, K, A, lda, B, ldb, C, ldc, mode);
     if (st != MFG_OK) return st;
     if (count > 1 && M > 0 && N > 0 && strideC < (M - 1) * ldc + N) return MFG_ERR_INVALID_ARG;  // outputs overlap
     if (m == MFG_FP8_E4M3) return MFG_ERR_UNSUPPORTED;
@@ -257,7 +265,16 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
     bool vec;
     const bool split_mode = two_planes_a(m);
     std::unique_ptr<WsLease> ws;
-    if (!split_mode) {
+    if (split_mode && pre) {
+        // entry b: head plane at A + b*strideA, residual plane rows*ld later
+        const uint16_t* pa = static_cast<const uint16_t*>(A);
+        const uint16_t* pb = static_cast<const uint16_t*>(B);
+        a.A[0] = pa, a.A[1] = pa + M * lda;
+        a.B[0] = pb, a.B[1] = two_planes_b(m) ? pb + K * ldb : nullptr;
+        a.lda = lda, a.ldb = ldb, a.sA = strideA, a.sB = strideB;
+        vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && strideA % 8 == 0 && strideB % 8 == 0 &&
+              buffer_ldc_ok(ldc);
+    } else if (!split_mode) {
         a.A[0] = static_cast<const uint16_t*>(A), a.B[0] = static_cast<const uint16_t*>(B);
         a.lda = lda, a.ldb = ldb, a.sA = strideA, a.sB = strideB;
         vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && strideA % 8 == 0 && strideB % 8 == 0 &&

@@ -17,6 +17,7 @@
 // configurations of a kind give bitwise-identical results.
 #include "fast16.h"
 #include "pipe16.h"
+#include "runtime.h"
 #include "tile16.h"
 
 namespace mfg {
@@ -183,6 +184,20 @@ const char* config16_name(int kind, int cfg) {
     return (cfg >= 0 && cfg < n) ? m[cfg].name : nullptr;
 }
 
+// Whether configuration `cfg` of `kind` serves this problem (launch_kind would
+// not return MFG_ERR_UNSUPPORTED): the simple kernel serves every problem;
+// the others need 16-byte aligned rows and ldc < kBufferLdcLimit, and the
+// fast and pipelined kernels also K % 64 == 0, N % 8 == 0, N >= 8.
+bool config16_ok(int kind, int cfg, int64_t M, int64_t N, int64_t K, int64_t ldc, bool vec_ok) {
+    int n;
+    const Cfg16* m = menu(kind, &n);
+    if (cfg < 0 || cfg >= n) return false;
+    if (cfg == 0) return true;
+    if (!vec_ok || !buffer_ldc_ok(ldc)) return false;
+    if (m[cfg].fast == 0) return true;
+    return K % 64 == 0 && N % 8 == 0 && N >= 8 && M >= 1;
+}
+
 template <int KIND>
 static int launch_kind(int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok, hipStream_t s) {
     int n;
@@ -279,6 +294,7 @@ static int launch_kind(int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok,
 }
 
 int launch_gemm16(int kind, int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok, hipStream_t s) {
+    if (fault_hit(kFaultLaunch)) return hip_fail(hipErrorLaunchFailure);  // injected (tests)
     switch (kind) {
         case K_F16: return launch_kind<K_F16>(cfg, a, batch, vec_ok, s);
         case K_BF16: return launch_kind<K_BF16>(cfg, a, batch, vec_ok, s);

@@ -8,6 +8,7 @@
 // products at k = kb + j (lane half 0) and k = kb + 4 + j (lane half 1).
 #include "device.h"
 #include "internal.h"
+#include "runtime.h"
 
 namespace mfg {
 
@@ -205,7 +206,13 @@ static int launch_f32_tiled(const GemmF32Args& a, int64_t batch, int group_m, hi
     return MFG_OK;
 }
 
+bool config_f32_ok(int cfg, int64_t ldc, bool vec_ok) {
+    if (cfg < 0 || cfg >= num_configs_f32()) return false;
+    return cfg == 0 || (vec_ok && buffer_ldc_ok(ldc));
+}
+
 int launch_gemm_f32(int cfg, const GemmF32Args& a, int64_t batch, bool vec_ok, hipStream_t s) {
+    if (fault_hit(kFaultLaunch)) return hip_fail(hipErrorLaunchFailure);  // injected (tests)
     if (cfg < 0 || cfg >= num_configs_f32()) return MFG_ERR_INVALID_ARG;
     if (cfg != 0 && (!vec_ok || !buffer_ldc_ok(a.ldc))) return MFG_ERR_UNSUPPORTED;
     const CfgF32& c = kCfgF32[cfg];

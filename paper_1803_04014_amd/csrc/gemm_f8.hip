@@ -12,6 +12,7 @@
 #include "device.h"
 #include "internal.h"
 #include "pipe16.h"
+#include "runtime.h"
 
 namespace mfg {
 
@@ -251,9 +252,15 @@ static int launch_f8_pipe(const GemmF8Args& a, int group_m, hipStream_t s) {
 int num_configs_f8() { return kNumF8; }
 const char* config_f8_name(int cfg) { return (cfg >= 0 && cfg < kNumF8) ? kCfgF8[cfg].name : nullptr; }
 bool f8_config_needs_bt(int cfg) { return cfg > 0 && cfg < kNumF8; }
+bool config_f8_ok(int cfg, int64_t M, int64_t N, int64_t K, int64_t ldc, bool vec_ok) {
+    if (cfg < 0 || cfg >= kNumF8) return false;
+    if (cfg == 0) return true;
+    return vec_ok && K % 128 == 0 && M >= 1 && N >= 1 && buffer_ldc_ok(ldc);
+}
 
 // The tiled kernels need K % 128 == 0, 16-byte aligned rows of A and Bt.
 int launch_gemm_f8(int cfg, const GemmF8Args& a, bool vec_ok, hipStream_t s) {
+    if (fault_hit(kFaultLaunch)) return hip_fail(hipErrorLaunchFailure);  // injected (tests)
     if (cfg < 0 || cfg >= kNumF8) return MFG_ERR_INVALID_ARG;
     if (cfg == 0) {
         dim3 grid((unsigned)cdiv(a.N, 32), (unsigned)cdiv(a.M, 32), 1);

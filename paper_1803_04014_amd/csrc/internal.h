@@ -80,6 +80,12 @@ int num_configs16(int kind);
 const char* config16_name(int kind, int cfg);
 int pick_config16(int kind, int64_t M, int64_t N, int64_t K, bool vec_ok);
 int launch_gemm16(int kind, int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok, hipStream_t s);
+// Whether a configuration serves a problem (its launch would not return
+// MFG_ERR_UNSUPPORTED); a tuned choice that does not is replaced by the
+// default.  vec_ok: 16-byte aligned rows of A and B (FP8: of A's codes).
+bool config16_ok(int kind, int cfg, int64_t M, int64_t N, int64_t K, int64_t ldc, bool vec_ok);
+bool config_f32_ok(int cfg, int64_t ldc, bool vec_ok);
+bool config_f8_ok(int cfg, int64_t M, int64_t N, int64_t K, int64_t ldc, bool vec_ok);
 
 int num_configs_f32();
 const char* config_f32_name(int cfg);

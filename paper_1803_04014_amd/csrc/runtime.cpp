@@ -2,8 +2,10 @@
 // tuned-configuration table of libmfgemm.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -61,6 +63,10 @@ void* grow(Region* r, hipStream_t s, size_t bytes, int* status) {
         r->ptr = nullptr;
         r->size = 0;
     }
+    if (fault_hit(kFaultAlloc)) {
+        *status = MFG_ERR_NO_MEMORY;
+        return nullptr;
+    }
     size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
     want = (want + ((size_t)2 << 20) - 1) / ((size_t)2 << 20) * ((size_t)2 << 20);
     void* p = nullptr;
@@ -105,6 +111,46 @@ int device_cu_count() {
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
     cache[dev] = n;
     return n;
+}
+
+// ---------------------------------------------------------- fault injection
+namespace {
+std::atomic<int64_t> g_fault_left[kFaultKinds];  // calls until the injected fault; <= 0: off
+std::once_flag g_fault_env_once;
+
+int64_t parse_fault(const char* spec, const char* key) {
+    if (!spec) return 0;
+    const char* p = std::strstr(spec, key);
+    if (!p) return 0;
+    p += std::strlen(key);
+    if (*p != ':') return 0;
+    const long long n = std::strtoll(p + 1, nullptr, 10);
+    return n > 0 ? (int64_t)n : 0;
+}
+}  // namespace
+
+void fault_arm(int64_t launch_n, int64_t alloc_n) {
+    g_fault_left[kFaultLaunch].store(launch_n > 0 ? launch_n : 0);
+    g_fault_left[kFaultAlloc].store(alloc_n > 0 ? alloc_n : 0);
+}
+
+void fault_reload() {
+    const char* spec = std::getenv("MFG_FAULT");
+    fault_arm(parse_fault(spec, "launch"), parse_fault(spec, "alloc"));
+}
+
+bool fault_hit(int kind) {
+    std::call_once(g_fault_env_once, fault_reload);
+    if (g_fault_left[kind].load(std::memory_order_relaxed) <= 0) return false;
+    return g_fault_left[kind].fetch_sub(1) == 1;
+}
+
+bool log_enabled() {
+    static const bool on = [] {
+        const char* p = std::getenv("MFG_LOG");
+        return p && *p && *p != '0';
+    }();
+    return on;
 }
 
 // ------------------------------------------------------------- tuned table
@@ -187,5 +233,12 @@ extern "C" int mfg_tune_clear(void) {
     std::lock_guard<std::mutex> g(mfg::g_tune_mu);
     mfg::g_tune.clear();
     mfg::g_tune_env_loaded = true;
+    return MFG_OK;
+}
+
+extern "C" int mfg_fault_inject(int64_t launch_n, int64_t alloc_n) {
+    if (launch_n < 0 || alloc_n < 0) return MFG_ERR_INVALID_ARG;
+    mfg::fault_hit(mfg::kFaultLaunch);  // reads MFG_FAULT once, so it cannot override this call later
+    mfg::fault_arm(launch_n, alloc_n);
     return MFG_OK;
 }

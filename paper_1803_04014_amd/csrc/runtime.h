@@ -24,6 +24,19 @@ class WsLease {
     int status_ = 0;
 };
 
+// Fault injection for tests of failure handling (MFG_FAULT=launch:<n>,alloc:<n>
+// or mfg_fault_inject): the n-th kernel launch / device allocation after
+// arming fails as if the HIP runtime had refused it, once.  Launches are
+// counted where a GEMM, grouped or conversion launch is about to be
+// enqueued, allocations where the library or the server allocates device
+// memory.  Off unless armed.
+enum { kFaultLaunch = 0, kFaultAlloc = 1, kFaultKinds = 2 };
+void fault_arm(int64_t launch_n, int64_t alloc_n);
+void fault_reload();  // re-read MFG_FAULT
+bool fault_hit(int kind);
+// MFG_LOG set (not "0"): one line per GEMM launch decision on stderr.
+bool log_enabled();
+
 int size_bucket(int64_t x);
 int tuned_lookup(int mode, int64_t M, int64_t N, int64_t K);
 void tuned_store(int mode, int64_t M, int64_t N, int64_t K, int cfg);

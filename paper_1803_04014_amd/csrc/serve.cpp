@@ -11,15 +11,18 @@
 //      that does not fit blocks the ones behind it (no starvation of large
 //      requests);
 //   3. launches: while a slot (one non-blocking HIP stream of default
-//      priority) is free, the oldest admitted request picks a group of up to
-//      max_group admitted requests with its mode (and its alpha and beta,
-//      which a grouped launch shares).  On the slot's stream
-//      each request's FP32 operands are converted into stream-ordered
-//      allocations (the paper's rounding / Eq. R split / FP8 quantisation),
-//      then the GEMMs run: small FP16 / BF16 / refined (Eq. 1, Eq. 2)
-//      problems of the group as ONE persistent grouped launch, every other
-//      problem through mfg_gemm on
-//      the converted operands; one event marks the group's end.
+//      priority) is free, the oldest admitted request takes it.  A small
+//      FP16 / BF16 / refined (Eq. 1, Eq. 2) request takes up to max_group
+//      admitted small requests with its mode, alpha and beta into ONE
+//      persistent grouped launch; any other request runs alone on the slot
+//      through mfg_gemm, so large requests spread over the free slots and
+//      a small request never waits for a large one's completion event.  On
+//      the slot's stream each request's FP32 operands are converted into
+//      stream-ordered allocations (the paper's rounding / Eq. R split / FP8
+//      quantisation), then the GEMM runs; one event marks the slot's end.
+// The scheduler picks the groups under the server mutex, then enqueues the
+// conversions and launches (and queries completion events) with the mutex
+// released, so mfg_submit / mfg_poll never wait behind HIP calls.
 // Every kernel the server runs is one that mfg_gemm / the grouped plan would
 // run for the same problem, and all 16-bit kernels share one accumulation
 // order, so a request's result does not depend on what it was batched with.
@@ -32,6 +35,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdio>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -44,6 +48,7 @@
 
 #include "internal.h"
 #include "mfgemm.h"
+#include "runtime.h"
 
 namespace mfg {
 namespace {
@@ -97,11 +102,13 @@ int grouped_kind(int mode) {
     }
 }
 
-// A problem the grouped kernel takes (few work items).
+// A problem the grouped kernel takes (few work items; K within its int32
+// work records).  Requests that convert nothing run through mfg_gemm.
 constexpr int64_t kSmallTiles = 256;
 bool grouped_small(const mfg_request& r) {
     const int kind = grouped_kind(r.mode);
-    if (kind < 0 || r.M * r.N >= (int64_t)512 * 512) return false;
+    if (kind < 0 || r.M * r.N >= (int64_t)512 * 512 || r.K > INT32_MAX) return false;
+    if (r.M == 0 || r.N == 0 || r.K == 0 || r.alpha == 0.0f) return false;
     const int t = grouped_tile(kind);
     return cdiv(r.M, t) * cdiv(r.N, t) <= kSmallTiles;
 }
@@ -145,11 +152,12 @@ struct mfg_server {
     int init_device();
     void release_device();
     void loop();
-    bool complete_ready();
+    bool complete_ready(std::unique_lock<std::mutex>& lk);
     bool admit();
-    bool launch_ready();
-    void launch_group(int si, std::vector<Req*>& g);
-    int run_request(Slot& sl, Req* q, bool& grouped);
+    bool launch_ready(std::unique_lock<std::mutex>& lk);
+    void start_group(int si, const std::vector<Req*>& g);
+    void enqueue_group(int si, const std::vector<Req*>& g, std::vector<int>& status, bool& event_failed);
+    int run_request(Slot& sl, Req* q, bool grouped);
     int run_grouped(Slot& sl, const std::vector<Req*>& g);
 };
 
@@ -184,10 +192,27 @@ void mfg_server::release_device() {
     }
 }
 
-bool mfg_server::complete_ready() {
+// Called with the mutex held; releases it around the event queries (the
+// slots' streams and events belong to the scheduler thread alone).
+bool mfg_server::complete_ready(std::unique_lock<std::mutex>& lk) {
     bool any = false;
     const int64_t t = now_ns();
-    for (auto& sl : slots) {
+    std::vector<hipError_t> ev(slots.size(), hipErrorNotReady);
+    std::vector<char> query(slots.size(), 0);
+    bool need_query = false;
+    for (size_t i = 0; i < slots.size(); ++i) {
+        const Slot& sl = slots[i];
+        query[i] = sl.busy && !sl.force_ready && !dry;
+        need_query |= query[i] != 0;
+    }
+    if (need_query) {
+        lk.unlock();
+        for (size_t i = 0; i < slots.size(); ++i)
+            if (query[i]) ev[i] = hipEventQuery(slots[i].done);
+        lk.lock();
+    }
+    for (size_t i = 0; i < slots.size(); ++i) {
+        Slot& sl = slots[i];
         if (!sl.busy) continue;
         bool ready;
         if (sl.force_ready) {
@@ -195,7 +220,7 @@ bool mfg_server::complete_ready() {
         } else if (dry) {
             ready = t >= sl.dry_end_ns;
         } else {
-            const hipError_t e = hipEventQuery(sl.done);
+            const hipError_t e = ev[i];
             ready = e != hipErrorNotReady;
             if (ready && e != hipSuccess) {
                 const int code = hip_fail(e);
@@ -239,39 +264,82 @@ bool mfg_server::admit() {
     return any;
 }
 
-bool mfg_server::launch_ready() {
-    bool any = false;
+// Called with the mutex held.  Picks a group for every free slot (marking
+// the slot busy and its requests running), then releases the mutex while
+// it enqueues their work, and records the outcome under it again.
+bool mfg_server::launch_ready(std::unique_lock<std::mutex>& lk) {
+    std::vector<std::pair<int, std::vector<Req*>>> picked;
     for (int si = 0; si < (int)slots.size() && !admitted.empty(); ++si) {
         if (slots[si].busy) continue;
-        const mfg_request& h = admitted.front()->r;
-        const int mode = h.mode;
-        const float al = h.alpha, be = h.beta;
+        Req* head = admitted.front();
         std::vector<Req*> g;
-        for (auto it = admitted.begin(); it != admitted.end() && (int)g.size() < cfg.max_group;) {
-            const mfg_request& r = (*it)->r;
-            if (r.mode == mode && r.alpha == al && r.beta == be) {
-                g.push_back(*it);
-                it = admitted.erase(it);
-            } else {
-                ++it;
+        if (!grouped_small(head->r)) {
+            g.push_back(head);
+            admitted.pop_front();
+        } else {
+            const mfg_request& h = head->r;
+            for (auto it = admitted.begin(); it != admitted.end() && (int)g.size() < cfg.max_group;) {
+                const mfg_request& r = (*it)->r;
+                if (r.mode == h.mode && r.alpha == h.alpha && r.beta == h.beta && grouped_small(r)) {
+                    g.push_back(*it);
+                    it = admitted.erase(it);
+                } else {
+                    ++it;
+                }
             }
         }
-        launch_group(si, g);
-        any = true;
+        start_group(si, g);
+        picked.emplace_back(si, std::move(g));
     }
     int64_t busy = 0;
     for (auto& sl : slots) busy += sl.busy ? 1 : 0;
     st.max_concurrent_slots = std::max(st.max_concurrent_slots, busy);
-    return any;
+    if (picked.empty()) return false;
+    if (dry) {
+        // the dry run's executor: the fault hooks, in the order a real run meets them
+        for (auto& [si, g] : picked) {
+            bool grouped_failed = false;
+            const bool grouped = grouped_small(g.front()->r);
+            for (Req* q : g)
+                if (q->footprint > 0 && fault_hit(kFaultAlloc)) q->res.status = MFG_ERR_NO_MEMORY;
+            if (grouped) grouped_failed = fault_hit(kFaultLaunch);
+            for (Req* q : g) {
+                const mfg_request& r = q->r;
+                const bool gemm = r.M > 0 && r.N > 0 && r.K > 0 && r.alpha != 0.0f;  // else no GEMM launch
+                if (q->res.status == MFG_PENDING && (grouped ? grouped_failed : gemm && fault_hit(kFaultLaunch)))
+                    q->res.status = MFG_ERR_HIP;
+            }
+            if (log_enabled())
+                std::fprintf(stderr, "mfg_server: slot %d mode %d group %zu (dry run)\n", si, g.front()->r.mode,
+                             g.size());
+        }
+        return true;
+    }
+    std::vector<std::vector<int>> status(picked.size());
+    std::vector<char> event_failed(picked.size(), 0);
+    lk.unlock();
+    for (size_t i = 0; i < picked.size(); ++i) {
+        bool ef = false;
+        enqueue_group(picked[i].first, picked[i].second, status[i], ef);
+        event_failed[i] = ef;
+    }
+    lk.lock();
+    for (size_t i = 0; i < picked.size(); ++i) {
+        const std::vector<Req*>& g = picked[i].second;
+        for (size_t j = 0; j < g.size(); ++j)
+            if (status[i][j] != MFG_OK && g[j]->res.status == MFG_PENDING) g[j]->res.status = status[i][j];
+        if (event_failed[i]) slots[picked[i].first].force_ready = true;
+    }
+    return true;
 }
 
-// Convert one request's operands on the slot stream; run it unless it joins
-// the group's grouped launch.
-int mfg_server::run_request(Slot& sl, Req* q, bool& grouped) {
+// Convert one request's operands on the slot stream and run it, unless it
+// joins the group's grouped launch (grouped: conversion only).
+int mfg_server::run_request(Slot& sl, Req* q, bool grouped) {
     const mfg_request& r = q->r;
-    grouped = false;
     if (q->footprint == 0)  // F32, empty, K == 0 or alpha == 0: no conversion
         return mfg_gemm(r.M, r.N, r.K, r.A, r.lda, r.B, r.ldb, r.C, r.ldc, r.alpha, r.beta, r.mode, sl.stream);
+    if (fault_hit(kFaultAlloc)) return MFG_ERR_NO_MEMORY;
     hipError_t e = hipMallocAsync(&q->ws, (size_t)q->footprint, sl.stream);
     if (e != hipSuccess) {
         q->ws = nullptr;
@@ -283,11 +351,7 @@ int mfg_server::run_request(Slot& sl, Req* q, bool& grouped) {
     const int mb = (r.mode == MFG_F16_REFINE_A) ? MFG_F16 : r.mode;
     int s = mfg_convert(r.M, r.K, r.A, r.lda, wa, q->lda_c, r.mode, sl.stream);
     if (s == MFG_OK) s = mfg_convert(r.K, r.N, r.B, r.ldb, wb, q->ldb_c, mb, sl.stream);
-    if (s != MFG_OK) return s;
-    if (grouped_small(r)) {
-        grouped = true;
-        return MFG_OK;
-    }
+    if (s != MFG_OK || grouped) return s;
     return mfg_gemm(r.M, r.N, r.K, wa, q->lda_c, wb, q->ldb_c, r.C, r.ldc, r.alpha, r.beta,
                     r.mode | MFG_IN_PRECONVERTED, sl.stream);
 }
@@ -329,7 +393,8 @@ int mfg_server::run_grouped(Slot& sl, const std::vector<Req*>& g) {
                           g.front()->r.beta, sl.stream);
 }
 
-void mfg_server::launch_group(int si, std::vector<Req*>& g) {
+// Mutex held: the slot takes the group.
+void mfg_server::start_group(int si, const std::vector<Req*>& g) {
     Slot& sl = slots[si];
     const int64_t t = now_ns();
     double flops = 0.0;
@@ -343,35 +408,48 @@ void mfg_server::launch_group(int si, std::vector<Req*>& g) {
     sl.running = g;
     sl.busy = true;
     ++st.launches;
-    if (dry) {
-        sl.dry_end_ns = t + (int64_t)(flops / 1e5);  // 1e14 flop/s
-        return;
-    }
+    if (dry) sl.dry_end_ns = t + (int64_t)(flops / 1e5);  // 1e14 flop/s
+}
+
+// Mutex released: enqueue the group's conversions and GEMM(s) on the slot's
+// stream and its completion event.  status[j] receives request j's outcome
+// (MFG_OK or an error); event_failed is set when no completion event could
+// be recorded (the stream has then been synchronised).
+void mfg_server::enqueue_group(int si, const std::vector<Req*>& g, std::vector<int>& status, bool& event_failed) {
+    Slot& sl = slots[si];
+    status.assign(g.size(), MFG_OK);
+    const bool grouped = grouped_small(g.front()->r);
     std::vector<Req*> small;
-    for (Req* q : g) {
-        bool grouped = false;
-        const int s = run_request(sl, q, grouped);
-        if (s != MFG_OK) q->res.status = s;
-        else if (grouped) small.push_back(q);
+    std::vector<size_t> small_idx;
+    for (size_t j = 0; j < g.size(); ++j) {
+        status[j] = run_request(sl, g[j], grouped);
+        if (status[j] == MFG_OK && grouped) {
+            small.push_back(g[j]);
+            small_idx.push_back(j);
+        }
     }
     if (!small.empty()) {
         const int s = run_grouped(sl, small);
         if (s != MFG_OK)
-            for (Req* q : small) q->res.status = s;
+            for (size_t j : small_idx) status[j] = s;
     }
+    if (log_enabled())
+        std::fprintf(stderr, "mfg_server: slot %d mode %d group %zu%s\n", si, g.front()->r.mode, g.size(),
+                     grouped ? " grouped" : "");
     for (Req* q : g)
         if (q->ws) {
             (void)hipFreeAsync(q->ws, sl.stream);
             q->ws = nullptr;
         }
     const hipError_t e = hipEventRecord(sl.done, sl.stream);
+    event_failed = false;
     if (e != hipSuccess) {
         // no event to wait for: finish the stream here and report the error
         const int code = hip_fail(e);
         (void)hipStreamSynchronize(sl.stream);
-        for (Req* q : g)
-            if (q->res.status == MFG_PENDING) q->res.status = code;
-        sl.force_ready = true;
+        for (size_t j = 0; j < g.size(); ++j)
+            if (status[j] == MFG_OK) status[j] = code;
+        event_failed = true;
     }
 }
 
@@ -387,9 +465,9 @@ void mfg_server::loop() {
     init_status = MFG_OK;
     cv_done.notify_all();
     while (true) {
-        bool progressed = complete_ready();
+        bool progressed = complete_ready(lk);
         progressed |= admit();
-        progressed |= launch_ready();
+        progressed |= launch_ready(lk);
         if (progressed) continue;
         bool busy = false;
         for (auto& sl : slots) busy |= sl.busy;
@@ -406,6 +484,7 @@ extern "C" int mfg_server_create(const mfg_server_config* cfg, mfg_server** out)
     if (cfg->slots < 1 || cfg->slots > 64 || cfg->max_group < 1 || cfg->max_group > 4096 || cfg->device < -1 ||
         cfg->reserved != 0)
         return MFG_ERR_INVALID_ARG;
+    fault_reload();  // MFG_FAULT as set now (also for the dry run's executor)
     try {
         std::unique_ptr<mfg_server> s(new mfg_server());
         s->cfg = *cfg;

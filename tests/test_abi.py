@@ -156,3 +156,40 @@ def test_grouped_plan_rejects_bad_modes_before_any_device_call():
     assert L.mfg_grouped_plan_create(-1, probs, capi.MFG_F16, ctypes.byref(h)) == capi.MFG_ERR_INVALID_ARG
     # MFG_IN_FP32 is a grouped-plan flag only: the single GEMM's validation rejects it
     assert L.mfg_validate_gemm(8, 8, 8, P, 8, P, 8, P, 8, capi.MFG_F16 | capi.MFG_IN_FP32) == capi.MFG_ERR_INVALID_ARG
+
+
+def test_batched_validates_mode_flags_before_any_device_call():
+    """mfg_gemm_batched checks the whole mode: only MFG_IN_PRECONVERTED may
+    accompany it (implied for F16 / BF16 / F32, the preconverted planes for
+    the refined modes); FP8 is unsupported.  count = 0 returns before any
+    device call once the arguments are valid."""
+    L = mfg.lib()
+
+    def call(count, mode):
+        return L.mfg_gemm_batched(count, 8, 8, 8, P, 8, 64, P, 8, 64, P, 8, 64, 1.0, 0.0, mode, None)
+
+    assert call(1, capi.MFG_F16 | capi.MFG_IN_FP32) == capi.MFG_ERR_INVALID_ARG
+    assert call(1, capi.MFG_F16_SPLIT3 | capi.MFG_IN_FP32) == capi.MFG_ERR_INVALID_ARG
+    assert call(1, capi.MFG_F16_SPLIT3 | 0x400) == capi.MFG_ERR_INVALID_ARG
+    assert call(1, 99) == capi.MFG_ERR_INVALID_ARG
+    assert call(1, capi.MFG_FP8_E4M3) == capi.MFG_ERR_UNSUPPORTED
+    assert call(1, capi.MFG_FP8_E4M3 | capi.MFG_IN_PRECONVERTED) == capi.MFG_ERR_UNSUPPORTED
+    for m in ("f16", "bf16", "f32", "refine_a", "split3", "split4", "bf16_split3"):
+        assert call(0, capi.MODE_BY_NAME[m]) == capi.MFG_OK
+        assert call(0, capi.MODE_BY_NAME[m] | capi.MFG_IN_PRECONVERTED) == capi.MFG_OK
+
+
+def test_fault_inject_arguments():
+    L = mfg.lib()
+    assert L.mfg_fault_inject(-1, 0) == capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_fault_inject(0, -3) == capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_fault_inject(0, 0) == capi.MFG_OK
+
+
+def test_probe_mfma_arguments():
+    L = mfg.lib()
+    f = ctypes.c_double()
+    assert L.mfg_probe_mfma(2, P, 1, 1, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_probe_mfma(0, None, 1, 1, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_probe_mfma(0, P, 0, 1, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_probe_mfma(1, P, 1, 0, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG

@@ -132,3 +132,65 @@ def test_degenerate_requests_on_gpu():
     assert res[t1]["status"] == 0 and res[t2]["status"] == 0
     assert np.all(host(c0) == 1.0)
     assert np.all(np.isfinite(host(c1)))
+
+
+def test_small_requests_overlap_a_long_one():
+    """Continuous batching on the device: with four slots, small requests that
+    arrive while a long request runs are admitted onto the free slots and
+    finish before it; each result is bitwise that of the request alone."""
+    A, B, dA, dB = _pools(21)
+    big = [torch.ones((8192, 8192), device=DEV) for _ in range(3)]  # FP32 8192^3: ~9 ms alone
+    reqs = _requests(22, 12, 64, 384)
+    views = []
+    for r in reqs:
+        (ar, ac), (br, bc) = r["a"], r["b"]
+        views.append((dA[ar:ar + r["M"], ac:ac + r["K"]], dB[br:br + r["K"], bc:bc + r["N"]], dev(r["C0"])))
+    torch.cuda.synchronize()
+    server = mfg.Server(1 << 30, slots=4, max_group=4)
+    tb = server.submit(big[0], big[1], big[2], "f32")
+    time.sleep(0.002)  # the long request is on the device
+    tickets = [server.submit(a, b, c, r["mode"], r["alpha"], r["beta"]) for r, (a, b, c) in zip(reqs, views)]
+    res = _wait(server, [tb] + tickets)
+    stats = server.stats()
+    server.close()
+    assert res[tb]["status"] == 0
+    assert stats["max_concurrent_slots"] >= 2
+    early = [t for t in tickets if res[t]["t_end_ns"] < res[tb]["t_end_ns"]]
+    assert len(early) >= len(tickets) // 2, "small requests waited for the long one"
+    for i, (r, (a, b, c), t) in enumerate(zip(reqs, views, tickets)):
+        assert res[t]["status"] == 0
+        if t in early:
+            assert res[t]["slot"] != res[tb]["slot"]
+        alone = dev(r["C0"])
+        mfg.gemm(a, b, alone, r["alpha"], r["beta"], mode=r["mode"])
+        assert np.array_equal(host(c).view(np.uint32), host(alone).view(np.uint32)), f"request {i} ({r['mode']})"
+
+
+def test_injected_launch_fault_fails_one_request_on_gpu():
+    """A launch failure (injected on the host: the GEMM is not launched) marks
+    that request failed; the server keeps serving and every other result is
+    bitwise that of the request alone."""
+    A, B, dA, dB = _pools(23)
+    shapes = [(600, 520, 256), (640, 520, 320), (520, 600, 128), (700, 512, 192)]  # not grouped: one launch each
+    views = [(dA[:m, :k], dB[:k, :n], dev(np.zeros((m, n), np.float32))) for m, n, k in shapes]
+    torch.cuda.synchronize()
+    server = mfg.Server(1 << 30, slots=1, max_group=1)
+    assert mfg.lib().mfg_fault_inject(2, 0) == 0
+    try:
+        tickets = []
+        for a, b, c in views:  # one at a time: launches happen in submission order
+            tickets.append(server.submit(a, b, c, "split3"))
+            server.drain()
+        res = _wait(server, tickets)
+    finally:
+        mfg.lib().mfg_fault_inject(0, 0)
+    stats = server.stats()
+    server.close()
+    assert [res[t]["status"] for t in tickets] == [0, mfg.capi.MFG_ERR_HIP, 0, 0]
+    assert stats["failed"] == 1 and stats["completed"] == 3 and stats["bytes_in_use"] == 0
+    for i, ((a, b, c), t) in enumerate(zip(views, tickets)):
+        if i == 1:
+            continue
+        alone = torch.zeros_like(c)
+        mfg.gemm(a, b, alone, 1.0, 0.0, mode="split3")
+        assert np.array_equal(host(c).view(np.uint32), host(alone).view(np.uint32))

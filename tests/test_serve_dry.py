@@ -221,3 +221,98 @@ def test_concurrent_submitters_and_drain():
     res = wait_all(s, tickets)
     assert all(r["status"] == 0 for r in res.values())
     s.close()
+
+
+def _arm(launch_n=0, alloc_n=0):
+    assert mfg.lib().mfg_fault_inject(launch_n, alloc_n) == 0
+
+
+def test_injected_launch_fault_fails_one_request_and_serving_continues():
+    s = mfg.Server(1 << 40, slots=1, device=-1, max_group=1)
+    _arm(launch_n=3)
+    try:
+        # 1024^3: not a grouped size, so one launch per request, in submission order
+        tickets = [submit(s, 1024, 1024, 1024, "f16") for _ in range(6)]
+        res = wait_all(s, tickets)
+    finally:
+        _arm()
+    status = [res[t]["status"] for t in tickets]
+    assert status == [0, 0, capi.MFG_ERR_HIP, 0, 0, 0]
+    st = s.stats()
+    assert st["failed"] == 1 and st["completed"] == 5 and st["bytes_in_use"] == 0
+    # the server keeps serving after the failure
+    t = submit(s, 64, 64, 64, "split3")
+    assert wait_all(s, [t])[t]["status"] == 0
+    s.close()
+
+
+def test_injected_alloc_fault_marks_request_out_of_memory():
+    s = mfg.Server(1 << 40, slots=2, device=-1, max_group=1)
+    _arm(alloc_n=2)
+    try:
+        tickets = []
+        for _ in range(5):  # one at a time, so allocations happen in submission order
+            tickets.append(submit(s, 1024, 1024, 1024, "split3"))
+            s.drain()
+        res = wait_all(s, tickets)
+    finally:
+        _arm()
+    assert [res[t]["status"] for t in tickets] == [0, capi.MFG_ERR_NO_MEMORY, 0, 0, 0]
+    assert s.stats()["failed"] == 1 and s.stats()["bytes_in_use"] == 0
+    s.close()
+
+
+def test_injected_fault_in_grouped_launch_fails_its_group_only():
+    s = mfg.Server(1 << 40, slots=1, device=-1, max_group=4)
+    big = submit(s, 8192, 8192, 8192, "f16")  # holds the one slot while the small ones queue
+    small = [submit(s, 48, 48, 48, "bf16") for _ in range(8)]
+    _arm(launch_n=2)  # the first group after the big request
+    try:
+        res = wait_all(s, [big] + small)
+    finally:
+        _arm()
+    assert res[big]["status"] == 0
+    failed = [t for t in small if res[t]["status"] != 0]
+    assert len(failed) == 4 and all(res[t]["status"] == capi.MFG_ERR_HIP for t in failed)
+    assert len({res[t]["t_start_ns"] for t in failed}) == 1  # one grouped launch
+    assert s.stats()["failed"] == 4
+    s.close()
+
+
+def test_fault_from_environment(monkeypatch):
+    monkeypatch.setenv("MFG_FAULT", "launch:2")
+    s = mfg.Server(1 << 40, slots=1, device=-1, max_group=1)  # reads MFG_FAULT
+    monkeypatch.delenv("MFG_FAULT")
+    try:
+        tickets = [submit(s, 1024, 1024, 1024, "bf16") for _ in range(3)]
+        res = wait_all(s, tickets)
+    finally:
+        _arm()
+    assert [res[t]["status"] for t in tickets] == [0, capi.MFG_ERR_HIP, 0]
+    s.close()
+
+
+def test_large_requests_run_alone_on_separate_slots():
+    s = mfg.Server(1 << 40, slots=4, device=-1, max_group=16)
+    big = [submit(s, 8192, 8192, 8192, "f16") for _ in range(4)]  # 11 ms of dry-run time each
+    small = [submit(s, 64, 64, 64, "f16") for _ in range(3)]
+    res = wait_all(s, big + small)
+    assert all(res[t]["group_size"] == 1 for t in big)
+    assert len({res[t]["slot"] for t in big}) == 4
+    assert s.stats()["max_concurrent_slots"] == 4
+    # the small ones form one group of their own, never joined with a large one
+    assert len({res[t]["t_start_ns"] for t in small}) == 1 and res[small[0]]["group_size"] == 3
+    s.close()
+
+
+def test_huge_k_never_joins_a_grouped_launch():
+    # K > INT32_MAX does not fit the grouped kernel's work records
+    s = mfg.Server(1 << 40, slots=1, device=-1, max_group=8)
+    big = submit(s, 8192, 8192, 8192, "f16")
+    small = [submit(s, 16, 16, 16, "f16") for _ in range(3)]
+    K = (1 << 31) + 8
+    huge = submit(s, 16, 16, K, "f16")
+    res = wait_all(s, [big, huge] + small)
+    assert res[huge]["status"] == 0 and res[huge]["group_size"] == 1
+    assert all(res[t]["group_size"] == 3 for t in small)
+    s.close()
