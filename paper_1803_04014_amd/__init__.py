@@ -67,16 +67,23 @@ def gemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, mode="f16", preconverte
     check("mfg_gemm", st)
 
 
-def gemm_batched(A, B, C, alpha: float = 1.0, beta: float = 0.0, mode="f16", stream=None) -> None:
-    """mfg_gemm_batched over 3-D tensors (batch, rows, cols), row-major entries."""
-    cnt, M, K = A.shape
-    N = B.shape[2]
+def gemm_batched(A, B, C, alpha: float = 1.0, beta: float = 0.0, mode="f16", preconverted: bool = False,
+                 M: int | None = None, K: int | None = None, stream=None) -> None:
+    """mfg_gemm_batched over 3-D tensors (batch, rows, cols), row-major entries.
+
+    With ``preconverted`` each entry holds the mode's storage form (head plane,
+    then residual plane); ``M`` and ``K`` then give the logical sizes."""
+    cnt = A.shape[0]
+    Mv = C.shape[1] if M is None else M
+    Kv = A.shape[2] if K is None else K
+    N = C.shape[2]
     for t in (A, B, C):
         if t.dim() != 3 or t.stride(2) != 1:
             raise ValueError("expected 3-D tensors with unit innermost stride")
-    st = lib().mfg_gemm_batched(cnt, M, N, K, _ptr(A), max(1, A.stride(1)), A.stride(0), _ptr(B),
+    m = mode_of(mode) | (MFG_IN_PRECONVERTED if preconverted else 0)
+    st = lib().mfg_gemm_batched(cnt, Mv, N, Kv, _ptr(A), max(1, A.stride(1)), A.stride(0), _ptr(B),
                                 max(1, B.stride(1)), B.stride(0), _ptr(C), max(1, C.stride(1)), C.stride(0),
-                                float(alpha), float(beta), mode_of(mode), ctypes.c_void_p(_stream(stream)))
+                                float(alpha), float(beta), m, ctypes.c_void_p(_stream(stream)))
     check("mfg_gemm_batched", st)
 
 

@@ -79,3 +79,36 @@ def test_autotune_rejects_bad_arguments():
     st = mfg.lib().mfg_autotune(8, 8, 8, None, 8, A.data_ptr(), 8, C.data_ptr(), 8, mfg.MFG_F16 | mfg.MFG_IN_PRECONVERTED,
                                 1, ctypes.byref(best), None, None)
     assert st == mfg.capi.MFG_ERR_INVALID_ARG
+
+
+def test_tuned_config_that_does_not_serve_the_shape_falls_back(tmp_path):
+    """The tuned table is keyed by power-of-two size buckets.  An entry naming
+    a kernel that needs K % 64 == 0 and N % 8 == 0 (the 256 x 256 pipelined
+    configuration) must not break a same-bucket shape without them: mfg_gemm
+    falls back to the default choice, bitwise equal to configuration 0."""
+    cfg = next(i for i in range(mfg.num_configs("f16")) if mfg.config_name("f16", i).startswith("q256x256"))
+    path = tmp_path / "tuned.txt"
+    path.write_text(f"{mfg.MFG_F16} 10 10 10 {cfg}\n")  # bucket of sizes 1024 .. 2047
+    assert mfg.lib().mfg_tune_load(str(path).encode()) == 0
+    assert mfg.lib().mfg_tune_lookup(1024, 1024, 1024, mfg.MFG_F16) == cfg
+    M, N, K = 1100, 1036, 1030  # same bucket; K % 64 != 0, N % 8 != 0
+    A, B = workloads.uniform(33, [(M, K), (K, N)])
+    sa = torch.zeros((M, 1032), dtype=torch.float16, device=DEV)
+    sb = torch.zeros((K, 1040), dtype=torch.float16, device=DEV)
+    sa[:, :K] = dev(A).half()
+    sb[:, :N] = dev(B).half()
+    dA, dB = sa[:, :K], sb[:, :N]
+    c = torch.zeros((M, N), dtype=torch.float32, device=DEV)
+    c0 = torch.zeros((M, N), dtype=torch.float32, device=DEV)
+    mfg.gemm(dA, dB, c, 1.0, 0.0, mode="f16", preconverted=True)
+    mfg.gemm(dA, dB, c0, 1.0, 0.0, mode="f16", preconverted=True, config=0)
+    assert np.array_equal(host(c).view(np.uint32), host(c0).view(np.uint32))
+    for mode, m32 in (("split3", mfg.MFG_F16_SPLIT3), ("f16", mfg.MFG_F16)):  # library-converted operands too
+        path.write_text(f"{m32} 10 10 10 {mfg.num_configs(mode) - 1}\n")
+        mfg.lib().mfg_tune_clear()
+        assert mfg.lib().mfg_tune_load(str(path).encode()) == 0
+        c = torch.zeros((M, N), dtype=torch.float32, device=DEV)
+        c0 = torch.zeros((M, N), dtype=torch.float32, device=DEV)
+        mfg.gemm(dev(A), dev(B), c, 1.0, 0.0, mode=mode)
+        mfg.gemm(dev(A), dev(B), c0, 1.0, 0.0, mode=mode, config=0)
+        assert np.array_equal(host(c).view(np.uint32), host(c0).view(np.uint32)), mode

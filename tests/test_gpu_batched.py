@@ -256,3 +256,25 @@ def test_grouped_fp32_input_equals_solo(mode):
         for i in range(0, len(probs), 5):
             assert np.array_equal(host(probs[i][2]).view(np.uint32), first[i].view(np.uint32)), f"replay {rep} {i}"
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["refine_a", "split3", "split4", "bf16_split3"])
+def test_batched_refined_preconverted_equals_fp32_input(mode):
+    """MFG_IN_PRECONVERTED on a refined batch: entry b's head plane at
+    A + b*strideA and its residual plane M*lda later (as mfg_convert writes
+    them) give the same bits as the batch from FP32 operands."""
+    count, M, N, K = 40, 48, 72, 60
+    A, B, C0 = workloads.normal(23, [(count, M, K), (count, K, N), (count, M, N)])
+    dC = dev(C0)
+    mfg.gemm_batched(dev(A), dev(B), dC, 1.25, -0.5, mode=mode)
+    ldk, ldn = 64, 72
+    two_b = mode != "refine_a"
+    pa = torch.zeros((count, 2 * M, ldk), dtype=torch.int16, device=DEV)
+    pb = torch.zeros((count, (2 if two_b else 1) * K, ldn), dtype=torch.int16, device=DEV)
+    for b in range(count):
+        mfg.convert(dev(A[b]), pa[b], ldk, mode)
+        mfg.convert(dev(B[b]), pb[b], ldn, mode if two_b else "f16")
+    dP = dev(C0)
+    mfg.gemm_batched(pa, pb, dP, 1.25, -0.5, mode=mode, preconverted=True, M=M, K=K)
+    assert np.array_equal(host(dP).view(np.uint32), host(dC).view(np.uint32))
+    assert_parity(host(dP)[7], oracle.reference(mode, A[7], B[7], 1.25, -0.5, C0[7]), f"{mode} entry 7")
