@@ -136,6 +136,28 @@ int mfg_gemm_config(int64_t M, int64_t N, int64_t K,
                     float* C, int64_t ldc,
                     float alpha, float beta, int mode, int config, void* stream);
 
+/* mfg_gemm_noalloc -- mfg_gemm for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and results (bitwise) as mfg_gemm.  The
+ * operands the call converts (the FP32 inputs of the 16-bit, refined and
+ * FP8 modes) go into a fixed per-device array of MFG_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every device it runs on until the process
+ * ends, instead of the per-stream workspace: the call makes no hipMalloc,
+ * hipFree or other allocating call.  A call whose converted operands need
+ * more than that (e.g. FP16 from FP32 beyond about M*K + K*N = 32 Mi
+ * elements, the two-plane modes beyond half that) returns
+ * MFG_ERR_UNSUPPORTED before anything is enqueued.  Every call on one device
+ * shares that device's array and leaves its contents behind: calls that
+ * overlap on one GPU (other streams, other threads) race, so the caller
+ * orders them.  The first call on a device looks up the array's address
+ * there (no allocation). */
+#define MFG_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int mfg_gemm_noalloc(int64_t M, int64_t N, int64_t K,
+                     const void* A, int64_t lda,
+                     const void* B, int64_t ldb,
+                     float* C, int64_t ldc,
+                     float alpha, float beta, int mode, void* stream);
+
 /* Number of tile configurations of a mode and a short text description of
  * one of them (written to `buf`, host, at most `n` bytes incl. the NUL). */
 int mfg_num_configs(int mode);

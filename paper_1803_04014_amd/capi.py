@@ -36,6 +36,7 @@ MFG_IN_FP32 = 0x200  # grouped plans: FP32 operands, converted on every run
 MFG_MODE_MASK = 0xFF
 MFG_RESID_SCALE_LOG2 = 11
 MFG_FP8_TILE = 128
+MFG_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 MODE_BY_NAME = {
     "f32": MFG_F32, "f16": MFG_F16, "bf16": MFG_BF16, "refine_a": MFG_F16_REFINE_A,
@@ -79,6 +80,7 @@ SIGNATURES = {
     "mfg_fp8_scale_offset": (i64, [i64, i64]),
     "mfg_gemm": (i32, [i64, i64, i64, vp, i64, vp, i64, vp, i64, f32, f32, i32, vp]),
     "mfg_gemm_config": (i32, [i64, i64, i64, vp, i64, vp, i64, vp, i64, f32, f32, i32, i32, vp]),
+    "mfg_gemm_noalloc": (i32, [i64, i64, i64, vp, i64, vp, i64, vp, i64, f32, f32, i32, vp]),
     "mfg_num_configs": (i32, [i32]),
     "mfg_config_name": (i32, [i32, i32, ctypes.c_char_p, i32]),
     "mfg_gemm_batched": (i32, [i64, i64, i64, i64, vp, i64, i64, vp, i64, i64, vp, i64, i64, f32, f32, i32, vp]),

@@ -55,8 +55,32 @@ static int choose16(int m, int config, int64_t M, int64_t N, int64_t K, int64_t 
     return pick_config16(kind_of(m), M, N, K, vec);
 }
 
+// The storage a call converts its operands into: the per-stream workspace
+// (grown with hipMalloc, held by a lease), or caller-provided device memory
+// of a fixed capacity (the allocation-free entry point).
+struct ExtWs {
+    void* ptr;
+    size_t cap;
+};
+struct CallWs {
+    std::unique_ptr<WsLease> lease;
+    void* ptr = nullptr;
+};
+static int call_ws(hipStream_t s, size_t bytes, const ExtWs* ext, CallWs& w) {
+    if (ext) {
+        if (bytes > ext->cap) return MFG_ERR_UNSUPPORTED;
+        w.ptr = ext->ptr;
+        return MFG_OK;
+    }
+    w.lease.reset(new WsLease(s, bytes));
+    if (!w.lease->ptr()) return w.lease->status();
+    w.ptr = w.lease->ptr();
+    return MFG_OK;
+}
+
 static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
-                     float* C, int64_t ldc, float alpha, float beta, int mode, int config, hipStream_t s) {
+                     float* C, int64_t ldc, float alpha, float beta, int mode, int config, hipStream_t s,
+                     const ExtWs* ext = nullptr) {
     int st = validate_gemm(M, N, K, A, lda, B, ldb, C, ldc, mode);
     if (st != MFG_OK) return st;
     const int m = mode & MFG_MODE_MASK;
@@ -99,9 +123,9 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
             if (cfg < 0 || cfg >= num_configs_f8()) return MFG_ERR_INVALID_ARG;
             if (!f8_config_needs_bt(cfg)) return launch_gemm_f8(cfg, a, vec, s);
             if (!vec || K % 128 != 0) return MFG_ERR_UNSUPPORTED;
-            WsLease ws(s, (size_t)bT);
-            if (!ws.ptr()) return ws.status();
-            uint8_t* bt = static_cast<uint8_t*>(ws.ptr());
+            CallWs ws;
+            if ((st = call_ws(s, (size_t)bT, ext, ws)) != MFG_OK) return st;
+            uint8_t* bt = static_cast<uint8_t*>(ws.ptr);
             if ((st = launch_transpose_b8(K, N, a.B, ldb, bt, ldt, s)) != MFG_OK) return st;
             a.Bt = bt, a.ldbt = ldt;
             return launch_gemm_f8(cfg, a, vec, s);
@@ -116,9 +140,9 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         // scales, the codes being quantised straight into the K-contiguous layout
         const int64_t bB = need_bt ? cdiv(K, MFG_FP8_TILE) * cdiv(N, MFG_FP8_TILE) * 4
                                    : mfg_convert_bytes(K, N, ldn, MFG_FP8_E4M3);
-        WsLease ws(s, (size_t)(up(bA, 256) + up(bB, 256) + (need_bt ? bT : 0)));
-        if (!ws.ptr()) return ws.status();
-        uint8_t* qa = static_cast<uint8_t*>(ws.ptr());
+        CallWs ws;
+        if ((st = call_ws(s, (size_t)(up(bA, 256) + up(bB, 256) + (need_bt ? bT : 0)), ext, ws)) != MFG_OK) return st;
+        uint8_t* qa = static_cast<uint8_t*>(ws.ptr);
         uint8_t* qb = qa + up(bA, 256);
         float* sa = reinterpret_cast<float*>(qa + mfg_fp8_scale_offset(M, ldk));
         float* sb = need_bt ? reinterpret_cast<float*>(qb) : reinterpret_cast<float*>(qb + mfg_fp8_scale_offset(K, ldn));
@@ -152,9 +176,9 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     const int64_t ldk = up(K, 8), ldn = up(N, 8);
     const int64_t pa_elems = M * ldk, pb_elems = K * ldn;
     const size_t bytes = (size_t)(npa(m) * up(pa_elems, 128) + npb(m) * up(pb_elems, 128)) * 2;
-    WsLease ws(s, bytes);
-    if (!ws.ptr()) return ws.status();
-    uint16_t* w = static_cast<uint16_t*>(ws.ptr());
+    CallWs ws;
+    if ((st = call_ws(s, bytes, ext, ws)) != MFG_OK) return st;
+    uint16_t* w = static_cast<uint16_t*>(ws.ptr);
     uint16_t* a0 = w;
     uint16_t* a1 = npa(m) == 2 ? a0 + up(pa_elems, 128) : nullptr;
     uint16_t* b0 = (a1 ? a1 : a0) + up(pa_elems, 128);
@@ -182,6 +206,27 @@ using namespace mfg;
 extern "C" int mfg_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
                         float* C, int64_t ldc, float alpha, float beta, int mode, void* stream) {
     MFG_GUARD(gemm_impl(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, mode, -1, (hipStream_t)stream));
+}
+
+// Scratch of the allocation-free entry point (noalloc.hip): this device's
+// copy of the array and its size.
+namespace mfg {
+int noalloc_scratch(void** ptr, size_t* bytes);
+}
+
+extern "C" int mfg_gemm_noalloc(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
+                                int64_t ldb, float* C, int64_t ldc, float alpha, float beta, int mode, void* stream) {
+    try {
+        int st = validate_gemm(M, N, K, A, lda, B, ldb, C, ldc, mode);
+        if (st != MFG_OK) return st;
+        ExtWs ext{nullptr, 0};
+        if ((st = noalloc_scratch(&ext.ptr, &ext.cap)) != MFG_OK) return st;
+        return gemm_impl(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, mode, -1, (hipStream_t)stream, &ext);
+    } catch (const std::bad_alloc&) {
+        return MFG_ERR_NO_MEMORY;
+    } catch (...) {
+        return MFG_ERR_INTERNAL;
+    }
 }
 
 extern "C" int mfg_gemm_config(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,

@@ -238,7 +238,7 @@ static int launch_split(int64_t rows, int64_t cols, const float* X, int64_t ldx,
     const int64_t nparts = (int64_t)grid.x * grid.y;
     if (norms != nullptr) {
         int st = MFG_OK;
-        part = static_cast<Red4*>(scratch(s, (size_t)nparts * sizeof(Red4) + 64, &st));
+        part = static_cast<Red4*>(partials_ws(s, (size_t)nparts * sizeof(Red4) + 64, &st));
         if (part == nullptr) return st;
     }
     if (rows > 0 && cols > 0) {
@@ -537,7 +537,7 @@ int launch_error_norms(int64_t M, int64_t N, const float* C, int64_t ldc, const 
                        double* out4, hipStream_t s) {
     const int64_t G = (M == 0 || N == 0) ? 0 : (M < 2048 ? M : 2048);
     int st = MFG_OK;
-    Red4* part = static_cast<Red4*>(scratch(s, (size_t)(G + 1) * sizeof(Red4), &st));
+    Red4* part = static_cast<Red4*>(partials_ws(s, (size_t)(G + 1) * sizeof(Red4), &st));
     if (part == nullptr) return st;
     if (G > 0) {
         const int vec = aligned(C, ldc, 16, 4) && aligned(R, ldr, 16, 2);

@@ -31,7 +31,7 @@ int hip_fail(hipError_t e);
 // stream before freeing the old region.
 void* workspace(hipStream_t s, size_t bytes, int* status);
 // A second, independent per-stream region for reduction partials.
-void* scratch(hipStream_t s, size_t bytes, int* status);
+void* partials_ws(hipStream_t s, size_t bytes, int* status);
 // Number of compute units of the current device (cached).
 int device_cu_count();
 

@@ -93,7 +93,7 @@ void* workspace(hipStream_t s, size_t bytes, int* status) {
     return grow(r, s, bytes, status);
 }
 
-void* scratch(hipStream_t s, size_t bytes, int* status) {
+void* partials_ws(hipStream_t s, size_t bytes, int* status) {
     Region* r = region_for(1, s, nullptr);
     std::lock_guard<std::mutex> g(r->mu);
     return grow(r, s, bytes, status);
