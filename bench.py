@@ -164,6 +164,45 @@ def pmc_summarize(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_byt
     return 0
 
 
+XCDS = 8            # GRBM_GUI_ACTIVE is summed over the XCDs' graphics blocks
+SIMDS = 1024        # 256 CUs x 4 SIMDs
+MFMA_CYCLES = {"v_mfma_f32_32x32x16": 32}   # SQ_VALU_MFMA_BUSY_CYCLES per instruction (measured: 2^30 / 2^25)
+
+
+def mfma_summary(d: str, name_part: str) -> int:
+    """Markdown rows of MFMA utilisation per dispatch of the kernels whose name
+    contains name_part, from one rocprofv3 --pmc run with --kernel-trace:
+    SQ_VALU_MFMA_BUSY_CYCLES (summed over the 1024 SIMDs), GRBM_GUI_ACTIVE
+    (summed over the 8 XCDs, in shader-clock cycles) and the dispatch's time.
+    clock = GUI_ACTIVE / 8 / time; utilisation = busy / (GUI_ACTIVE / 8 * 1024)
+    (rocprofv3's MfmaUtil uses the largest XCD's GUI_ACTIVE instead of the mean);
+    MOPS counters (per 512 flops) give the matrix flops and the rate."""
+    import collections
+
+    per = collections.defaultdict(dict)
+    for r in _csv_rows(d, "counter_collection.csv"):
+        if name_part not in r["Kernel_Name"]:
+            continue
+        k = int(r["Dispatch_Id"])
+        per[k][r["Counter_Name"]] = float(r["Counter_Value"])
+        per[k]["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        per[k]["name"] = r["Kernel_Name"].split("(")[0]
+    if not per:
+        raise SystemExit(f"no dispatches of kernels matching {name_part!r} under {d}")
+    print("| dispatch | kernel | time us | MFMA busy cycles | GUI_ACTIVE / 8 | clock GHz | MFMA util | matrix TFLOP/s |")
+    print("|---|---|---|---|---|---|---|---|")
+    for k, v in sorted(per.items()):
+        gui = v.get("GRBM_GUI_ACTIVE", 0.0) / XCDS
+        busy = v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        mops = sum(x for c, x in v.items() if c.startswith("SQ_INSTS_VALU_MFMA_MOPS"))
+        clk = gui / v["ns"] if gui else 0.0
+        util = busy / (gui * SIMDS) if gui else 0.0
+        tf = mops * 512 / v["ns"] / 1e3 if mops else 0.0
+        print(f"| {k} | `{v['name']}` | {v['ns'] / 1e3:.1f} | {busy:.4g} | {gui:.4g} | {clk:.3f} | {util:.3f} | "
+              f"{tf:.1f} |")
+    return 0
+
+
 def copy_probe(nbytes: int) -> int:
     """A plain device copy of nbytes, three times: the calibration kernel for
     the FETCH_SIZE / WRITE_SIZE counters."""
@@ -330,6 +369,8 @@ def main() -> int:
     ap.add_argument("--grouped-only", action="store_true", help="only the grouped-plan legs (one JSON line)")
     ap.add_argument("--kernel-only", metavar="MODE", help="only time MODE's GEMM at N^3 on preconverted operands")
     ap.add_argument("--mfma-ceiling", action="store_true", help="only the register-only MFMA ceiling probe")
+    ap.add_argument("--mfma-summary", nargs=2, metavar=("DIR", "KERNEL"),
+                    help="only print MFMA utilisation per dispatch from a rocprofv3 --pmc output folder")
     args = ap.parse_args()
     if args.copy_probe:
         return copy_probe(args.copy_probe)
@@ -339,6 +380,8 @@ def main() -> int:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build is single-GPU)",
               file=sys.stderr)
         return 2
+    if args.mfma_summary:
+        return mfma_summary(*args.mfma_summary)
     if args.kernel_only:
         return kernel_only(args.kernel_only, args.n, args.steps, args.warmup)
     if args.mfma_ceiling:

@@ -170,7 +170,8 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         a.A[0] = pa, a.A[1] = npa(m) == 2 ? pa + M * lda : nullptr;
         a.B[0] = pb, a.B[1] = npb(m) == 2 ? pb + K * ldb : nullptr;
         a.lda = lda, a.ldb = ldb;
-        const bool vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && buffer_ldc_ok(ldc);
+        const bool vec =
+            al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && buffer_ldc_ok(ldc) && operand_ld_ok(lda, ldb);
         return launch_gemm16(kind, choose16(m, config, M, N, K, ldc, vec), a, 1, vec, s);
     }
     const int64_t ldk = up(K, 8), ldn = up(N, 8);
@@ -186,7 +187,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     if ((st = convert16(m, M, K, static_cast<const float*>(A), lda, a0, a1, ldk, npa(m) == 2, s)) != MFG_OK) return st;
     if ((st = convert16(m, K, N, static_cast<const float*>(B), ldb, b0, b1, ldn, npb(m) == 2, s)) != MFG_OK) return st;
     a.A[0] = a0, a.A[1] = a1, a.B[0] = b0, a.B[1] = b1, a.lda = ldk, a.ldb = ldn;
-    const bool vec = buffer_ldc_ok(ldc);  // workspace planes: aligned, ld a multiple of 8
+    const bool vec = buffer_ldc_ok(ldc) && operand_ld_ok(ldk, ldn);  // workspace planes: aligned, ld a multiple of 8
     return launch_gemm16(kind, choose16(m, config, M, N, K, ldc, vec), a, 1, vec, s);
 }
 
@@ -318,12 +319,12 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
         a.B[0] = pb, a.B[1] = two_planes_b(m) ? pb + K * ldb : nullptr;
         a.lda = lda, a.ldb = ldb, a.sA = strideA, a.sB = strideB;
         vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && strideA % 8 == 0 && strideB % 8 == 0 &&
-              buffer_ldc_ok(ldc);
+              buffer_ldc_ok(ldc) && operand_ld_ok(lda, ldb);
     } else if (!split_mode) {
         a.A[0] = static_cast<const uint16_t*>(A), a.B[0] = static_cast<const uint16_t*>(B);
         a.lda = lda, a.ldb = ldb, a.sA = strideA, a.sB = strideB;
         vec = al16(A) && al16(B) && lda % 8 == 0 && ldb % 8 == 0 && strideA % 8 == 0 && strideB % 8 == 0 &&
-              buffer_ldc_ok(ldc);
+              buffer_ldc_ok(ldc) && operand_ld_ok(lda, ldb);
     } else {
         // FP32 operands split into the workspace, packed per batch entry.
         const int64_t ldk = up(K, 8), ldn = up(N, 8);
@@ -357,7 +358,7 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
         }
         a.A[0] = a0, a.A[1] = a1, a.B[0] = b0, a.B[1] = b1;
         a.lda = ldk, a.ldb = ldn, a.sA = pa, a.sB = pb;
-        vec = buffer_ldc_ok(ldc);
+        vec = buffer_ldc_ok(ldc) && operand_ld_ok(ldk, ldn);
     }
     if (M <= 32 && N <= 32) return launch_batched_small(kind, a, count, vec, device_cu_count(), s);
     const int cfg = vec ? pick_config16(kind, M, N, K, vec) : 0;

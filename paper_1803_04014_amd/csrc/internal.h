@@ -158,6 +158,12 @@ struct GroupedDesc {  // one problem (host side; the kernel reads GroupedWork)
 // kernels (single 32 x 32 blocks, 64-bit addressing).
 constexpr int64_t kBufferLdcLimit = int64_t(1) << 24;
 inline bool buffer_ldc_ok(int64_t ldc) { return ldc < kBufferLdcLimit; }
+// The 64-wide pipelined kernels address a tile's operand rows with 32-bit
+// byte offsets from its corner (at most 256 rows of A, 64 of B): lda and
+// ldb must stay below this bound for the tiled 16-bit kernels; larger ones
+// use the simple kernels.
+constexpr int64_t kOperandLdLimit = int64_t(1) << 22;
+inline bool operand_ld_ok(int64_t lda, int64_t ldb) { return lda < kOperandLdLimit && ldb < kOperandLdLimit; }
 
 constexpr int kGroupedTile = 128;        // output tile of a grouped work item (one workgroup): F16, BF16
 constexpr int kGroupedTileRefined = 64;  // REFINE_A, SPLIT3, SPLIT4 (two operand planes in LDS)

@@ -372,6 +372,71 @@ __device__ __forceinline__ void pipe64_load(const uint16_t* const (&Ap)[2], cons
     }
 }
 
+// The same loads with their addressing split into a per-lane part fixed for
+// the whole K loop and a per-stage part that is the same in every lane.  Each
+// lane's byte offset from the tile's corner (A: row m0, column 0 of the stage;
+// B: row 0 of the stage, column n0), with the row clamps and the swizzled
+// chunk of pipe64_load, is computed once (32 bits: the caller guarantees
+// BM * lda and BK * ldb below 2^30 elements); a stage adds its K offset to
+// the corner in scalar registers, and the LDS destinations come from the
+// wavefront index made visibly uniform, so a load costs one address add
+// instead of a 64-bit multiply per lane.  Same sources, same LDS layout and
+// the same instruction order as pipe64_load.
+template <int KIND, int BM, int BN, int WM, int WN, int S>
+struct P64Loader {
+    using G = Pipe64Cfg<KIND, BM, BN, WM, WN, S>;
+    const char* a[2];  // tile corner of each A plane, row m0 (same in every lane)
+    const char* b[2];  // of each B plane, column n0
+    int64_t ldb2;      // B row pitch in bytes
+    int wid;           // this wavefront's index (scalar)
+    uint32_t offa[G::A_INSTR];
+    uint32_t offb[G::B_INSTR];
+
+    __device__ __forceinline__ void init(const uint16_t* const (&Ap)[2], const uint16_t* const (&Bp)[2], int64_t lda,
+                                         int64_t ldb, int64_t M, int64_t N, int64_t m0, int64_t n0, int wid_, int lane) {
+        wid = __builtin_amdgcn_readfirstlane(wid_);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            a[q] = (const char*)uniform64((int64_t)(Ap[q] ? Ap[q] + m0 * lda : nullptr));
+            b[q] = (const char*)uniform64((int64_t)(Bp[q] ? Bp[q] + n0 : nullptr));
+        }
+        ldb2 = uniform64(ldb * 2);
+#pragma unroll
+        for (int i = 0; i < G::A_INSTR; ++i) {
+            const int row = (wid * G::A_INSTR + i) * 8 + (lane >> 3);
+            const int c = (lane & 7) ^ swz<8>(row);
+            const int64_t gm = m0 + row < M ? m0 + row : M - 1;
+            offa[i] = (uint32_t)(((gm - m0) * lda + c * 8) * 2);
+        }
+#pragma unroll
+        for (int i = 0; i < G::B_INSTR; ++i) {
+            const int krow = (wid * G::B_INSTR + i) * G::B_ROWS_PER_INSTR + lane / G::B_CPR;
+            const int c = (lane % G::B_CPR) ^ swzB(krow);
+            const int64_t gn = n0 + c * 8 + 8 <= N ? n0 + c * 8 : N - 8;
+            offb[i] = (uint32_t)((krow * ldb + (gn - n0)) * 2);
+        }
+    }
+
+    // The loads of the stage starting at column (A) / row (B) k0 into `st`.
+    __device__ __forceinline__ void load(int64_t k0, uint16_t* st) const {
+        const int64_t ka = uniform64(k0 * 2), kb = uniform64(k0 * ldb2);
+#pragma unroll
+        for (int q = 0; q < G::NPA; ++q)
+#pragma unroll
+            for (int i = 0; i < G::A_INSTR; ++i)
+                __builtin_amdgcn_global_load_lds((const void*)(a[q] + ka + offa[i]),
+                                                 (lds_void*)(st + q * G::A_PLANE + (wid * G::A_INSTR + i) * 512), 16,
+                                                 0, 0);
+#pragma unroll
+        for (int q = 0; q < G::NPB; ++q)
+#pragma unroll
+            for (int i = 0; i < G::B_INSTR; ++i)
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)(b[q] + kb + offb[i]),
+                    (lds_void*)(st + G::NPA * G::A_PLANE + q * G::B_PLANE + (wid * G::B_INSTR + i) * 512), 16, 0, 0);
+    }
+};
+
 // Operand fragments of one fragment step: KK 16-deep chunks.
 template <int FM, int FN, int KK>
 struct P64Frags {
@@ -436,7 +501,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe64(Gemm16Args p, int 
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
-    const int64_t KTN = K / BK;  // >= 1
+    const int64_t KTN = uniform64(K / BK);  // >= 1
     auto kclamp = [&](int64_t t) { return (t < KTN ? t : KTN - 1) * BK; };
     auto stage = [&](int s) -> uint16_t* { return s == 0 ? st0 : s == 1 ? st1 : st2; };
 
@@ -450,10 +515,12 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe64(Gemm16Args p, int 
             if constexpr (T::RR) rr[i][j] = f32x16{};
         }
 
+    P64Loader<KIND, BM, BN, WM, WN, S> ld;
+    ld.init(Ap, Bp, lda, ldb, M, N, m0, n0, wid, lane);
+
     // prologue: stages 0 .. S-1 in flight; wait for stage 0, read its first fragments
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-        pipe64_load<KIND, BM, BN, WM, WN, S>(Ap, Bp, lda, ldb, M, N, m0, n0, kclamp(s), stage(s), wid, lane);
+    for (int s = 0; s < S; ++s) ld.load(kclamp(s), stage(s));
     F f[2];
     wait_vmcnt<G::LOADS * (S - 1)>();
     bare_barrier();
@@ -482,8 +549,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm16_pipe64(Gemm16Args p, int 
                 wait_vmcnt<G::LOADS * (S - 2)>();
                 wait_lgkm0();
                 bare_barrier();
-                pipe64_load<KIND, BM, BN, WM, WN, S>(Ap, Bp, lda, ldb, M, N, m0, n0, kclamp(t + S), stage(u), wid,
-                                                     lane);
+                ld.load(kclamp(t + S), stage(u));
                 pipe64_read<KIND, BM, BN, WM, WN, S, KK>(stage((u + 1) % S), 0, wm, wn, lane, f[(h + 1) & 1]);
                 mma(f[h & 1]);
                 if constexpr (EVEN) pipe_interleave_loads_even<G::READS, G::LOADS, G::MFMAS>();
