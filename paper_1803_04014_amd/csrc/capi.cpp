@@ -118,7 +118,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
             a.B = static_cast<const uint8_t*>(B), a.ldb = ldb;
             a.sa = reinterpret_cast<const float*>(a.A + mfg_fp8_scale_offset(M, lda));
             a.sb = reinterpret_cast<const float*>(a.B + mfg_fp8_scale_offset(K, ldb));
-            const bool vec = al16(A) && lda % 16 == 0 && buffer_ldc_ok(ldc);
+            const bool vec = al16(A) && lda % 16 == 0 && buffer_ldc_ok(ldc) && lda < kF8LdLimit && ldt < kF8LdLimit;
             const int cfg = choose(vec);
             if (cfg < 0 || cfg >= num_configs_f8()) return MFG_ERR_INVALID_ARG;
             if (!f8_config_needs_bt(cfg)) return launch_gemm_f8(cfg, a, vec, s);
@@ -130,7 +130,8 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
             a.Bt = bt, a.ldbt = ldt;
             return launch_gemm_f8(cfg, a, vec, s);
         }
-        const int cfg = choose(buffer_ldc_ok(ldc));
+        const bool vec8 = buffer_ldc_ok(ldc) && up(K, 16) < kF8LdLimit;  // workspace codes: ld = K rounded up
+        const int cfg = choose(vec8);
         if (cfg < 0 || cfg >= num_configs_f8()) return MFG_ERR_INVALID_ARG;
         const bool need_bt = f8_config_needs_bt(cfg);
         if (need_bt && K % 128 != 0) return MFG_ERR_UNSUPPORTED;
@@ -157,7 +158,7 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
             if ((st = launch_quantize_fp8(K, N, static_cast<const float*>(B), ldb, qb, ldn, sb, s)) != MFG_OK) return st;
             a.B = qb;
         }
-        return launch_gemm_f8(cfg, a, buffer_ldc_ok(ldc), s);
+        return launch_gemm_f8(cfg, a, vec8, s);
     }
 
     // 16-bit modes

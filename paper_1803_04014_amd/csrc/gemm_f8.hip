@@ -114,6 +114,53 @@ __device__ __forceinline__ void f8_load(const uint8_t* A, const uint8_t* Bt, int
     }
 }
 
+// f8_load with the addressing of P64Loader: each lane's byte offset from the
+// tile's corner (A row m0, Bt row n0) fixed for the K loop, the stage's K
+// offset and the LDS destinations in scalar registers.  Same sources, LDS
+// layout and instruction order as f8_load.
+template <int BM, int BN, int WM, int WN, int S>
+struct F8Loader {
+    using G = F8Cfg<BM, BN, WM, WN, S>;
+    const uint8_t* a;
+    const uint8_t* b;
+    int wid;
+    uint32_t offa[G::A_INSTR], offb[G::B_INSTR];
+
+    __device__ __forceinline__ void init(const uint8_t* A, const uint8_t* Bt, int64_t lda, int64_t ldbt, int64_t M,
+                                         int64_t N, int64_t m0, int64_t n0, int wid_, int lane) {
+        wid = __builtin_amdgcn_readfirstlane(wid_);
+        a = (const uint8_t*)uniform64((int64_t)(A + m0 * lda));
+        b = (const uint8_t*)uniform64((int64_t)(Bt + n0 * ldbt));
+        const int rr = lane >> 3;
+#pragma unroll
+        for (int i = 0; i < G::A_INSTR; ++i) {
+            const int row = (wid * G::A_INSTR + i) * 8 + rr;
+            const int c = (lane & 7) ^ swz<8>(row);
+            const int64_t gm = m0 + row < M ? m0 + row : M - 1;
+            offa[i] = (uint32_t)((gm - m0) * lda + c * 16);
+        }
+#pragma unroll
+        for (int i = 0; i < G::B_INSTR; ++i) {
+            const int row = (wid * G::B_INSTR + i) * 8 + rr;
+            const int c = (lane & 7) ^ swz<8>(row);
+            const int64_t gn = n0 + row < N ? n0 + row : N - 1;
+            offb[i] = (uint32_t)((gn - n0) * ldbt + c * 16);
+        }
+    }
+
+    __device__ __forceinline__ void load(int64_t k0, uint8_t* st) const {
+        const int64_t k = uniform64(k0);
+#pragma unroll
+        for (int i = 0; i < G::A_INSTR; ++i)
+            __builtin_amdgcn_global_load_lds((const void*)(a + k + offa[i]),
+                                             (lds_void*)(st + (wid * G::A_INSTR + i) * 1024), 16, 0, 0);
+#pragma unroll
+        for (int i = 0; i < G::B_INSTR; ++i)
+            __builtin_amdgcn_global_load_lds((const void*)(b + k + offb[i]),
+                                             (lds_void*)(st + G::A_PLANE + (wid * G::B_INSTR + i) * 1024), 16, 0, 0);
+    }
+};
+
 template <int FM, int FN>
 struct F8Frags {
     i32x8 a[FM];
@@ -154,7 +201,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
-    const int64_t KTN = K / BK;  // >= 1
+    const int64_t KTN = uniform64(K / BK);  // >= 1
     auto kclamp = [&](int64_t t) { return (t < KTN ? t : KTN - 1) * BK; };
     auto stage = [&](int s) -> uint8_t* { return s == 0 ? st0 : s == 1 ? st1 : st2; };
     // this wave's scale tiles (rows clamped like the operand rows)
@@ -176,9 +223,10 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
 
+    F8Loader<BM, BN, WM, WN, S> ld;
+    ld.init(p.A, p.Bt, p.lda, p.ldbt, M, N, m0, n0, wid, lane);
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-        f8_load<BM, BN, WM, WN, S>(p.A, p.Bt, p.lda, p.ldbt, M, N, m0, n0, kclamp(s), stage(s), wid, lane);
+    for (int s = 0; s < S; ++s) ld.load(kclamp(s), stage(s));
     int ca, cb, na, nb;
     scale_codes(0, ca, cb);
     F f[2];
@@ -203,7 +251,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
         wait_vmcnt<G::LOADS * (S - 2)>();
         wait_lgkm0();
         bare_barrier();
-        f8_load<BM, BN, WM, WN, S>(p.A, p.Bt, p.lda, p.ldbt, M, N, m0, n0, kclamp(t + S), stage(u), wid, lane);
+        ld.load(kclamp(t + S), stage(u));
         f8_read<BM, BN, WM, WN, S>(stage((u + 1) % S), 0, wm, wn, lane, f[0]);
         mma(f[1], ca, cb);
         if constexpr (EVEN) pipe_interleave_even<G::READS, G::MFMAS>();

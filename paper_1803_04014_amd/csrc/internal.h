@@ -164,6 +164,9 @@ inline bool buffer_ldc_ok(int64_t ldc) { return ldc < kBufferLdcLimit; }
 // use the simple kernels.
 constexpr int64_t kOperandLdLimit = int64_t(1) << 22;
 inline bool operand_ld_ok(int64_t lda, int64_t ldb) { return lda < kOperandLdLimit && ldb < kOperandLdLimit; }
+// Likewise for the FP8 tiled kernel's code rows (A and transposed B, bytes;
+// up to 256 rows per tile).
+constexpr int64_t kF8LdLimit = int64_t(1) << 24;
 
 constexpr int kGroupedTile = 128;        // output tile of a grouped work item (one workgroup): F16, BF16
 constexpr int kGroupedTileRefined = 64;  // REFINE_A, SPLIT3, SPLIT4 (two operand planes in LDS)
