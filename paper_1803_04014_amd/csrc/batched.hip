@@ -220,7 +220,6 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
 // operands and order of the simple kernel on that tile.
 constexpr int kGroupedBK = 64;  // K per block: 128-byte A and B rows
 // 16 zero bytes in device memory: the load source of lanes with nothing to load
-__device__ __attribute__((aligned(16))) const uint16_t kZero16[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 typedef __attribute__((address_space(1))) const uint16_t g_u16;
 typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
 typedef __attribute__((address_space(1))) const uint32_t g_u32;
@@ -316,9 +315,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
     // 16 bytes as its first element, inside the row's ld extent (and never
     // across a page).  A's elements at or beyond K are then zeroed in
     // registers; B's columns at or beyond the tile's width only reach
-    // discarded outputs, and B rows at or beyond K, like A rows beyond the
-    // tile, read 16 zero bytes.  So every block issues the same loads and no
-    // branch.  Unaligned items load element by element.
+    // discarded outputs.  Pieces wholly outside the item (A rows beyond the
+    // tile, B rows or A columns at or beyond K, B columns beyond the tile)
+    // are zero in registers and issue no memory request: their lanes sit out
+    // the load, so a small item costs requests for its own data only.
+    // Unaligned items load element by element.
     // Residual planes sit at element offsets pa (A) and pb (B) from the head
     // planes of the item being loaded (refined kinds; read with the item).
     int64_t pa = 0, pb = 0;
@@ -330,8 +331,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
                 const bool fa = row < t.rows && ka < t.K;
                 const int64_t o = row * t.lda + ka;
 #pragma unroll
-                for (int q = 0; q < NA; ++q)
-                    a[q][j] = *(const g_u32x4*)(fa ? t.A + (q ? pa : 0) + o : (const g_u16*)kZero16);
+                for (int q = 0; q < NA; ++q)  // pieces outside the item issue no request
+                    a[q][j] = fa ? *(const g_u32x4*)(t.A + (q ? pa : 0) + o) : zero4();
                 nv[j] = t.K - ka;  // valid elements of the A piece (masked when it is stored)
             }
 #pragma unroll
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
                 const int64_t o = kr * t.ldb + cb;
 #pragma unroll
                 for (int q = 0; q < NB; ++q)
-                    b[q][j] = *(const g_u32x4*)(fb ? t.B + (q ? pb : 0) + o : (const g_u16*)kZero16);
+                    b[q][j] = fb ? *(const g_u32x4*)(t.B + (q ? pb : 0) + o) : zero4();
             }
         } else {
 #pragma unroll
@@ -481,6 +482,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm) {
                 const int r0 = wm * TH + fm * 32;
+                if (r0 >= cur.rows || wn * TH >= cur.cols) continue;  // this wavefront's blocks lie outside C
                 g_f32* cq = cur.C + (int64_t)r0 * cur.ldc + wn * TH;
                 auto val = [&](int fn, int e) { return combine_at<KIND>(hi[fm][fn], lo[fm][fn], rr[fm][fn], e); };
                 // the VEC list holds only ldc < kBufferLdcLimit: no 64-bit path
