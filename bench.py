@@ -203,6 +203,37 @@ def mfma_summary(d: str, name_part: str) -> int:
     return 0
 
 
+def trace_overlap(d: str, name_part: str = "mfg::") -> int:
+    """From a rocprofv3 --kernel-trace output folder: how the kernels whose name
+    contains name_part overlapped in time across HIP streams -- kernels per
+    stream, the largest number running at once, and the share of the busy
+    time with kernels of two or more streams on the device."""
+    rows = [r for r in _csv_rows(d, "kernel_trace.csv") if name_part in r["Kernel_Name"]]
+    if not rows:
+        raise SystemExit(f"no kernels matching {name_part!r} under {d}")
+    ev, per_stream = [], {}
+    for r in rows:
+        s, e, q = int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r.get("Stream_Id") or r.get("Queue_Id")
+        per_stream[q] = per_stream.get(q, 0) + 1
+        ev += [(s, 1, q), (e, -1, q)]
+    ev.sort()
+    active, by_q, most, busy, multi, last = 0, {}, 0, 0, 0, ev[0][0]
+    for t, dlt, q in ev:
+        span = t - last
+        if active > 0:
+            busy += span
+        if sum(1 for v in by_q.values() if v > 0) >= 2:
+            multi += span
+        last = t
+        active += dlt
+        by_q[q] = by_q.get(q, 0) + dlt
+        most = max(most, active)
+    out = {"kernels": len(rows), "kernels_per_stream": per_stream, "max_concurrent_kernels": most,
+           "busy_ms": round(busy / 1e6, 3), "share_of_busy_time_with_two_or_more_streams": round(multi / max(busy, 1), 3)}
+    print(json.dumps(out))
+    return 0
+
+
 def copy_probe(nbytes: int) -> int:
     """A plain device copy of nbytes, three times: the calibration kernel for
     the FETCH_SIZE / WRITE_SIZE counters."""
@@ -285,34 +316,40 @@ def mfma_ceiling(dev, iters: int = 2048, workgroups_per_cu: int = 2) -> dict:
     return res
 
 
-def served_errors(trace, views, per_mode: int = 3, max_flops: float = 2 * 512.0 ** 3):
+def served_errors(trace, views, per_mode: int = 3, rows: int = 16):
     """Part of the CPU oracle leg: max relative error vs FP64 of a few served
-    requests per mode (the oracle computes their exact products)."""
+    requests per mode, the first `per_mode` of each mode whatever their size,
+    on `rows` sampled rows of each (the oracle computes their exact products)."""
     import numpy as np
 
     import oracle
 
     errs = {}
     for mode in sorted({r["mode"] for r in trace}):
-        picked = [i for i, r in enumerate(trace) if r["mode"] == mode and 2.0 * r["M"] * r["N"] * r["K"] <= max_flops]
-        worst = 0.0
-        for i in picked[:per_mode]:
+        picked = [i for i, r in enumerate(trace) if r["mode"] == mode][:per_mode]
+        worst, shapes = 0.0, []
+        for i in picked:
             a, b, c = views[i]
+            M = a.shape[0]
+            rsel = oracle.sample_rows(M, n=rows, seed=i)
             A = a.cpu().numpy()
             B = b.cpu().numpy()
-            ref = oracle.exact(A, B, 1.0, 0.0, None)
-            err = np.max(np.abs(c.cpu().numpy().astype(np.float64) - ref)) / max(np.max(np.abs(ref)), 1e-300)
+            ref = oracle.exact(A, B, 1.0, 0.0, None, rows=rsel)
+            got = c.cpu().numpy().astype(np.float64)[rsel]
+            err = np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)
             worst = max(worst, float(err))
-        errs[mode] = {"max_rel": worst, "sampled": min(per_mode, len(picked))}
+            shapes.append(f"{M}x{b.shape[1]}x{a.shape[1]}")
+        errs[mode] = {"max_rel": worst, "sampled": shapes, "rows_per_request": rows}
     return errs
 
 
-def serving_leg(rate: float, seconds: float, seed: int, pools, budget: float = 200e9, slots: int = 4,
-                max_group: int = 16):
+def serving_leg(rate: float, seconds: float, max_requests: int, seed: int, pools, budget: float = 200e9,
+                slots: int = 4, max_group: int = 16):
     """Replay a Poisson trace of GEMM requests (M, N, K log-uniform in [32, 4096],
     modes F16 / BF16 / SPLIT3 / FP8, operands sub-blocks of resident 4096 x 4096
-    FP32 pools, a distinct C per request, alpha = 1, beta = 0) into mfg_server.
-    Latency = completion observed - submit, per request."""
+    FP32 pools, a distinct C per request, alpha = 1, beta = 0) into mfg_server:
+    min(max_requests, rate * seconds) requests.  Latency = completion observed -
+    submit, per request."""
     import numpy as np
     import torch
 
@@ -320,7 +357,7 @@ def serving_leg(rate: float, seconds: float, seed: int, pools, budget: float = 2
     import workloads
 
     dA, dB = pools
-    n = max(1, int(rate * seconds))
+    n = max(1, min(max_requests, int(rate * seconds)))
     trace = workloads.serving_trace(seed, rate, n)
     sizes = [r["M"] * r["N"] for r in trace]
     arena = torch.empty(int(sum(sizes)), dtype=torch.float32, device=dA.device)
@@ -339,18 +376,226 @@ def serving_leg(rate: float, seconds: float, seed: int, pools, budget: float = 2
             pass
         tickets.append(server.submit(a, b, c, r["mode"], 1.0, 0.0))
     server.drain()
-    res = [server.poll(t)[1] for t in tickets]
+    polled = [server.poll(t) for t in tickets]
     stats = server.stats()
     server.close()
+    res = [x[1] for x in polled]
     lat = np.array([(x["t_end_ns"] - x["t_submit_ns"]) * 1e-6 for x in res])
+    wait = np.array([(x["t_start_ns"] - x["t_submit_ns"]) * 1e-6 for x in res])  # queued until launched
+    big = np.array([x["flops"] for x in res])
     span = (max(x["t_end_ns"] for x in res) - min(x["t_submit_ns"] for x in res)) * 1e-9
     flops = sum(x["flops"] for x in res)
+    tail = lat >= np.percentile(lat, 99)
     out = {"rate_per_s": rate, "requests": n, "p50_ms": round(float(np.percentile(lat, 50)), 3),
            "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
-           "useful_tflops": round(flops / span / 1e12, 2), "launches": stats["launches"],
-           "mean_group": round(float(np.mean([x["group_size"] for x in res])), 2),
-           "failed": stats["failed"], "peak_converted_gb": round(stats["peak_bytes_in_use"] / 1e9, 3)}
+           "p50_wait_ms": round(float(np.percentile(wait, 50)), 3),
+           "p99_wait_ms": round(float(np.percentile(wait, 99)), 3),
+           "slowest_1pct_mean_gflop": round(float(big[tail].mean()) / 1e9, 2),
+           "useful_tflops": round(flops / span / 1e12, 2), "offered_tflops": round(flops / trace[-1]["t"] / 1e12, 2),
+           "launches": stats["launches"], "mean_group": round(float(np.mean([x["group_size"] for x in res])), 2),
+           "max_concurrent_slots": stats["max_concurrent_slots"], "slots": slots,
+           "failed": stats["failed"] + sum(1 for st, _ in polled if st != 0),
+           "peak_converted_gb": round(stats["peak_bytes_in_use"] / 1e9, 3)}
     return out, trace, views
+
+
+def rate_stats(flops: float, ms: list) -> dict:
+    """Per-launch rates of `flops` over launch times `ms`: the harmonic mean
+    (flops over the mean time, the paper's convention), median, p10 and p90."""
+    import numpy as np
+
+    t = np.asarray(ms, dtype=np.float64)
+    r = flops / (t * 1e-3) / 1e12
+    return {"tflops_hmean": round(flops / (t.mean() * 1e-3) / 1e12, 2), "tflops_median": round(float(np.median(r)), 2),
+            "tflops_p10": round(float(np.percentile(r, 10)), 2), "tflops_p90": round(float(np.percentile(r, 90)), 2),
+            "launches": int(t.size)}
+
+
+def launch_times(fn, reps: int, warm: int = 2) -> list:
+    """Per-launch milliseconds of fn() (HIP events around each launch on the current stream)."""
+    import torch
+
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def smi_sample():
+    """One amd-smi reading of the graphics clocks (MHz, per XCD) and socket power (W), or None."""
+    import subprocess
+
+    try:
+        out = subprocess.run(["amd-smi", "metric", "-g", "0", "-c", "-p", "--json"], capture_output=True, text=True,
+                             timeout=10).stdout
+        d = json.loads(out)
+        g = d["gpu_data"][0] if isinstance(d, dict) and "gpu_data" in d else (d[0] if isinstance(d, list) else d)
+        clk = [v["clk"]["value"] for k, v in g["clock"].items()
+               if k.startswith("gfx_") and isinstance(v, dict) and isinstance(v.get("clk"), dict)]
+        pw = g["power"]["socket_power"]["value"]
+        return {"sclk_mhz": [float(c) for c in clk], "power_w": float(pw)}
+    except Exception:
+        return None
+
+
+def sustained_clock(step, flops: float, seconds: float) -> dict:
+    """Run `step` back to back for `seconds` while another thread samples the
+    graphics clocks and socket power: the clock the headline kernel runs at
+    under a sustained load (the dense peak assumes 2.4 GHz)."""
+    import threading
+
+    import torch
+
+    samples, stop = [], [False]
+
+    def sampler():
+        while not stop[0]:
+            x = smi_sample()
+            if x is None:
+                return
+            samples.append(x)
+            time.sleep(0.05)
+
+    th = threading.Thread(target=sampler, daemon=True)
+    for _ in range(20):
+        step()
+    torch.cuda.synchronize()
+    th.start()
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            step()
+        torch.cuda.synchronize()
+        k += 20
+    el = time.perf_counter() - t0
+    stop[0] = True
+    th.join(timeout=15)
+    out = {"seconds": round(el, 2), "launches": k, "tflops": round(flops * k / el / 1e12, 1)}
+    mid = samples[len(samples) // 4:] if len(samples) >= 4 else samples
+    if mid:
+        clks = [c for s_ in mid for c in s_["sclk_mhz"]]
+        out.update({"sclk_mhz_mean": round(sum(clks) / len(clks), 1), "sclk_mhz_min": min(clks),
+                    "sclk_mhz_max": max(clks), "power_w_mean": round(sum(s_["power_w"] for s_ in mid) / len(mid), 1),
+                    "samples": len(mid)})
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_single_thread(n: int = 1024) -> dict:
+    """The FP64 oracle GEMM at n^3 on one host thread (a child process with
+    OMP_NUM_THREADS=1): context for the many-core cpu_baseline."""
+    import subprocess
+
+    code = ("import time, sys; sys.path.insert(0, %r); import numpy as np, oracle, workloads; "
+            "A, B = workloads.uniform(2, [(%d, %d), (%d, %d)]); oracle.exact(A[:8], B); "
+            "t = time.perf_counter(); oracle.exact(A, B); dt = time.perf_counter() - t; "
+            "print(dt, oracle.num_threads())") % (ROOT, n, n, n, n)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    dt, thr = r.stdout.split()[-2:]
+    return {"n": n, "seconds": round(float(dt), 3), "gflops": round(2.0 * n ** 3 / float(dt) / 1e9, 2),
+            "threads": int(thr)}
+
+
+def precision_legs(dev, cpu: bool) -> dict:
+    """The refinement study (paper Sec. VII.B) on FP32 inputs drawn two ways,
+    normal(0, 1) (seed 3) and sign * 2^u with u uniform in [-10, 10] (seed 4),
+    at N = 4096 and 8192: for each mode, the end-to-end time from FP32
+    operands (conversion included) and, with the oracle, the max and
+    Frobenius errors relative to the exact FP64 product on 32 sampled rows
+    (reduced in FP64 on the GPU)."""
+    import numpy as np
+    import torch
+
+    import paper_1803_04014_amd as mfg
+    import workloads
+
+    modes = ("f16", "refine_a", "split3", "split4", "f32", "bf16", "bf16_split3")
+    products = {"refine_a": 2, "split3": 3, "split4": 4, "bf16_split3": 3}
+    out = {}
+    for dist, seed in (("normal", 3), ("pow2", 4)):
+        for n in (4096, 8192):
+            A, B = workloads.by_name(dist, seed, [(n, n), (n, n)])
+            dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+            dC = torch.empty((n, n), dtype=torch.float32, device=dev)
+            fl = 2.0 * n ** 3
+            ref = rows = None
+            if cpu:
+                import oracle
+
+                rows = oracle.sample_rows(n, n=32, seed=seed)
+                ref = torch.from_numpy(oracle.exact(A, B, 1.0, 0.0, None, rows=rows)).to(dev)
+                ridx = torch.from_numpy(rows).to(dev)
+            row = {}
+            for mode in modes:
+                ms = launch_times(lambda: mfg.gemm(dA, dB, dC, 1.0, 0.0, mode=mode), 3, warm=1)
+                st = rate_stats(fl, ms)
+                e = {"useful_tflops": st["tflops_hmean"],
+                     "executed_tflops": round(products.get(mode, 1) * st["tflops_hmean"], 1),
+                     "ms": round(float(np.mean(ms)), 3)}
+                if cpu:
+                    sub = dC.index_select(0, ridx).contiguous()
+                    o4 = torch.zeros(4, dtype=torch.float64, device=dev)
+                    mfg.error_norms(sub, ref, o4)
+                    o = o4.cpu().numpy()
+                    e["max_rel"], e["fro_rel"] = float(o[0] / o[3]), float(o[1] / o[2])
+                row[mode] = e
+            out[f"{dist}_n{n}"] = row
+            del dA, dB, dC
+    return out
+
+
+def autotune_leg(dA, dB, dev) -> dict:
+    """The autotuner on a few FP16 shapes: the default configuration against the
+    tuned one, timed interleaved (default, tuned, default, ...) after the same
+    warm-up; when the tuner keeps the default there is one timing and no gain."""
+    import numpy as np
+    import torch
+
+    import paper_1803_04014_amd as mfg
+
+    out = {}
+    mfg.lib().mfg_tune_clear()
+    for (m_, n_, k_) in ((4096, 4096, 4096), (8192, 2048, 4096), (2048, 2048, 8192), (1536, 1536, 1536)):
+        a = dA[:m_, :k_].contiguous()
+        b = dB[:k_, :n_].contiguous()
+        c = torch.empty((m_, n_), dtype=torch.float32, device=dev)
+        m16 = mfg.MFG_F16 | mfg.MFG_IN_PRECONVERTED
+        default = mfg.lib().mfg_tune_lookup(m_, n_, k_, m16)
+        best, _ = mfg.autotune(a, b, c, "f16", reps=3, preconverted=True)
+        fl = 2.0 * m_ * n_ * k_
+        run = lambda cfg: mfg.gemm(a, b, c, 1.0, 0.0, mode="f16", preconverted=True, config=cfg)
+        e = {"default_config": mfg.config_name("f16", default), "tuned_config": mfg.config_name("f16", best)}
+        if best == default:
+            ms = launch_times(lambda: run(default), 10, warm=5)
+            e.update({"same_as_default": True, "tflops": rate_stats(fl, ms)["tflops_median"]})
+        else:
+            td, tt = [], []
+            for _ in range(3):
+                td += launch_times(lambda: run(default), 5, warm=3)
+                tt += launch_times(lambda: run(best), 5, warm=3)
+            e.update({"same_as_default": False, "default_tflops": rate_stats(fl, td)["tflops_median"],
+                      "tuned_tflops": rate_stats(fl, tt)["tflops_median"]})
+        out[f"{m_}x{n_}x{k_}"] = e
+    mfg.lib().mfg_tune_clear()
+    return out
 
 
 def main() -> int:
@@ -360,6 +605,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle time for cpu_baseline")
+    ap.add_argument("--sclk-seconds", type=float, default=2.0, help="sustained-load clock sampling")
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="per arrival rate (at most 20000 requests)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, metavar="BYTES", help="only run the counter-calibration copy")
@@ -367,11 +614,18 @@ def main() -> int:
                     help="only turn four rocprofv3 --pmc output folders into the traffic record")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--grouped-only", action="store_true", help="only the grouped-plan legs (one JSON line)")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving legs (one JSON line)")
     ap.add_argument("--kernel-only", metavar="MODE", help="only time MODE's GEMM at N^3 on preconverted operands")
     ap.add_argument("--mfma-ceiling", action="store_true", help="only the register-only MFMA ceiling probe")
     ap.add_argument("--mfma-summary", nargs=2, metavar=("DIR", "KERNEL"),
                     help="only print MFMA utilisation per dispatch from a rocprofv3 --pmc output folder")
+    ap.add_argument("--trace-overlap", metavar="DIR",
+                    help="only print how the library's kernels overlapped across streams in a kernel trace")
     args = ap.parse_args()
+    if args.trace_overlap:
+        return trace_overlap(args.trace_overlap)
+    if args.mfma_summary:
+        return mfma_summary(*args.mfma_summary)
     if args.copy_probe:
         return copy_probe(args.copy_probe)
     if args.pmc_summarize:
@@ -380,8 +634,6 @@ def main() -> int:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build is single-GPU)",
               file=sys.stderr)
         return 2
-    if args.mfma_summary:
-        return mfma_summary(*args.mfma_summary)
     if args.kernel_only:
         return kernel_only(args.kernel_only, args.n, args.steps, args.warmup)
     if args.mfma_ceiling:
@@ -403,6 +655,27 @@ def main() -> int:
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+
+    def serving_legs(rates, cpu):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(7)
+        pools = (torch.randn((4096, 4096), device=dev, generator=gen),
+                 torch.randn((4096, 4096), device=dev, generator=gen))
+        serving = {}
+        for rate in rates:
+            log(f"bench: serving at {rate:.0f} requests/s")
+            srv, trace, views = serving_leg(rate, args.serve_seconds, 20000, 7, pools)
+            if cpu:
+                srv["errors_vs_fp64"] = served_errors(trace, views)
+            serving[f"lambda_{int(rate)}"] = srv
+            del views
+        return serving
+
+    rates = (200.0, 500.0, 1000.0, 2000.0, 5000.0)
+    if args.serving_only:
+        print(json.dumps({"serving": serving_legs(rates, not args.no_cpu)}), flush=True)
+        return 0
+
     N = args.n
     log(f"bench: generating inputs N={N}")
     A32, B32, C0 = workloads.uniform(2, [(N, N), (N, N), (N, N)])
@@ -434,7 +707,8 @@ def main() -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    times = [a.elapsed_time(b) for a, b in evs]
+    kernel_ms = sum(times) / args.steps
     value = flops * args.steps / wall / 1e12
     achieved = flops / (kernel_ms * 1e-3) / 1e12
 
@@ -457,8 +731,18 @@ def main() -> int:
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["f16"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f16"], 4), "traffic": traffic,
                      "kernel_ms": round(kernel_ms, 4), "kernel_hash": kernel_hash()},
+        "launch_stats": rate_stats(flops, times),
     }
     log(f"bench: f16 N={N}: {value:.1f} TFLOP/s wall, kernel {kernel_ms:.3f} ms -> {achieved:.1f} TFLOP/s")
+
+    # the clock under a sustained headline load, and the roofline at that clock
+    if args.sclk_seconds > 0:
+        log("bench: sustained clock")
+        sc = sustained_clock(step, flops, args.sclk_seconds)
+        out["sustained_clock"] = sc
+        if "sclk_mhz_mean" in sc:
+            out["roofline"]["frac_at_measured_clock"] = round(
+                sc["tflops"] / (PEAK_TFLOPS["f16"] * sc["sclk_mhz_mean"] / 2400.0), 4)
 
     # fresh result for the error figures: C = A B + C0 once
     results = {}
@@ -496,7 +780,8 @@ def main() -> int:
         cpu_s = time.perf_counter() - t
         out["cpu_baseline"] = {"value": round(2.0 * len(rows) * N * N / cpu_s / 1e12, 5), "unit": "TFLOP/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
-                               "sample": f"FP64 GEMM of {len(rows)} of {N} rows (x {N} x {N}), {cpu_s:.1f} s"}
+                               "sample": f"FP64 GEMM of {len(rows)} of {N} rows (x {N} x {N}), {cpu_s:.1f} s",
+                               "cpu_model": cpu_model()}
         # FP64 error reductions on the GPU (rows of C against the oracle's rows)
         dref = torch.from_numpy(ref).to(dev)
         ridx = torch.from_numpy(rows).to(dev)
@@ -509,6 +794,9 @@ def main() -> int:
             errs[name] = {"max_rel": float(o[0] / o[3]), "fro_rel": float(o[1] / o[2])}
         out["errors_vs_fp64"] = errs
         out["max_rel_err_vs_fp64"] = errs["f16"]["max_rel"]
+        if not args.no_extras:
+            log("bench: single-thread oracle at 1024")
+            out["cpu_baseline"]["single_thread_n1024"] = oracle_single_thread(1024)
 
     # ------------------------------------------------------------- extras
     if not args.no_extras:
@@ -519,37 +807,67 @@ def main() -> int:
         mfg.round_bf16(dA32, dAb)
         mfg.round_bf16(dB32, dBb)
         dCx = dC0.clone()
-        ms = timed(lambda: mfg.gemm(dAb, dBb, dCx, 1.0, 1.0, mode="bf16", preconverted=True), reps)
-        ex["bf16_n8192"] = {"tflops": round(flops / ms / 1e9, 1), "pct_peak": round(flops / ms / 1e9 / 25.0, 1)}
+        ex["bf16_n8192"] = rate_stats(flops, launch_times(
+            lambda: mfg.gemm(dAb, dBb, dCx, 1.0, 1.0, mode="bf16", preconverted=True), reps))
         # context only (not this library): the vendor GEMM behind torch.matmul on the
-        # same FP16 operands, FP16 output and no C read -- less traffic than the headline
+        # same operands: FP16 (FP16 output, no C read -- less traffic than the headline)
+        # and FP32 (TF32 off), beside this library's FP32 comparator
         ms = timed(lambda: torch.matmul(dA, dB), reps)
         ex["context_torch_matmul_f16_n8192"] = {"tflops": round(flops / ms / 1e9, 1),
                                                 "note": "vendor library via torch.matmul, FP16 out, beta = 0"}
-        ms = timed(lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode="f32"), 3, warm=1)
-        ex["f32_n8192"] = {"tflops": round(flops / ms / 1e9, 1), "pct_peak": round(flops / ms / 1e9 / 1.573, 1)}
+        torch.backends.cuda.matmul.allow_tf32 = False
+        ms = timed(lambda: torch.matmul(dA32, dB32), 3, warm=1)
+        ex["context_torch_matmul_f32_n8192"] = {"tflops": round(flops / ms / 1e9, 1),
+                                                "note": "vendor library via torch.matmul, FP32, TF32 off"}
+        ex["f32_n8192"] = rate_stats(flops, launch_times(
+            lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode="f32"), 3, warm=1))
         for mode in ("refine_a", "split3", "split4", "fp8", "bf16_split3"):
             ms = timed(lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode=mode), 3, warm=1)
             products = {"refine_a": 2, "split3": 3, "split4": 4, "bf16_split3": 3}.get(mode, 1)
             ex[f"{mode}_n8192_fp32_in"] = {"useful_tflops": round(flops / ms / 1e9, 1),
                                            "executed_tflops": round(products * flops / ms / 1e9, 1), "ms": round(ms, 3)}
-        # N sweep (FP16, preconverted)
-        sweep = {}
-        for n in (1024, 2048, 4096):
-            a = dA[:n, :n].contiguous()
-            b = dB[:n, :n].contiguous()
-            c = dC0[:n, :n].contiguous()
-            ms = timed(lambda: mfg.gemm(a, b, c, 1.0, 1.0, mode="f16", preconverted=True), 20)
-            sweep[str(n)] = round(2.0 * n ** 3 / ms / 1e9, 1)
-        del a, b, c
-        n = 16384  # the largest square size of the sweep, from fresh operands
-        a = torch.empty((n, n), dtype=torch.float16, device=dev).uniform_(-1, 1)
-        b = torch.empty((n, n), dtype=torch.float16, device=dev).uniform_(-1, 1)
-        c = torch.empty((n, n), dtype=torch.float32, device=dev).uniform_(-1, 1)
-        ms = timed(lambda: mfg.gemm(a, b, c, 1.0, 1.0, mode="f16", preconverted=True), 4, warm=1)
-        sweep[str(n)] = round(2.0 * n ** 3 / ms / 1e9, 1)
-        del a, b, c
-        ex["f16_sweep_tflops"] = sweep
+        # N sweep: FP16 and BF16 (preconverted), FP32 (harmonic mean of per-launch rates)
+        sweep = {"f16": {}, "bf16": {}, "f32": {}}
+        for n in (1024, 2048, 4096, 16384):
+            fl = 2.0 * n ** 3
+            if n == 16384:  # fresh operands of the largest size
+                a16 = torch.empty((n, n), dtype=torch.float16, device=dev).uniform_(-1, 1)
+                b16 = torch.empty((n, n), dtype=torch.float16, device=dev).uniform_(-1, 1)
+                c = torch.empty((n, n), dtype=torch.float32, device=dev).uniform_(-1, 1)
+                a32, b32 = a16.float(), b16.float()
+                ab, bb = a16.bfloat16(), b16.bfloat16()
+            else:
+                a16, b16 = dA[:n, :n].contiguous(), dB[:n, :n].contiguous()
+                ab, bb = dAb[:n, :n].contiguous(), dBb[:n, :n].contiguous()
+                a32, b32 = dA32[:n, :n].contiguous(), dB32[:n, :n].contiguous()
+                c = dC0[:n, :n].contiguous()
+            rp = 4 if n == 16384 else 20
+            sweep["f16"][str(n)] = rate_stats(fl, launch_times(
+                lambda: mfg.gemm(a16, b16, c, 1.0, 1.0, mode="f16", preconverted=True), rp))["tflops_hmean"]
+            sweep["bf16"][str(n)] = rate_stats(fl, launch_times(
+                lambda: mfg.gemm(ab, bb, c, 1.0, 1.0, mode="bf16", preconverted=True), rp))["tflops_hmean"]
+            sweep["f32"][str(n)] = rate_stats(fl, launch_times(
+                lambda: mfg.gemm(a32, b32, c, 1.0, 1.0, mode="f32"), 2 if n == 16384 else 5, warm=1))["tflops_hmean"]
+            del a16, b16, ab, bb, a32, b32, c
+        for key, row in (("f16", None), ("bf16", "bf16_n8192"), ("f32", "f32_n8192")):
+            sweep[key]["8192"] = round(achieved, 2) if row is None else ex[row]["tflops_hmean"]
+        ex["sweep_tflops"] = sweep
+        # the one-GPU share of an eight-GPU row-panel split of N = 8192: M = 1024, N = K = 8192
+        share = {}
+        a_s, c_s = dA[:1024].contiguous(), dC0[:1024].contiguous()
+        fl = 2.0 * 1024 * N * N
+        share["f16"] = rate_stats(fl, launch_times(
+            lambda: mfg.gemm(a_s, dB, c_s, 1.0, 1.0, mode="f16", preconverted=True), 20))["tflops_hmean"]
+        a_s32 = dA32[:1024].contiguous()
+        share["split3_fp32_in"] = rate_stats(fl, launch_times(
+            lambda: mfg.gemm(a_s32, dB32, c_s, 1.0, 1.0, mode="split3"), 5, warm=1))["tflops_hmean"]
+        share["f32"] = rate_stats(fl, launch_times(
+            lambda: mfg.gemm(a_s32, dB32, c_s, 1.0, 1.0, mode="f32"), 5, warm=1))["tflops_hmean"]
+        ex["gpu_share_m1024_n8192_k8192"] = share
+        del a_s, c_s, a_s32
+        # refinement study inputs (normal, sign * 2^u) at 4096 and 8192
+        log("bench: precision study")
+        ex["precision_fp32_in"] = precision_legs(dev, not args.no_cpu)
         # the HBM-bound steps at N x N: operand rounding, split with FP64 norms,
         # FP8 tile quantisation, FP64 error norms (algorithmic bytes per element:
         # 4 + 2, 4 + 2 + 2, 4 + 1, 4 + 8)
@@ -582,11 +900,11 @@ def main() -> int:
                 sets.append((a16, b16, torch.empty((cnt, s, s), dtype=torch.float32, device=dev)))
             it = [0]
 
-            def step():
+            def bstep():
                 a16, b16, c = sets[it[0] % nsets]
                 it[0] += 1
                 mfg.gemm_batched(a16, b16, c, 1.0, 0.0, mode="f16")
-            ms = timed(step, reps * nsets, warm=warm)
+            ms = timed(bstep, reps * nsets, warm=warm)
             del sets
             return {"gemm_per_s": round(cnt / ms * 1e3, 1), "tflops": round(2 * cnt * s ** 3 / ms / 1e9, 2),
                     "hbm_gbs": round(byts / ms / 1e6, 1), "pct_hbm": round(100 * byts / ms / 1e6 / HBM_GBS, 1),
@@ -596,36 +914,14 @@ def main() -> int:
         # 16^3 batches from 2^10 to 2^18 problems (GEMM/s against the batch size)
         ex["batched_16^3_sweep_gemm_per_s"] = {str(cnt): batched_leg(cnt, 16, reps=10, warm=20)["gemm_per_s"]
                                                for cnt in (1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18)}
-        # autotuner: default configuration against the tuned one on a few shapes
-        tune = {}
-        mfg.lib().mfg_tune_clear()
-        for (m_, n_, k_) in ((4096, 4096, 4096), (8192, 2048, 4096), (2048, 2048, 8192), (1536, 1536, 1536)):
-            a = dA[:m_, :k_].contiguous()
-            b = dB[:k_, :n_].contiguous()
-            c = torch.empty((m_, n_), dtype=torch.float32, device=dev)
-            ms_def = timed(lambda: mfg.gemm(a, b, c, 1.0, 0.0, mode="f16", preconverted=True), 10)
-            best, _ = mfg.autotune(a, b, c, "f16", reps=3, preconverted=True)
-            ms_tuned = timed(lambda: mfg.gemm(a, b, c, 1.0, 0.0, mode="f16", preconverted=True), 10)
-            fl = 2.0 * m_ * n_ * k_
-            tune[f"{m_}x{n_}x{k_}"] = {"default_tflops": round(fl / ms_def / 1e9, 1),
-                                       "tuned_tflops": round(fl / ms_tuned / 1e9, 1),
-                                       "tuned_config": mfg.config_name("f16", best)}
-        mfg.lib().mfg_tune_clear()
-        ex["autotune_f16"] = tune
+        log("bench: autotuner")
+        ex["autotune_f16"] = autotune_leg(dA, dB, dev)
+        log("bench: grouped")
         ex.update(grouped_legs(timed, dev))
-        # serving: Poisson arrivals at two rates
-        gen = torch.Generator(device=dev)
-        gen.manual_seed(7)
-        pools = (torch.randn((4096, 4096), device=dev, generator=gen), torch.randn((4096, 4096), device=dev, generator=gen))
-        serving = {}
-        for rate, secs in ((1000.0, 2.0), (5000.0, 1.0)):
-            log(f"bench: serving at {rate:.0f} requests/s")
-            srv, trace, views = serving_leg(rate, secs, 7, pools)
-            if not args.no_cpu:
-                srv["errors_vs_fp64"] = served_errors(trace, views)
-            serving[f"lambda_{int(rate)}"] = srv
-            del views
-        ex["serving"] = serving
+        log("bench: MFMA ceiling probe")
+        ex["mfma_ceiling"] = mfma_ceiling(torch.device(dev))
+        # serving: Poisson arrivals at 200 .. 5000 requests/s
+        ex["serving"] = serving_legs(rates, not args.no_cpu)
         out["extras"] = ex
     print(json.dumps(out), flush=True)
     return 0
