@@ -203,6 +203,39 @@ def mfma_summary(d: str, name_part: str) -> int:
     return 0
 
 
+def counter_table(d: str, name_part: str) -> int:
+    """Markdown table of every counter of a rocprofv3 --pmc output folder, mean
+    over the dispatches of the kernels whose name contains name_part (the
+    first dispatch, a warm-up at a cold clock, left out when there are
+    others), with the SQ_WAIT_* and SQ_ACTIVE_* counters (wave-level, in the
+    same units as SQ_WAVE_CYCLES) also as a share of SQ_WAVE_CYCLES when that
+    counter was collected."""
+    import collections
+
+    per = collections.defaultdict(dict)
+    for r in _csv_rows(d, "counter_collection.csv"):
+        if name_part not in r["Kernel_Name"]:
+            continue
+        k = int(r["Dispatch_Id"])
+        per[k][r["Counter_Name"]] = float(r["Counter_Value"])
+        per[k]["time_ns"] = float(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    if not per:
+        raise SystemExit(f"no dispatches of kernels matching {name_part!r} under {d}")
+    keys = sorted(per)
+    if len(keys) > 1:
+        keys = keys[1:]
+    names = sorted({c for k in keys for c in per[k]})
+    mean = {c: sum(per[k].get(c, 0.0) for k in keys) / len(keys) for c in names}
+    wave = mean.get("SQ_WAVE_CYCLES")
+    print(f"dispatches averaged: {len(keys)} ({keys[0]}..{keys[-1]})")
+    print("| counter | mean per dispatch | share of SQ_WAVE_CYCLES |")
+    print("|---|---|---|")
+    for c in names:
+        share = f"{mean[c] / wave:.3f}" if wave and c.startswith(("SQ_WAIT", "SQ_ACTIVE")) else ""
+        print(f"| {c} | {mean[c]:.6g} | {share} |")
+    return 0
+
+
 def trace_overlap(d: str, name_part: str = "mfg::") -> int:
     """From a rocprofv3 --kernel-trace output folder: how the kernels whose name
     contains name_part overlapped in time across HIP streams -- kernels per
@@ -619,6 +652,8 @@ def main() -> int:
     ap.add_argument("--mfma-ceiling", action="store_true", help="only the register-only MFMA ceiling probe")
     ap.add_argument("--mfma-summary", nargs=2, metavar=("DIR", "KERNEL"),
                     help="only print MFMA utilisation per dispatch from a rocprofv3 --pmc output folder")
+    ap.add_argument("--counter-table", nargs=2, metavar=("DIR", "KERNEL"),
+                    help="only print every counter's mean per dispatch from a rocprofv3 --pmc output folder")
     ap.add_argument("--trace-overlap", metavar="DIR",
                     help="only print how the library's kernels overlapped across streams in a kernel trace")
     args = ap.parse_args()
@@ -626,12 +661,14 @@ def main() -> int:
         return trace_overlap(args.trace_overlap)
     if args.mfma_summary:
         return mfma_summary(*args.mfma_summary)
+    if args.counter_table:
+        return counter_table(*args.counter_table)
     if args.copy_probe:
         return copy_probe(args.copy_probe)
     if args.pmc_summarize:
         return pmc_summarize(*args.pmc_summarize, args.copy_bytes, args.n)
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build is single-GPU)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path)",
               file=sys.stderr)
         return 2
     if args.kernel_only:
