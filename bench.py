@@ -560,8 +560,8 @@ def precision_legs(dev, cpu: bool) -> dict:
     import paper_1803_04014_amd as mfg
     import workloads
 
-    modes = ("f16", "refine_a", "split3", "split4", "f32", "bf16", "bf16_split3")
-    products = {"refine_a": 2, "split3": 3, "split4": 4, "bf16_split3": 3}
+    modes = ("f16", "refine_a", "split3", "split4", "f32", "bf16", "bf16_split3", "bf16_split6")
+    products = {"refine_a": 2, "split3": 3, "split4": 4, "bf16_split3": 3, "bf16_split6": 6}
     out = {}
     for dist, seed in (("normal", 3), ("pow2", 4)):
         for n in (4096, 8192):
@@ -858,9 +858,9 @@ def main() -> int:
                                                 "note": "vendor library via torch.matmul, FP32, TF32 off"}
         ex["f32_n8192"] = rate_stats(flops, launch_times(
             lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode="f32"), 3, warm=1))
-        for mode in ("refine_a", "split3", "split4", "fp8", "bf16_split3"):
+        for mode in ("refine_a", "split3", "split4", "fp8", "bf16_split3", "bf16_split6"):
             ms = timed(lambda: mfg.gemm(dA32, dB32, dCx, 1.0, 1.0, mode=mode), 3, warm=1)
-            products = {"refine_a": 2, "split3": 3, "split4": 4, "bf16_split3": 3}.get(mode, 1)
+            products = {"refine_a": 2, "split3": 3, "split4": 4, "bf16_split3": 3, "bf16_split6": 6}.get(mode, 1)
             ex[f"{mode}_n8192_fp32_in"] = {"useful_tflops": round(flops / ms / 1e9, 1),
                                            "executed_tflops": round(products * flops / ms / 1e9, 1), "ms": round(ms, 3)}
         # N sweep: FP16 and BF16 (preconverted), FP32 (harmonic mean of per-launch rates)

@@ -43,7 +43,7 @@ enum {
     MFG_OK = 0,
     MFG_PENDING = 1,              /* mfg_poll: request not finished yet        */
     MFG_ERR_INVALID_ARG = -1,     /* bad size, leading dimension, pointer, mode */
-    MFG_ERR_UNSUPPORTED = -2,     /* valid request this build does not serve    */
+    MFG_ERR_UNSUPPORTED = -2,     /* valid request the library does not serve   */
     MFG_ERR_NO_MEMORY = -3,       /* workspace or descriptor allocation failed  */
     MFG_ERR_OVER_BUDGET = -4,     /* serving: request larger than the budget    */
     MFG_ERR_HIP = -5,             /* a HIP runtime call failed                  */
@@ -72,6 +72,16 @@ enum {
  *                     bits per operand over FP32's whole range.
  *   MFG_FP8_E4M3      OCP E4M3 codes with one power-of-two FP32 scale per
  *                     128 x 128 tile of A (M x K) and of B (K x N).
+ *   MFG_BF16_SPLIT6   the paper's Eq. R applied twice on bfloat16 planes:
+ *                     h = rnebf16(A), r1 = rnebf16(A - h), r2 =
+ *                     rnebf16(A - h - r1) (h + r1 + r2 == A for FP32 A
+ *                     away from the subnormal range), likewise for B, and
+ *                     the six products of combined order <= 2:
+ *                     r2 h + r1 r1 + h r2 + r1 h + h r1 + h h, summed in one
+ *                     FP32 accumulator in that order per K chunk (the
+ *                     dropped r1 r2 + r2 r1 + r2 r2 is below 2^-23 |A||B|).
+ *                     FP32 operands only (no preconverted form); not served
+ *                     by the batched and grouped launches.
  * The residual scale is s = 2^11 (MFG_RESID_SCALE_LOG2).
  *
  * Preconverted storage forms (MFG_IN_PRECONVERTED), as written by
@@ -95,7 +105,8 @@ enum {
     MFG_F16_SPLIT4 = 5,
     MFG_FP8_E4M3 = 6,
     MFG_BF16_SPLIT3 = 7,
-    MFG_NUM_MODES = 8
+    MFG_BF16_SPLIT6 = 8,
+    MFG_NUM_MODES = 9
 };
 #define MFG_IN_PRECONVERTED 0x100
 /* mfg_grouped_plan_create only: A and B are FP32 (see "grouped GEMM"). */
@@ -305,7 +316,9 @@ int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode);
  * REFINE_A / SPLIT3 / SPLIT4) run as one persistent grouped launch, the
  * others one by one; one completion event per group.  Footprint: the mode's converted A (ld = K
  * rounded up to 8, or to 16 for FP8) and B (ld = N rounded likewise), each
- * rounded up to 256 bytes; 0 for MFG_F32 and for empty problems.  The fixed
+ * rounded up to 256 bytes; 0 for MFG_F32 and for empty problems, and 0 for
+ * MFG_BF16_SPLIT6, which runs through mfg_gemm and its per-stream workspace
+ * (12 bytes per element of A and B, outside the budget).  The fixed
  * per-slot descriptor staging is not counted.  Results are bitwise those of
  * mfg_gemm on the same FP32 operands, whatever a request is grouped with.
  * Config limits: 1 <= slots <= 64, 1 <= max_group <= 4096, reserved = 0.

@@ -42,7 +42,7 @@ S_RESID = 2.0 ** 11
 FP8_TILE = 128
 E4M3_MAX = 448.0
 
-MODES = ("f32", "f16", "bf16", "refine_a", "split3", "split4", "fp8")
+MODES = ("f32", "f16", "bf16", "refine_a", "split3", "split4", "fp8", "bf16_split3", "bf16_split6")
 
 _lib = None
 
@@ -168,6 +168,29 @@ def split_bf16(x) -> Split:
 
 
 @dataclass
+class Split3Way:
+    """Eq. R applied twice on bfloat16 planes: x = h + r1 + r2 (+ what r2 rounds away)."""
+    h: np.ndarray   # FP64 value of rnebf16(x)
+    r1: np.ndarray  # FP64 value of rnebf16(x - h)
+    r2: np.ndarray  # FP64 value of rnebf16(x - h - r1)
+    bits: tuple     # uint16 bfloat16 codes of (h, r1, r2)
+
+
+def split3_bf16(x) -> Split3Way:
+    """Three-way bfloat16 split: the residual of Eq. R is itself split by Eq. R.
+    Both differences are exact in FP64 (and in FP32 for FP32 x), so for FP32 x
+    whose planes stay normal, h + r1 + r2 == x: each plane carries the next 8
+    significant bits."""
+    x64 = np.asarray(x, dtype=np.float64)
+    hb = bf16_encode(x64)
+    h = bf16_decode(hb)
+    ab = bf16_encode(x64 - h)
+    a = bf16_decode(ab)
+    bb = bf16_encode((x64 - h) - a)
+    return Split3Way(h, a, bf16_decode(bb), (hb, ab, bb))
+
+
+@dataclass
 class Fp8Tiles:
     """Per-tile FP8-E4M3 quantisation of a matrix."""
     codes: np.ndarray      # uint8, same shape as the input
@@ -256,6 +279,8 @@ def mode_terms(mode: str, A, B):
     split3   : Eq. 2 without the R_A R_B product -- A_h B_h + (A_h R_B + R_A B_h)/s
     split4   : Eq. 2 -- split3 + R_A R_B / s^2
     bf16_split3 : Eq. 2 without R_A R_B on bfloat16 head and unscaled residual planes
+    bf16_split6 : three-way bfloat16 split of A and B (split3_bf16), every product of
+                  combined order <= 2: h h + (h r1 + r1 h) + (h r2 + r1 r1 + r2 h)
     fp8      : per-tile dequantised codes, deq(A) deq(B)
     """
     A = np.asarray(A, dtype=np.float64)
@@ -279,6 +304,10 @@ def mode_terms(mode: str, A, B):
     if mode == "bf16_split3":
         sa, sb = split_bf16(A), split_bf16(B)
         return [(1.0, sa.head, sb.head), (1.0, sa.head, sb.resid), (1.0, sa.resid, sb.head)]
+    if mode == "bf16_split6":
+        a, b = split3_bf16(A), split3_bf16(B)
+        return [(1.0, a.h, b.h), (1.0, a.h, b.r1), (1.0, a.r1, b.h),
+                (1.0, a.h, b.r2), (1.0, a.r1, b.r1), (1.0, a.r2, b.h)]
     if mode == "fp8":
         return [(1.0, fp8_quantize(A).deq, fp8_quantize(B).deq)]
     raise ValueError(f"unknown mode {mode!r}")
@@ -349,6 +378,15 @@ def representation_bound(mode: str, A, B, alpha: float = 1.0, rows=None) -> np.n
         At = mode_terms(mode, A, B)[0][1]
         Bt = mode_terms(mode, A, B)[0][2]
         extra = None
+    elif mode == "bf16_split6":
+        a, b = split3_bf16(A), split3_bf16(B)
+        At, Bt = a.h + a.r1 + a.r2, b.h + b.r1 + b.r2
+        # dropped products of combined order 3 and 4
+        dropped = (gemm(np.abs(a.r1), np.abs(b.r2), rows=rows) + gemm(np.abs(a.r2), np.abs(b.r1), rows=rows)
+                   + gemm(np.abs(a.r2), np.abs(b.r2), rows=rows))
+        dA, dB = np.abs(A - At), np.abs(B - Bt)
+        bnd = gemm(dA, np.abs(B), rows=rows) + gemm(np.abs(At), dB, rows=rows) + dropped
+        return abs(alpha) * bnd
     elif mode == "refine_a":
         sa = split_f16(A)
         At = sa.head + sa.resid / sa.s

@@ -30,7 +30,8 @@ MFG_F16_SPLIT3 = 4
 MFG_F16_SPLIT4 = 5
 MFG_FP8_E4M3 = 6
 MFG_BF16_SPLIT3 = 7
-MFG_NUM_MODES = 8
+MFG_BF16_SPLIT6 = 8
+MFG_NUM_MODES = 9
 MFG_IN_PRECONVERTED = 0x100
 MFG_IN_FP32 = 0x200  # grouped plans: FP32 operands, converted on every run
 MFG_MODE_MASK = 0xFF
@@ -41,6 +42,7 @@ MFG_NOALLOC_SCRATCH_BYTES = 64 << 20
 MODE_BY_NAME = {
     "f32": MFG_F32, "f16": MFG_F16, "bf16": MFG_BF16, "refine_a": MFG_F16_REFINE_A,
     "split3": MFG_F16_SPLIT3, "split4": MFG_F16_SPLIT4, "fp8": MFG_FP8_E4M3, "bf16_split3": MFG_BF16_SPLIT3,
+    "bf16_split6": MFG_BF16_SPLIT6,
 }
 
 i64, i32, f32, f64, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_double, ctypes.c_void_p

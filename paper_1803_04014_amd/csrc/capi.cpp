@@ -55,6 +55,16 @@ static int choose16(int m, int config, int64_t M, int64_t N, int64_t K, int64_t 
     return pick_config16(kind_of(m), M, N, K, vec);
 }
 
+// BF16_SPLIT6 runs the BF16 kernels over K' = 6 * up(K, 64); its tuned
+// entries are keyed by its own mode and the caller's K.
+static int choose_split6(int config, int64_t M, int64_t N, int64_t K, int64_t ldc, bool vec) {
+    if (config >= 0) return config;
+    const int64_t kk = 6 * up(K, 64);
+    const int t = tuned_lookup(MFG_BF16_SPLIT6, M, N, K);
+    if (t >= 0 && config16_ok(K_BF16, t, M, N, kk, ldc, vec)) return t;
+    return pick_config16(K_BF16, M, N, kk, vec);
+}
+
 // The storage a call converts its operands into: the per-stream workspace
 // (grown with hipMalloc, held by a lease), or caller-provided device memory
 // of a fixed capacity (the allocation-free entry point).
@@ -161,6 +171,27 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
         return launch_gemm_f8(cfg, a, vec8, s);
     }
 
+    if (m == MFG_BF16_SPLIT6) {
+        // Both operands split three ways into the long-K layout (launch_split6_bf16),
+        // then one BF16 GEMM over K' = 6 kp.
+        if (pre) return MFG_ERR_UNSUPPORTED;
+        const int64_t kp = up(K, 64), kk = 6 * kp, ldn = up(N, 8);
+        const int64_t ea = up(M * kk, 128), eb = up(kk * ldn, 128);
+        CallWs ws;
+        if ((st = call_ws(s, (size_t)(ea + eb) * 2, ext, ws)) != MFG_OK) return st;
+        uint16_t* a0 = static_cast<uint16_t*>(ws.ptr);
+        uint16_t* b0 = a0 + ea;
+        if ((st = launch_split6_bf16(M, K, static_cast<const float*>(A), lda, a0, kk, kp, false, s)) != MFG_OK)
+            return st;
+        if ((st = launch_split6_bf16(K, N, static_cast<const float*>(B), ldb, b0, ldn, kp, true, s)) != MFG_OK)
+            return st;
+        Gemm16Args a{};
+        a.M = M, a.N = N, a.K = kk, a.C = C, a.ldc = ldc, a.alpha = alpha, a.beta = beta;
+        a.A[0] = a0, a.B[0] = b0, a.lda = kk, a.ldb = ldn;
+        const bool vec = buffer_ldc_ok(ldc) && operand_ld_ok(kk, ldn);
+        return launch_gemm16(K_BF16, choose_split6(config, M, N, K, ldc, vec), a, 1, vec, s);
+    }
+
     // 16-bit modes
     const int kind = kind_of(m);
     Gemm16Args a{};
@@ -239,7 +270,8 @@ extern "C" int mfg_gemm_config(int64_t M, int64_t N, int64_t K, const void* A, i
 }
 
 extern "C" int mfg_num_configs(int mode) {
-    const int m = mode & MFG_MODE_MASK;
+    int m = mode & MFG_MODE_MASK;
+    if (m == MFG_BF16_SPLIT6) m = MFG_BF16;  // runs the BF16 kernels
     if (m == MFG_F32) return num_configs_f32();
     if (m == MFG_FP8_E4M3) return num_configs_f8();
     const int k = kind_of(m);
@@ -247,7 +279,8 @@ extern "C" int mfg_num_configs(int mode) {
 }
 
 extern "C" int mfg_config_name(int mode, int config, char* buf, int n) {
-    const int m = mode & MFG_MODE_MASK;
+    int m = mode & MFG_MODE_MASK;
+    if (m == MFG_BF16_SPLIT6) m = MFG_BF16;
     const char* name = nullptr;
     if (m == MFG_F32) name = config_f32_name(config);
     else if (m == MFG_FP8_E4M3) name = config_f8_name(config);
@@ -269,6 +302,7 @@ extern "C" int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode) {
         const int t = tuned_lookup(m, M, N, K);
         return (t >= 0 && t < num_configs_f8()) ? t : pick_config_f8(M, N, K, true);
     }
+    if (m == MFG_BF16_SPLIT6) return choose_split6(-1, M, N, K, N, true);
     return choose16(m, -1, M, N, K, N, true);
 }
 
@@ -286,7 +320,7 @@ static int batched_impl(int64_t count, int64_t M, int64_t N, int64_t K, const vo
     int st = validate_gemm(M, N, K, A, lda, B, ldb, C, ldc, mode);
     if (st != MFG_OK) return st;
     if (count > 1 && M > 0 && N > 0 && strideC < (M - 1) * ldc + N) return MFG_ERR_INVALID_ARG;  // outputs overlap
-    if (m == MFG_FP8_E4M3) return MFG_ERR_UNSUPPORTED;
+    if (m == MFG_FP8_E4M3 || m == MFG_BF16_SPLIT6) return MFG_ERR_UNSUPPORTED;
     if (count == 0 || M == 0 || N == 0) return MFG_OK;
     if (K == 0 || alpha == 0.0f) return launch_scale_c(M, N, C, ldc, beta, count, strideC, s);
 
@@ -435,7 +469,7 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
         return MFG_ERR_INVALID_ARG;
     const bool fp32_in = (mode & MFG_IN_FP32) != 0;
     if (fp32_in && (mode & MFG_IN_PRECONVERTED)) return MFG_ERR_INVALID_ARG;
-    if (m == MFG_F32 || m == MFG_FP8_E4M3) return MFG_ERR_UNSUPPORTED;
+    if (m == MFG_F32 || m == MFG_FP8_E4M3 || m == MFG_BF16_SPLIT6) return MFG_ERR_UNSUPPORTED;
     if (count > ((int64_t)1 << 31) - 1) return MFG_ERR_UNSUPPORTED;
     // Refined modes read their operands in the preconverted storage form:
     // A's residual plane at A + M*lda, and for the two-sided splits B's at
@@ -652,6 +686,7 @@ static int convert_impl(int64_t rows, int64_t cols, const float* X, int64_t ldx,
             return launch_quantize_fp8(rows, cols, X, ldx, c, ldo,
                                        reinterpret_cast<float*>(c + mfg_fp8_scale_offset(rows, ldo)), s);
         }
+        case MFG_BF16_SPLIT6: return MFG_ERR_UNSUPPORTED;  // no preconverted form
         default: return MFG_ERR_INVALID_ARG;
     }
 }

@@ -11,6 +11,10 @@
 //   split_bf16  : the same with bfloat16 planes and an unscaled residual
 //                 (bfloat16 has FP32's exponent range): head = rnebf16(x),
 //                 resid = rnebf16(x - head), x - head exact in FP32 as above.
+//   split6_bf16 : Eq. R applied twice on bfloat16 planes, h = rnebf16(x),
+//                 r1 = rnebf16(x - h), r2 = rnebf16(x - h - r1) (both
+//                 differences exact in FP32), written as six K-blocks of one
+//                 long-K operand; see launch_split6_bf16.
 //   quantize_fp8: one power-of-two scale per 128 x 128 tile, OCP E4M3 codes,
 //                 round-to-nearest-even, saturating at +-448.
 //   error_norms : max|C - R|, ||C - R||_F, ||R||_F, max|R| in FP64 (the
@@ -263,6 +267,84 @@ int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, ui
 int launch_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head, uint16_t* resid,
                       int64_t ldo, double* norms, hipStream_t s) {
     return launch_split<true>(rows, cols, X, ldx, head, resid, ldo, norms, s);
+}
+
+// ------------------------------------------------------ three-way bf16 split
+// Source element (r, c) of an (rows x cols) FP32 matrix, zero outside it, goes
+// to six blocks of the output: block j holds plane (order >> 2j) & 3 (0 = h,
+// 1 = r1, 2 = r2) at out + j * bstride + r * ldo + c.  The iteration covers
+// (it_rows x it_cols), which includes the zero padding the long-K GEMM reads.
+__global__ __launch_bounds__(kEltThreads) void split6_bf16_kernel(int64_t rows, int64_t cols, int64_t it_rows,
+                                                                  int64_t it_cols, const float* X, int64_t ldx,
+                                                                  uint16_t* out, int64_t ldo, int64_t bstride,
+                                                                  int order, int vec) {
+    const int64_t c0 = ((int64_t)blockIdx.x * kEltThreads + threadIdx.x) * kColsPerThread;
+    if (c0 >= it_cols) return;
+    const int cnt = it_cols - c0 < kColsPerThread ? (int)(it_cols - c0) : kColsPerThread;
+    for (int64_t r = blockIdx.y; r < it_rows; r += gridDim.y) {
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (r < rows) {
+            const float* x = X + r * ldx;
+            if (vec && c0 + kColsPerThread <= cols) {
+                const f32x4 t = *reinterpret_cast<const f32x4*>(x + c0);
+                v[0] = t[0], v[1] = t[1], v[2] = t[2], v[3] = t[3];
+            } else {
+                for (int j = 0; j < kColsPerThread; ++j)
+                    if (c0 + j < cols) v[j] = x[c0 + j];
+            }
+        }
+        uint32_t pl[3][2];  // plane p, packed pairs
+#pragma unroll
+        for (int j = 0; j < 4; j += 2) {
+            uint16_t h[2], a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                h[i] = f32_to_bf16_bits(v[j + i]);
+                const float d1 = v[j + i] - bf16_bits_to_f32(h[i]);  // exact
+                a[i] = f32_to_bf16_bits(d1);
+                b[i] = f32_to_bf16_bits(d1 - bf16_bits_to_f32(a[i]));  // exact difference
+            }
+            pl[0][j >> 1] = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+            pl[1][j >> 1] = (uint32_t)a[0] | ((uint32_t)a[1] << 16);
+            pl[2][j >> 1] = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
+        }
+        uint16_t* o = out + r * ldo + c0;
+#pragma unroll
+        for (int blk = 0; blk < 6; ++blk) {
+            const int p = (order >> (2 * blk)) & 3;
+            const uint32_t w0 = p == 0 ? pl[0][0] : p == 1 ? pl[1][0] : pl[2][0];
+            const uint32_t w1 = p == 0 ? pl[0][1] : p == 1 ? pl[1][1] : pl[2][1];
+            uint16_t* ob = o + blk * bstride;
+            if (cnt == 4) {
+                *reinterpret_cast<u32x2*>(ob) = u32x2{w0, w1};
+            } else {
+                const uint16_t e[4] = {(uint16_t)w0, (uint16_t)(w0 >> 16), (uint16_t)w1, (uint16_t)(w1 >> 16)};
+                for (int i = 0; i < cnt; ++i) ob[i] = e[i];
+            }
+        }
+    }
+}
+
+// The long-K operands of the three-way bfloat16 split: six products summed in
+// one FP32 accumulator by a plain BF16 GEMM over K' = 6 * kp (kp = K rounded
+// up to a multiple of 64, zero-padded).  The K-blocks pair up as
+//   A': [r2 | r1 | h  | r1 | h  | h ]      (M x 6kp, ld = 6kp)
+//   B': [h  ; r1 ; r2 ; h  ; r1 ; h ]      (6kp x N, block j at rows j*kp)
+// i.e. r2*h + r1*r1 + h*r2 + r1*h + h*r1 + h*h, the smallest terms first.
+// side_b selects B's layout.  out: 8-byte aligned, ldo a multiple of 4.
+int launch_split6_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* out, int64_t ldo,
+                       int64_t kp, bool side_b, hipStream_t s) {
+    constexpr int kOrderA = 2 | 1 << 2 | 0 << 4 | 1 << 6 | 0 << 8 | 0 << 10;
+    constexpr int kOrderB = 0 | 1 << 2 | 2 << 4 | 0 << 6 | 1 << 8 | 0 << 10;
+    const int64_t it_rows = side_b ? kp : rows, it_cols = side_b ? cols : kp;
+    if (it_rows == 0 || it_cols == 0) return MFG_OK;
+    if (((uintptr_t)out & 7u) != 0 || ldo % 4 != 0) return MFG_ERR_INVALID_ARG;
+    const int vec = aligned(X, ldx, 16, 4);
+    const int64_t bstride = side_b ? kp * ldo : kp;
+    hipLaunchKernelGGL(split6_bf16_kernel, elt_grid(it_rows, it_cols), dim3(kEltThreads), 0, s, rows, cols, it_rows,
+                       it_cols, X, ldx, out, ldo, bstride, side_b ? kOrderB : kOrderA, vec);
+    MFG_LAUNCH_CHECK();
+    return MFG_OK;
 }
 
 // ---------------------------------------------------- conversion job lists

@@ -109,6 +109,8 @@ int launch_split_f16(int64_t rows, int64_t cols, const float* X, int64_t ldx, ui
                      uint16_t* resid, int64_t ldo, double* norms, hipStream_t s);
 int launch_split_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* head,
                       uint16_t* resid, int64_t ldo, double* norms, hipStream_t s);
+int launch_split6_bf16(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint16_t* out, int64_t ldo,
+                       int64_t kp, bool side_b, hipStream_t s);
 int launch_quantize_fp8(int64_t rows, int64_t cols, const float* X, int64_t ldx, uint8_t* codes,
                         int64_t ldo, float* scales, hipStream_t s);
 // The same codes written transposed (code of X[r][c] at codes_t[c * ldt + r]),

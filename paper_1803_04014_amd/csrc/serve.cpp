@@ -75,7 +75,9 @@ struct Req {
 void plan_footprint(Req& q) {
     const mfg_request& r = q.r;
     const int m = r.mode;
-    if (m == MFG_F32 || r.M == 0 || r.N == 0 || r.K == 0 || r.alpha == 0.0f) {
+    // F32 converts nothing; BF16_SPLIT6 has no preconverted form and runs
+    // through mfg_gemm, whose per-stream workspace is outside the budget.
+    if (m == MFG_F32 || m == MFG_BF16_SPLIT6 || r.M == 0 || r.N == 0 || r.K == 0 || r.alpha == 0.0f) {
         q.footprint = 0;
         return;
     }
@@ -337,7 +339,7 @@ bool mfg_server::launch_ready(std::unique_lock<std::mutex>& lk) {
 // joins the group's grouped launch (grouped: conversion only).
 int mfg_server::run_request(Slot& sl, Req* q, bool grouped) {
     const mfg_request& r = q->r;
-    if (q->footprint == 0)  // F32, empty, K == 0 or alpha == 0: no conversion
+    if (q->footprint == 0)  // F32, BF16_SPLIT6, empty, K == 0 or alpha == 0: no conversion here
         return mfg_gemm(r.M, r.N, r.K, r.A, r.lda, r.B, r.ldb, r.C, r.ldc, r.alpha, r.beta, r.mode, sl.stream);
     if (fault_hit(kFaultAlloc)) return MFG_ERR_NO_MEMORY;
     hipError_t e = hipMallocAsync(&q->ws, (size_t)q->footprint, sl.stream);

@@ -87,7 +87,8 @@ P = 0x7F0000000000  # a non-null address: validation never dereferences
     ((8, 8, 8, P, 8, P, 8, P, 7, 1), -1),                   # ldc < N
     ((8, 8, 8, None, 8, P, 8, P, 8, 1), -1),
     ((8, 8, 8, P, 8, P, 8, None, 8, 1), -1),
-    ((8, 8, 8, P, 8, P, 8, P, 8, 8), -1),                   # no such mode
+    ((8, 8, 8, P, 8, P, 8, P, 8, 8), 0),                    # MFG_BF16_SPLIT6
+    ((8, 8, 8, P, 8, P, 8, P, 8, 9), -1),                   # no such mode
     ((8, 8, 8, P, 8, P, 8, P, 8, 0x201), -1),               # unknown flag
     ((8, 8, 8, P, 8, P, 8, P, 8, 0x101), 0),
 ])
@@ -101,6 +102,7 @@ def test_convert_bytes_and_fp8_scale_offset():
     assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_F16_SPLIT3) == 2 * 10 * 8 * 2
     assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_BF16_SPLIT3) == 2 * 10 * 8 * 2
     assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_NUM_MODES) == -1
+    assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_BF16_SPLIT6) == -1  # no preconverted form
     assert L.mfg_convert_bytes(10, 7, 8, capi.MFG_F32) == 10 * 8 * 4
     off = L.mfg_fp8_scale_offset(300, 272)
     assert off >= 300 * 272 and off % 16 == 0

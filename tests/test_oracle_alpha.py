@@ -70,7 +70,7 @@ def _check(ref, want, mag):
             assert Fraction(float(ref.absval[i, j])) == mag[i][j], (i, j)
 
 
-@pytest.mark.parametrize("mode", ["f32", "f16", "bf16", "refine_a", "split3", "split4", "bf16_split3", "fp8"])
+@pytest.mark.parametrize("mode", ["f32", "f16", "bf16", "refine_a", "split3", "split4", "bf16_split3", "bf16_split6", "fp8"])
 def test_small_integers_every_mode(mode):
     M, N, K = 6, 5, 37
     A = _ints(1, (M, K), -8, 8).astype(np.float32)
@@ -145,7 +145,7 @@ def test_exact_at_general_alpha_beta_is_f32_reference():
             assert Fraction(float(got[i, j])) == want[i][j]
 
 
-@pytest.mark.parametrize("mode", ["f16", "bf16", "refine_a", "split3", "split4", "bf16_split3", "fp8"])
+@pytest.mark.parametrize("mode", ["f16", "bf16", "refine_a", "split3", "split4", "bf16_split3", "bf16_split6", "fp8"])
 def test_representation_bound_scales_with_abs_alpha(mode):
     A, B = (np.random.default_rng(80 + k).standard_normal(size=s).astype(np.float32)
             for k, s in enumerate([(24, 40), (40, 16)]))
@@ -161,7 +161,7 @@ def test_representation_bound_holds_at_general_alpha():
     # |alpha R_mode - alpha R_exact| <= bound(alpha): the distance scales with |alpha|
     A, B = (np.random.default_rng(90 + k).uniform(-1, 1, size=s).astype(np.float32)
             for k, s in enumerate([(32, 48), (48, 20)]))
-    for mode in ("f16", "refine_a", "split3", "split4", "bf16_split3", "fp8"):
+    for mode in ("f16", "refine_a", "split3", "split4", "bf16_split3", "bf16_split6", "fp8"):
         for alpha in (-1.75, 3.0):
             d = np.abs(oracle.reference(mode, A, B, alpha).value - oracle.exact(A, B, alpha))
             bnd = oracle.representation_bound(mode, A, B, alpha=alpha)

@@ -16,7 +16,7 @@ from gpu_util import DEV, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["f16", "bf16", "refine_a", "split3", "split4", "bf16_split3", "fp8", "f32"]
+MODES = ["f16", "bf16", "refine_a", "split3", "split4", "bf16_split3", "bf16_split6", "fp8", "f32"]
 
 
 @pytest.fixture(autouse=True)
