@@ -281,6 +281,41 @@ def copy_probe(nbytes: int) -> int:
     return 0
 
 
+def fused_legs(dev, sizes=(2048, 4096, 8192), reps: int = 8) -> dict:
+    """The refined modes from FP32 operands two ways, timed interleaved: the
+    default two-pass path (split pass into workspace planes, then the GEMM on
+    them) and the fused kernel that splits while staging its tiles (the last
+    configuration of the mode, no workspace).  Per mode and N: milliseconds
+    (median of per-launch times) and useful TFLOP/s."""
+    import torch
+
+    import paper_1803_04014_amd as mfg
+
+    out = {}
+    for n in sizes:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(n)
+        A = torch.randn((n, n), device=dev, generator=gen)
+        B = torch.randn((n, n), device=dev, generator=gen)
+        C = torch.zeros((n, n), device=dev)
+        fl = 2.0 * n ** 3
+        for mode in ("split3", "refine_a", "bf16_split3"):
+            fused = mfg.num_configs(mode) - 1
+            assert mfg.config_name(mode, fused).startswith("fused")
+            t = {"two_pass": [], "fused": []}
+            for _ in range(3):
+                t["two_pass"] += launch_times(lambda: mfg.gemm(A, B, C, 1.0, 0.0, mode=mode), reps, warm=2)
+                t["fused"] += launch_times(lambda: mfg.gemm(A, B, C, 1.0, 0.0, mode=mode, config=fused), reps, warm=2)
+            e = {}
+            for k, v in t.items():
+                st = rate_stats(fl, v)
+                e[k] = {"ms": round(fl / st["tflops_median"] / 1e9, 4), "tflops": st["tflops_median"]}
+            e["fused_over_two_pass"] = round(e["fused"]["ms"] / e["two_pass"]["ms"], 3)
+            out[f"{mode}_n{n}"] = e
+        del A, B, C
+    return out
+
+
 def kernel_only(mode: str, n: int, steps: int, warmup: int) -> int:
     """`steps` launches of one mode's GEMM at n^3 on operands already in the
     mode's preconverted form (C = A B + C, alpha = beta = 1): the run the MFMA
@@ -647,6 +682,8 @@ def main() -> int:
                     help="only turn four rocprofv3 --pmc output folders into the traffic record")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--grouped-only", action="store_true", help="only the grouped-plan legs (one JSON line)")
+    ap.add_argument("--fused-only", action="store_true",
+                    help="only the refined modes from FP32: two-pass against the fused kernel (one JSON line)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving legs (one JSON line)")
     ap.add_argument("--kernel-only", metavar="MODE", help="only time MODE's GEMM at N^3 on preconverted operands")
     ap.add_argument("--mfma-ceiling", action="store_true", help="only the register-only MFMA ceiling probe")
@@ -682,6 +719,11 @@ def main() -> int:
         import torch
 
         print(json.dumps(grouped_legs(timed, torch.device("cuda", 0))), flush=True)
+        return 0
+    if args.fused_only:
+        import torch
+
+        print(json.dumps({"fused_fp32_in": fused_legs(torch.device("cuda", 0))}), flush=True)
         return 0
 
     import numpy as np
@@ -905,6 +947,9 @@ def main() -> int:
         # refinement study inputs (normal, sign * 2^u) at 4096 and 8192
         log("bench: precision study")
         ex["precision_fp32_in"] = precision_legs(dev, not args.no_cpu)
+        # refined modes from FP32: two-pass against the fused split-while-staging kernel
+        log("bench: fused split")
+        ex["fused_fp32_in"] = fused_legs(dev, sizes=(4096, 8192))
         # the HBM-bound steps at N x N: operand rounding, split with FP64 norms,
         # FP8 tile quantisation, FP64 error norms (algorithmic bytes per element:
         # 4 + 2, 4 + 2 + 2, 4 + 1, 4 + 8)

@@ -140,7 +140,15 @@ int mfg_gemm(int64_t M, int64_t N, int64_t K,
  * (0 <= config < mfg_num_configs(mode)), or -1 for the tuned choice.  Every
  * configuration of a mode produces bitwise-identical results: they differ
  * only in how output tiles are assigned to workgroups, never in the order in
- * which an output element accumulates its products.  Used by the autotuner. */
+ * which an output element accumulates its products.  Used by the autotuner.
+ * For MFG_F16_REFINE_A, MFG_F16_SPLIT3 and MFG_BF16_SPLIT3 the last
+ * configuration is the fused kernel: it reads the FP32 operands and splits
+ * them while staging its tiles (paper Sec. V, Eq. R), so it converts nothing
+ * into a workspace; it needs FP32 operands (with MFG_IN_PRECONVERTED:
+ * MFG_ERR_UNSUPPORTED), K % 64 == 0, N % 4 == 0, N >= 4, 16-byte aligned A
+ * and B with lda and ldb multiples of 4 below 2^22, ldc < 2^24, and reports
+ * MFG_ERR_UNSUPPORTED otherwise.  Its results equal the other
+ * configurations' bitwise for operands without NaN. */
 int mfg_gemm_config(int64_t M, int64_t N, int64_t K,
                     const void* A, int64_t lda,
                     const void* B, int64_t ldb,
@@ -157,7 +165,9 @@ int mfg_gemm_config(int64_t M, int64_t N, int64_t K,
  * hipFree or other allocating call.  A call whose converted operands need
  * more than that (e.g. FP16 from FP32 beyond about M*K + K*N = 32 Mi
  * elements, the two-plane modes beyond half that) returns
- * MFG_ERR_UNSUPPORTED before anything is enqueued.  Every call on one device
+ * MFG_ERR_UNSUPPORTED before anything is enqueued -- except that REFINE_A,
+ * SPLIT3 and BF16_SPLIT3 then run the fused kernel (see mfg_gemm_config)
+ * when the shape allows it, which needs no array.  Every call on one device
  * shares that device's array and leaves its contents behind: calls that
  * overlap on one GPU (other streams, other threads) race, so the caller
  * orders them.  The first call on a device looks up the array's address

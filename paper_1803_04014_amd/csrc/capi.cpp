@@ -194,6 +194,24 @@ static int gemm_impl(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
 
     // 16-bit modes
     const int kind = kind_of(m);
+    const int n16 = num_configs16(kind);  // configurations n16.. are the fused FP32-input kernels
+    if (config >= n16 + num_configs_fused(kind)) return MFG_ERR_INVALID_ARG;
+    if (!pre) {
+        const FusedArgs fa{M, N, K, static_cast<const float*>(A), static_cast<const float*>(B), C, lda, ldb, ldc,
+                           alpha, beta};
+        int fc = config >= n16 ? config - n16 : -1;
+        if (config < 0) {
+            const int t = tuned_lookup(m, M, N, K);
+            if (t >= n16 && fused_ok(kind, t - n16, fa)) fc = t - n16;
+            // allocation-free call whose planes would not fit its array: the
+            // fused kernel needs none
+            const int64_t planes = (npa(m) * up(M * up(K, 8), 128) + npb(m) * up(K * up(N, 8), 128)) * 2;
+            if (fc < 0 && ext && planes > (int64_t)ext->cap && fused_ok(kind, 0, fa)) fc = 0;
+        }
+        if (fc >= 0) return launch_gemm_fused(kind, fc, fa, s);
+    } else if (config >= n16) {
+        return MFG_ERR_UNSUPPORTED;  // the fused kernels read FP32 operands
+    }
     Gemm16Args a{};
     a.M = M, a.N = N, a.K = K, a.C = C, a.ldc = ldc, a.alpha = alpha, a.beta = beta;
     if (pre) {
@@ -275,7 +293,7 @@ extern "C" int mfg_num_configs(int mode) {
     if (m == MFG_F32) return num_configs_f32();
     if (m == MFG_FP8_E4M3) return num_configs_f8();
     const int k = kind_of(m);
-    return k < 0 ? MFG_ERR_INVALID_ARG : num_configs16(k);
+    return k < 0 ? MFG_ERR_INVALID_ARG : num_configs16(k) + num_configs_fused(k);
 }
 
 extern "C" int mfg_config_name(int mode, int config, char* buf, int n) {
@@ -284,7 +302,10 @@ extern "C" int mfg_config_name(int mode, int config, char* buf, int n) {
     const char* name = nullptr;
     if (m == MFG_F32) name = config_f32_name(config);
     else if (m == MFG_FP8_E4M3) name = config_f8_name(config);
-    else if (kind_of(m) >= 0) name = config16_name(kind_of(m), config);
+    else if (kind_of(m) >= 0) {
+        const int k = kind_of(m), n16 = num_configs16(k);
+        name = config < n16 ? config16_name(k, config) : config_fused_name(k, config - n16);
+    }
     if (!name || !buf || n <= 0) return MFG_ERR_INVALID_ARG;
     std::strncpy(buf, name, (size_t)n - 1);
     buf[n - 1] = '\0';
@@ -303,6 +324,11 @@ extern "C" int mfg_tune_lookup(int64_t M, int64_t N, int64_t K, int mode) {
         return (t >= 0 && t < num_configs_f8()) ? t : pick_config_f8(M, N, K, true);
     }
     if (m == MFG_BF16_SPLIT6) return choose_split6(-1, M, N, K, N, true);
+    if (!(mode & MFG_IN_PRECONVERTED)) {  // FP32 operands: a tuned fused kernel where the shape allows it
+        const int k = kind_of(m), n16 = num_configs16(k), t = tuned_lookup(m, M, N, K);
+        if (t >= n16 && t < n16 + num_configs_fused(k) && K % 64 == 0 && K > 0 && N % 8 == 0 && N >= 8 && M >= 1)
+            return t;
+    }
     return choose16(m, -1, M, N, K, N, true);
 }
 

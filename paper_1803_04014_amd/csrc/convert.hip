@@ -23,6 +23,7 @@
 // grid fixed by the shape and a fixed combining order: deterministic.
 #include <cmath>
 
+#include "cvt.h"
 #include "device.h"
 #include "internal.h"
 
@@ -31,20 +32,6 @@ namespace mfg {
 constexpr int kEltThreads = 256;
 constexpr int kColsPerThread = 4;
 constexpr int kColsPerBlock = kEltThreads * kColsPerThread;
-
-__device__ __forceinline__ uint16_t f32_to_f16_bits(float x) {
-    return __builtin_bit_cast(uint16_t, (_Float16)x);  // v_cvt_f16_f32, RNE
-}
-
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x0040u);  // quiet NaN
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float f16_bits_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
-__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 
 // OCP E4M3 ("fn": no infinity, S.1111.111 = NaN, max 448), RNE, saturating.
 __device__ __forceinline__ uint8_t f32_to_e4m3_sat(float v) {

@@ -85,6 +85,21 @@ int launch_gemm16(int kind, int cfg, const Gemm16Args& a, int64_t batch, bool ve
 // default.  vec_ok: 16-byte aligned rows of A and B (FP8: of A's codes).
 bool config16_ok(int kind, int cfg, int64_t M, int64_t N, int64_t K, int64_t ldc, bool vec_ok);
 bool config_f32_ok(int cfg, int64_t ldc, bool vec_ok);
+
+// Refined GEMMs straight from FP32 operands, split while staged (fused.hip).
+// Their configurations follow the plane kernels' in a kind's menu.
+struct FusedArgs {
+    int64_t M, N, K;
+    const float* A;
+    const float* B;
+    float* C;
+    int64_t lda, ldb, ldc;
+    float alpha, beta;
+};
+int num_configs_fused(int kind);
+const char* config_fused_name(int kind, int cfg);
+bool fused_ok(int kind, int cfg, const FusedArgs& a);
+int launch_gemm_fused(int kind, int cfg, const FusedArgs& a, hipStream_t s);
 bool config_f8_ok(int cfg, int64_t M, int64_t N, int64_t K, int64_t ldc, bool vec_ok);
 
 int num_configs_f32();
