@@ -630,6 +630,104 @@ def precision_legs(dev, cpu: bool) -> dict:
     return out
 
 
+def grouped_problem_set(dev, mode: str, seed: int = 6, count: int = 4096, lo: int = 16, hi: int = 512):
+    """The grouped workload: `count` problems with M, N, K log-uniform in [lo, hi]
+    (seed), FP16 uniform[-1, 1] operands in the mode's preconverted form (ld
+    rounded up to 8; head and residual planes for the refined modes), FP32 C."""
+    import torch
+
+    import workloads
+
+    two_a, two_b = mode != "f16", mode in ("split3", "split4")
+    probs = []
+    for (m_, n_, k_) in workloads.loguniform_dims(seed, count, lo, hi):
+        m_, n_, k_ = int(m_), int(n_), int(k_)
+        lda, ldb = -(-k_ // 8) * 8, -(-n_ // 8) * 8
+        a = torch.empty(((2 if two_a else 1) * m_, lda), dtype=torch.float16, device=dev).uniform_(-1, 1)
+        b = torch.empty(((2 if two_b else 1) * k_, ldb), dtype=torch.float16, device=dev).uniform_(-1, 1)
+        probs.append((a[:m_, :k_], b[:k_, :n_], torch.empty((m_, n_), dtype=torch.float32, device=dev)))
+    return probs
+
+
+def grouped_autotune_leg(dev) -> dict:
+    """The grouped tile-class tuner on the 4096-problem mix of F16 and SPLIT3
+    (it records the fastest class for every size bucket of the mix), then the
+    default plan against the one built after tuning: when they launch the same
+    classes there is one timing and no gain, else both are timed interleaved
+    as HIP graph replays after the same warm-up."""
+    import numpy as np
+
+    import paper_1803_04014_amd as mfg
+
+    out = {}
+    for mode in ("f16", "split3"):
+        mfg.lib().mfg_tune_clear()
+        probs = grouped_problem_set(dev, mode)
+        default = mfg.GroupedPlan(probs, mode)
+        best, tms = mfg.grouped_autotune(probs, mode, reps=5)
+        tuned = mfg.GroupedPlan(probs, mode)
+        e = {"classes": mfg.grouped_tile_classes(mode), "default_plan": {str(k): v for k, v in default.classes().items()},
+             "tuner_best": best, "tuner_us": round(tms * 1e3, 1),
+             "tuned_plan": {str(k): v for k, v in tuned.classes().items()}}
+        run_d, run_t = (lambda: default.graph_launch(1.0, 0.0)), (lambda: tuned.graph_launch(1.0, 0.0))
+        if default.classes() == tuned.classes():
+            e.update({"same_as_default": True, "us": round(float(np.median(launch_times(run_d, 20, warm=60))) * 1e3, 1)})
+        else:
+            td, tt = launch_times(run_d, 5, warm=60), launch_times(run_t, 5, warm=60)
+            for _ in range(3):
+                td += launch_times(run_d, 5, warm=5)
+                tt += launch_times(run_t, 5, warm=5)
+            e.update({"same_as_default": False, "default_us": round(float(np.median(td)) * 1e3, 1),
+                      "tuned_us": round(float(np.median(tt)) * 1e3, 1)})
+        out[mode] = e
+        default.close()
+        tuned.close()
+        del probs
+    mfg.lib().mfg_tune_clear()
+    return out
+
+
+def write_tune_table(path: str) -> int:
+    """Tune and save the table shipped with the library (MFG_TUNE_TABLE): the
+    GEMM configuration for F16 (preconverted) at 4096^3, 8192 x 2048 x 4096,
+    2048 x 2048 x 8192 and 1536^3, and for SPLIT3 and REFINE_A from FP32 at
+    2048^3 and 4096^3 (the two-pass configurations against the fused kernel);
+    the grouped tile class for the F16 and SPLIT3 4096-problem mixes."""
+    import torch
+
+    import paper_1803_04014_amd as mfg
+
+    dev = torch.device("cuda", 0)
+    mfg.lib().mfg_tune_clear()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    A32 = torch.rand((8192, 8192), device=dev, generator=gen) * 2 - 1
+    B32 = torch.rand((8192, 8192), device=dev, generator=gen) * 2 - 1
+    A16, B16 = A32.half(), B32.half()
+    rows = []
+    for (m_, n_, k_) in ((4096, 4096, 4096), (8192, 2048, 4096), (2048, 2048, 8192), (1536, 1536, 1536)):
+        a, b = A16[:m_, :k_].contiguous(), B16[:k_, :n_].contiguous()
+        c = torch.empty((m_, n_), dtype=torch.float32, device=dev)
+        best, ms = mfg.autotune(a, b, c, "f16", reps=3, preconverted=True)
+        rows.append({"mode": "f16", "shape": [m_, n_, k_], "config": mfg.config_name("f16", best), "ms": round(ms, 4)})
+    for mode in ("split3", "refine_a"):
+        for n in (2048, 4096):
+            a, b = A32[:n, :n].contiguous(), B32[:n, :n].contiguous()
+            c = torch.empty((n, n), dtype=torch.float32, device=dev)
+            best, ms = mfg.autotune(a, b, c, mode, reps=3)
+            rows.append({"mode": mode, "shape": [n, n, n], "config": mfg.config_name(mode, best), "ms": round(ms, 4)})
+    del A32, B32, A16, B16
+    for mode in ("f16", "split3"):
+        probs = grouped_problem_set(dev, mode)
+        best, ms = mfg.grouped_autotune(probs, mode, reps=5)
+        rows.append({"mode": mode, "grouped_4096_tile": best, "us": round(ms * 1e3, 1)})
+        del probs
+    st = mfg.lib().mfg_tune_save(path.encode())
+    print(json.dumps({"tune_table": path, "status": st, "entries": rows}), flush=True)
+    mfg.lib().mfg_tune_clear()
+    return 0 if st == 0 else 1
+
+
 def autotune_leg(dA, dB, dev) -> dict:
     """The autotuner on a few FP16 shapes: the default configuration against the
     tuned one, timed interleaved (default, tuned, default, ...) after the same
@@ -682,6 +780,7 @@ def main() -> int:
                     help="only turn four rocprofv3 --pmc output folders into the traffic record")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--grouped-only", action="store_true", help="only the grouped-plan legs (one JSON line)")
+    ap.add_argument("--write-tune-table", metavar="PATH", help="only tune and save the shipped tuned table")
     ap.add_argument("--fused-only", action="store_true",
                     help="only the refined modes from FP32: two-pass against the fused kernel (one JSON line)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving legs (one JSON line)")
@@ -720,6 +819,8 @@ def main() -> int:
 
         print(json.dumps(grouped_legs(timed, torch.device("cuda", 0))), flush=True)
         return 0
+    if args.write_tune_table:
+        return write_tune_table(args.write_tune_table)
     if args.fused_only:
         import torch
 
@@ -998,6 +1099,8 @@ def main() -> int:
                                                for cnt in (1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18)}
         log("bench: autotuner")
         ex["autotune_f16"] = autotune_leg(dA, dB, dev)
+        log("bench: grouped tile-class tuner")
+        ex["autotune_grouped"] = grouped_autotune_leg(dev)
         log("bench: grouped")
         ex.update(grouped_legs(timed, dev))
         log("bench: MFMA ceiling probe")

@@ -233,10 +233,17 @@ typedef struct mfg_problem {
 typedef struct mfg_grouped_plan mfg_grouped_plan;
 
 /* Build a plan: validates every problem (M, N <= 2^24, K < 2^31), splits it
- * into 128 x 128 output tiles (64 x 64 in the refined modes; work items, one
- * workgroup each), orders them by
- * decreasing K, and uploads the work list: one self-contained record per
- * item (device memory owned by the plan).  Rows of A and B that are 16-byte
+ * into square output tiles of its tile class (work items, one workgroup
+ * each), orders each class's items by decreasing K, and uploads the work
+ * list: one self-contained record per item (device memory owned by the
+ * plan).  Tile classes (mfg_grouped_tile_classes): 128 and 64 for F16 /
+ * BF16 / REFINE_A / SPLIT3 / BF16_SPLIT3, 64 for SPLIT4.  A problem takes
+ * the class the tuned table names for its mode and size bucket (entries of
+ * mode 32 + mode, config = tile side, written by mfg_grouped_autotune or
+ * loaded with mfg_tune_load), else the default: 128 for F16 / BF16, 64 for
+ * the refined modes.  A run launches the grouped kernel once per class
+ * present; a class that would carry under a quarter of the plan's flops
+ * runs in the other class instead (each launch adds its own tail).  Rows of A and B that are 16-byte
  * aligned with ld a multiple of 8 are read in whole 16-byte pieces, which may
  * touch up to 14 bytes past a row's last element (inside the same aligned 16
  * bytes, never another page); those bytes never reach a result.
@@ -255,6 +262,22 @@ int mfg_grouped_graph_launch(mfg_grouped_plan* plan, float alpha, float beta, vo
 int mfg_grouped_plan_info(const mfg_grouped_plan* plan, double* flops, double* bytes,
                           int64_t* work_items);
 int mfg_grouped_plan_destroy(mfg_grouped_plan* plan);
+/* The grouped kernel's tile classes for `mode` (tile sides, the default
+ * first) into `tiles` (host, `max` entries); returns their number. */
+int mfg_grouped_tile_classes(int mode, int* tiles, int max);
+/* The classes a plan launches (tile sides) and their work items, into
+ * `tiles` and `items` (host, `max` entries each); returns their number. */
+int mfg_grouped_plan_classes(const mfg_grouped_plan* plan, int* tiles, int64_t* items, int max);
+/* Autotune the grouped tile class on the caller's problems (mode as for
+ * mfg_grouped_plan_create): each class is forced on all of them and timed
+ * over `reps` runs with HIP events after one warm-up run (alpha = 1,
+ * beta = 0: every C is overwritten); a class counts only if every output is
+ * bitwise that of the first class.  The fastest is stored in the tuned table
+ * for every size bucket among the problems (tune one bucket's problems to
+ * decide that bucket, or a workload's mix to decide all of its buckets) and
+ * in *best_tile (host), its mean time per run in *best_ms (host). */
+int mfg_grouped_autotune(int64_t count, const mfg_problem* problems, int mode, int reps, int* best_tile,
+                         float* best_ms, void* stream);
 
 /* ----------------------------------------------------- operand conversion
  * The paper rounds FP32 inputs to half precision before the matrix-unit

@@ -87,19 +87,41 @@ def gemm_batched(A, B, C, alpha: float = 1.0, beta: float = 0.0, mode="f16", pre
     check("mfg_gemm_batched", st)
 
 
+def _problems(problems):
+    """(A, B, C) device tensors -> a ctypes mfg_problem array."""
+    arr = (capi.mfg_problem * len(problems))()
+    for i, (A, B, C) in enumerate(problems):
+        M, K = A.shape
+        N = B.shape[1]
+        arr[i] = capi.mfg_problem(M, N, K, _ld(A), _ld(B), _ld(C), A.data_ptr(), B.data_ptr(), C.data_ptr())
+    return arr
+
+
+def grouped_tile_classes(mode="f16"):
+    """mfg_grouped_tile_classes: the grouped kernel's tile sides for `mode`, the default first."""
+    t = (ctypes.c_int * 4)()
+    n = check("mfg_grouped_tile_classes", lib().mfg_grouped_tile_classes(mode_of(mode), t, 4))
+    return [t[i] for i in range(n)]
+
+
+def grouped_autotune(problems, mode="f16", fp32_in=False, reps=5, stream=None):
+    """mfg_grouped_autotune over (A, B, C) problems of one size bucket: (best tile side, ms per run)."""
+    arr = _problems(problems)
+    best, ms = ctypes.c_int(), ctypes.c_float()
+    m = mode_of(mode) | (capi.MFG_IN_FP32 if fp32_in else 0)
+    check("mfg_grouped_autotune", lib().mfg_grouped_autotune(len(problems), arr, m, int(reps), ctypes.byref(best),
+                                                             ctypes.byref(ms), ctypes.c_void_p(_stream(stream))))
+    return best.value, ms.value
+
+
 class GroupedPlan:
     """mfg_grouped_plan_*: many GEMMs of different shapes in one persistent launch."""
 
     def __init__(self, problems, mode="f16", fp32_in=False):
         """`problems`: list of (A, B, C) 2-D device tensors (A: M x K, B: K x N, C: M x N); A and B
         in the mode's preconverted form, or FP32 with `fp32_in` (MFG_IN_FP32)."""
-        arr = (capi.mfg_problem * len(problems))()
-        self._keep = []
-        for i, (A, B, C) in enumerate(problems):
-            M, K = A.shape
-            N = B.shape[1]
-            arr[i] = capi.mfg_problem(M, N, K, _ld(A), _ld(B), _ld(C), A.data_ptr(), B.data_ptr(), C.data_ptr())
-            self._keep.append((A, B, C))
+        arr = _problems(problems)
+        self._keep = list(problems)
         h = ctypes.c_void_p()
         m = mode_of(mode) | (capi.MFG_IN_FP32 if fp32_in else 0)
         check("mfg_grouped_plan_create", lib().mfg_grouped_plan_create(len(problems), arr, m, ctypes.byref(h)))
@@ -117,6 +139,12 @@ class GroupedPlan:
         check("mfg_grouped_plan_info", lib().mfg_grouped_plan_info(self.handle, ctypes.byref(f), ctypes.byref(b),
                                                                    ctypes.byref(w)))
         return {"flops": f.value, "bytes": b.value, "work_items": w.value}
+
+    def classes(self):
+        """{tile side: work items} of the classes this plan launches."""
+        t, n = (ctypes.c_int * 2)(), (ctypes.c_int64 * 2)()
+        k = check("mfg_grouped_plan_classes", lib().mfg_grouped_plan_classes(self.handle, t, n, 2))
+        return {t[i]: n[i] for i in range(k)}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -91,6 +91,9 @@ SIGNATURES = {
     "mfg_grouped_graph_launch": (i32, [vp, f32, f32, vp]),
     "mfg_grouped_plan_info": (i32, [vp, P(f64), P(f64), P(i64)]),
     "mfg_grouped_plan_destroy": (i32, [vp]),
+    "mfg_grouped_tile_classes": (i32, [i32, P(i32), i32]),
+    "mfg_grouped_plan_classes": (i32, [vp, P(i32), P(i64), i32]),
+    "mfg_grouped_autotune": (i32, [i64, P(mfg_problem), i32, i32, P(i32), P(f32), vp]),
     "mfg_round_f16": (i32, [i64, i64, vp, i64, vp, i64, vp]),
     "mfg_round_bf16": (i32, [i64, i64, vp, i64, vp, i64, vp]),
     "mfg_split_f16": (i32, [i64, i64, vp, i64, vp, vp, i64, vp, vp]),

@@ -224,21 +224,22 @@ typedef __attribute__((address_space(1))) const uint16_t g_u16;
 typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
 typedef __attribute__((address_space(1))) const uint32_t g_u32;
 typedef __attribute__((address_space(1))) float g_f32;
-// Tile side and occupancy (workgroups per CU) of the grouped kernel per
-// kind.  LDS per workgroup is 256 * tile * (planes of A + planes of B) bytes:
-// F16 / BF16 at 128: 64 KB, <= 256 VGPRs, two per CU.  The refined kinds
-// stage a second plane, which at 128 would leave one workgroup per CU
-// (measured 2.9x the F16 time for SPLIT3, latency-bound); at 64 REFINE_A
-// takes 48 KB (three per CU, <= 168 VGPRs), SPLIT3 / SPLIT4 64 KB (two).
-template <int KIND>
-constexpr int grouped_tile_of() {
-    return KT<KIND>::NPA > 1 ? kGroupedTileRefined : kGroupedTile;
-}
-template <int KIND>
+// Tile classes of the grouped kernel: output tiles of TT x TT (one
+// workgroup, four wavefronts of TT/2 x TT/2), TT = 128 or 64, chosen per
+// problem (size bucket) when a plan is built.  LDS per workgroup is
+// 256 * TT * (planes of A + planes of B) bytes; occupancy (workgroups per CU):
+//   TT = 128: F16 / BF16 64 KB, two per CU (<= 256 VGPRs); the refined kinds
+//             128 KB, one (latency-bound: measured 2.9x the F16 time for
+//             SPLIT3 on mixed sizes, kept as a class for the tuner);
+//   TT = 64:  F16 / BF16 32 KB, four per CU (<= 128 VGPRs); REFINE_A 48 KB,
+//             three (<= 168 VGPRs); SPLIT3 / SPLIT4 / BF16_SPLIT3 64 KB, two.
+template <int KIND, int TT>
 constexpr int grouped_wg_per_cu() {
-    return grouped_tile_of<KIND>() == 128 ? 2 : (KT<KIND>::NPA + KT<KIND>::NPB == 3 ? 3 : 2);
+    constexpr int planes = KT<KIND>::NPA + KT<KIND>::NPB;
+    if constexpr (TT == 128) return planes == 2 ? 2 : 1;
+    return planes == 2 ? 4 : planes == 3 ? 3 : 2;
 }
-static_assert(kGroupedTile == 128 && kGroupedTileRefined == 64, "wavefront tiles of 2 (F16) or 1 MFMA blocks a side");
+static_assert(kGroupedTile == 128 && kGroupedTileRefined == 64, "default classes: 128 (F16, BF16), 64 (refined)");
 
 // One work record in scalar registers.
 struct GItem {
@@ -275,10 +276,11 @@ __device__ __forceinline__ void grouped_barrier() {
 
 // `planes` (refined kinds only): per work item, the element offsets of the
 // residual planes of A and B from their head planes.
-template <int KIND, bool VEC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_per_cu<KIND>()))) void gemm16_grouped(
+template <int KIND, bool VEC, int TT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_per_cu<KIND, TT>()))) void gemm16_grouped(
     const GroupedWork* work, const int64_t* planes, GroupedSplit split, float alpha, float beta) {
-    constexpr int TT = grouped_tile_of<KIND>(), TH = TT / 2;  // workgroup tile, wavefront tile
+    static_assert(TT == 64 || TT == 128, "tile classes of 64 and 128");
+    constexpr int TH = TT / 2;  // workgroup tile, wavefront tile
     constexpr int FM = TH / 32, FN = TH / 32;       // 32 x 32 MFMA blocks per wavefront
     constexpr int PA = TT / 32, PB = TT / 32;       // 16-byte pieces per thread and block: A, B
     constexpr int BPR = TT / 8;                     // pieces per B row
@@ -587,52 +589,73 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
     }
 }
 
-static int wg_per_cu(int kind) {
+template <int TT>
+static int wg_per_cu_tt(int kind) {
     switch (kind) {
-        case K_REFINE_A: return grouped_wg_per_cu<K_REFINE_A>();
-        case K_SPLIT3: return grouped_wg_per_cu<K_SPLIT3>();
-        case K_SPLIT4: return grouped_wg_per_cu<K_SPLIT4>();
-        case K_BF16_SPLIT3: return grouped_wg_per_cu<K_BF16_SPLIT3>();
-        case K_BF16: return grouped_wg_per_cu<K_BF16>();
-        default: return grouped_wg_per_cu<K_F16>();
+        case K_REFINE_A: return grouped_wg_per_cu<K_REFINE_A, TT>();
+        case K_SPLIT3: return grouped_wg_per_cu<K_SPLIT3, TT>();
+        case K_SPLIT4: return grouped_wg_per_cu<K_SPLIT4, TT>();
+        case K_BF16_SPLIT3: return grouped_wg_per_cu<K_BF16_SPLIT3, TT>();
+        case K_BF16: return grouped_wg_per_cu<K_BF16, TT>();
+        default: return grouped_wg_per_cu<K_F16, TT>();
     }
 }
 
-int grouped_grid(const GroupedSplit& split, int list, int kind) {
+int grouped_grid(const GroupedSplit& split, int list, int kind, int tile) {
     int64_t most = 0;  // the largest per-XCD range sets how many workgroups each XCD needs
     for (int x = 0; x < kXcds; ++x) most = std::max<int64_t>(most, split.off[list][x + 1] - split.off[list][x]);
-    const int64_t per_xcd =
-        std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)device_cu_count() / kXcds * wg_per_cu(kind)));
+    const int per_cu = tile == 128 ? wg_per_cu_tt<128>(kind) : wg_per_cu_tt<64>(kind);
+    const int64_t per_xcd = std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)device_cu_count() / kXcds * per_cu));
     return (int)(per_xcd * kXcds);
 }
 
-template <int KIND>
+template <int KIND, int TT>
 static void launch_grouped_kind(int list, dim3 grid, const GroupedWork* work, const int64_t* planes,
                                 const GroupedSplit& split, float alpha, float beta, hipStream_t s) {
     if (list == 0)
-        hipLaunchKernelGGL((gemm16_grouped<KIND, true>), grid, dim3(256), 0, s, work, planes, split, alpha, beta);
+        hipLaunchKernelGGL((gemm16_grouped<KIND, true, TT>), grid, dim3(256), 0, s, work, planes, split, alpha, beta);
     else
-        hipLaunchKernelGGL((gemm16_grouped<KIND, false>), grid, dim3(256), 0, s, work, planes, split, alpha, beta);
+        hipLaunchKernelGGL((gemm16_grouped<KIND, false, TT>), grid, dim3(256), 0, s, work, planes, split, alpha, beta);
 }
 
-int grouped_launch(int kind, const GroupedWork* work, const int64_t* planes, const GroupedSplit& split, float alpha,
-                   float beta, hipStream_t s) {
-    if (kind < K_F16 || kind > K_BF16_SPLIT3) return MFG_ERR_UNSUPPORTED;
+template <int TT>
+static void launch_grouped_tt(int kind, int list, dim3 grid, const GroupedWork* work, const int64_t* planes,
+                              const GroupedSplit& split, float alpha, float beta, hipStream_t s) {
+    switch (kind) {
+        case K_F16: launch_grouped_kind<K_F16, TT>(list, grid, work, planes, split, alpha, beta, s); break;
+        case K_BF16: launch_grouped_kind<K_BF16, TT>(list, grid, work, planes, split, alpha, beta, s); break;
+        case K_REFINE_A: launch_grouped_kind<K_REFINE_A, TT>(list, grid, work, planes, split, alpha, beta, s); break;
+        case K_SPLIT3: launch_grouped_kind<K_SPLIT3, TT>(list, grid, work, planes, split, alpha, beta, s); break;
+        case K_BF16_SPLIT3: launch_grouped_kind<K_BF16_SPLIT3, TT>(list, grid, work, planes, split, alpha, beta, s); break;
+        default:
+            if constexpr (TT == 64) launch_grouped_kind<K_SPLIT4, TT>(list, grid, work, planes, split, alpha, beta, s);
+            break;
+    }
+}
+
+// SPLIT4 at 128 (three accumulator blocks of 64 x 64 per wavefront) spills:
+// it has the 64 class only.
+bool grouped_tile_ok(int kind, int tile) { return tile == 64 || (tile == 128 && kind != K_SPLIT4); }
+
+int grouped_tiles(int kind, int* tiles) {
+    tiles[0] = grouped_tile(kind);
+    if (kind == K_SPLIT4) return 1;
+    tiles[1] = tiles[0] == 128 ? 64 : 128;
+    return 2;
+}
+
+int grouped_launch(int kind, int tile, const GroupedWork* work, const int64_t* planes, const GroupedSplit& split,
+                   float alpha, float beta, hipStream_t s) {
+    if (kind < K_F16 || kind > K_BF16_SPLIT3 || !grouped_tile_ok(kind, tile)) return MFG_ERR_UNSUPPORTED;
     if (kind >= K_REFINE_A && !planes) return MFG_ERR_INTERNAL;  // the refined kinds read residual planes
     if (fault_hit(kFaultLaunch)) return hip_fail(hipErrorLaunchFailure);  // injected (tests)
     for (int list = 0; list < 2; ++list) {
         if (split.off[list][kXcds] == split.off[list][0]) continue;  // empty list
-        const dim3 grid((unsigned)grouped_grid(split, list, kind));
-        switch (kind) {
-            case K_F16: launch_grouped_kind<K_F16>(list, grid, work, planes, split, alpha, beta, s); break;
-            case K_BF16: launch_grouped_kind<K_BF16>(list, grid, work, planes, split, alpha, beta, s); break;
-            case K_REFINE_A: launch_grouped_kind<K_REFINE_A>(list, grid, work, planes, split, alpha, beta, s); break;
-            case K_SPLIT3: launch_grouped_kind<K_SPLIT3>(list, grid, work, planes, split, alpha, beta, s); break;
-            case K_BF16_SPLIT3:
-                launch_grouped_kind<K_BF16_SPLIT3>(list, grid, work, planes, split, alpha, beta, s);
-                break;
-            default: launch_grouped_kind<K_SPLIT4>(list, grid, work, planes, split, alpha, beta, s); break;
-        }
+        const dim3 grid((unsigned)grouped_grid(split, list, kind, tile));
+        if (tile == 128)
+            launch_grouped_tt<128>(kind, list, grid, work, planes, split, alpha, beta, s);
+        else
+            launch_grouped_tt<64>(kind, list, grid, work, planes, split, alpha, beta, s);
         MFG_LAUNCH_CHECK();
     }
     return MFG_OK;

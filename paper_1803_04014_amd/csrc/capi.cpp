@@ -446,7 +446,11 @@ extern "C" int mfg_gemm_batched(int64_t count, int64_t M, int64_t N, int64_t K, 
 struct mfg_grouped_plan {
     int mode = 0, kind = 0, device = 0;
     int64_t count = 0, nwork = 0;
-    GroupedSplit split{};
+    // tile classes present in the plan: work items of class c are the range
+    // split[c] of the one work array (one launch per class)
+    int nclass = 0;
+    int tile[2] = {0, 0};
+    GroupedSplit split[2]{};
     GroupedWork* d_work = nullptr;
     int64_t* d_planes = nullptr;  // refined modes: residual-plane offsets per work item
     // MFG_IN_FP32: converted operands (plan-owned) and the conversion job list
@@ -487,7 +491,16 @@ static int upload(const std::vector<T>& h, T** d) {
     return MFG_OK;
 }
 
-static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, mfg_grouped_plan** out) {
+// The tile class a problem of mode m runs in: its size bucket's tuned entry
+// if there is a valid one, else the kind's default; `force` (> 0) overrides.
+static int grouped_class(int m, int kind, int64_t M, int64_t N, int64_t K, int force) {
+    if (force > 0) return force;
+    const int t = tuned_lookup(kGroupedTuneBase + m, M, N, K);
+    return (t > 0 && grouped_tile_ok(kind, t)) ? t : grouped_tile(kind);
+}
+
+static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, mfg_grouped_plan** out,
+                            int force_tile = 0) {
     if (!out || count < 0 || (count > 0 && !probs)) return MFG_ERR_INVALID_ARG;
     *out = nullptr;
     const int m = mode & MFG_MODE_MASK;
@@ -572,10 +585,44 @@ static int plan_create_impl(int64_t count, const mfg_problem* probs, int mode, m
         if (st != MFG_OK) return st;
         plan->ntasks = (int64_t)tasks.size();
     }
-    GroupedSplit split{};
+    // problems by tile class, then one work list per class, concatenated
+    const int kind = kind_of(m);
+    if (force_tile > 0 && !grouped_tile_ok(kind, force_tile)) return MFG_ERR_UNSUPPORTED;
+    int tiles[2];
+    const int ntiles = grouped_tiles(kind, tiles);
+    // Each class is one more launch with its own tail: a class carrying under
+    // a quarter of the plan's flops runs in the other one instead.
+    std::vector<int> cls((size_t)count);
+    double cflops[2] = {0.0, 0.0};
+    for (int64_t i = 0; i < count; ++i) {
+        const GroupedDesc& d = descs[(size_t)i];
+        cls[(size_t)i] = grouped_class(m, kind, d.M, d.N, d.K, force_tile);
+        cflops[cls[(size_t)i] == tiles[0] ? 0 : 1] += 2.0 * (double)d.M * (double)d.N * (double)d.K;
+    }
+    if (ntiles == 2 && cflops[0] > 0.0 && cflops[1] > 0.0) {
+        const int minor = cflops[0] < cflops[1] ? 0 : 1;
+        if (cflops[minor] < 0.25 * (cflops[0] + cflops[1]))
+            for (int& c : cls) c = tiles[1 - minor];
+    }
     std::vector<int64_t> planes;
-    build_grouped_work(descs.data(), count, work, split, two_a ? &planes : nullptr, grouped_tile(kind_of(m)));
-    plan->split = split, plan->nwork = (int64_t)work.size();
+    for (int c = 0; c < ntiles; ++c) {
+        std::vector<GroupedDesc> sub;
+        for (int64_t i = 0; i < count; ++i)
+            if (cls[(size_t)i] == tiles[c]) sub.push_back(descs[(size_t)i]);
+        if (sub.empty()) continue;
+        std::vector<GroupedWork> w;
+        std::vector<int64_t> pl;
+        GroupedSplit sp{};
+        build_grouped_work(sub.data(), (int64_t)sub.size(), w, sp, two_a ? &pl : nullptr, tiles[c]);
+        const int64_t base = (int64_t)work.size();
+        for (auto& o : sp.off)
+            for (auto& v : o) v += base;
+        const int k = plan->nclass++;
+        plan->tile[k] = tiles[c], plan->split[k] = sp;
+        work.insert(work.end(), w.begin(), w.end());
+        planes.insert(planes.end(), pl.begin(), pl.end());
+    }
+    plan->nwork = (int64_t)work.size();
     int st = upload(work, &plan->d_work);
     if (st == MFG_OK && two_a) st = upload(planes, &plan->d_planes);
     if (st != MFG_OK) return st;
@@ -590,12 +637,138 @@ static int plan_launch(mfg_grouped_plan* plan, float alpha, float beta, hipStrea
         const int st = launch_convert_jobs(plan->d_jobs, plan->d_tasks, plan->ntasks, s);
         if (st != MFG_OK) return st;
     }
-    return grouped_launch(plan->kind, plan->d_work, plan->d_planes, plan->split, alpha, beta, s);
+    for (int c = 0; c < plan->nclass; ++c) {
+        const int st = grouped_launch(plan->kind, plan->tile[c], plan->d_work, plan->d_planes, plan->split[c], alpha,
+                                      beta, s);
+        if (st != MFG_OK) return st;
+    }
+    return MFG_OK;
 }
 
 extern "C" int mfg_grouped_plan_create(int64_t count, const mfg_problem* problems, int mode,
                                        mfg_grouped_plan** out) {
     MFG_GUARD(plan_create_impl(count, problems, mode, out));
+}
+
+// Time the grouped kernel on the caller's problems with every tile class of
+// the mode forced on all of them (alpha = 1, beta = 0: C is output only),
+// check each class's outputs bitwise against the first class's, and record
+// the fastest for the size bucket of the first problem.
+static int grouped_autotune_impl(int64_t count, const mfg_problem* probs, int mode, int reps, int* best_tile,
+                                 float* best_ms, hipStream_t s) {
+    if (count < 1 || !probs || reps < 1) return MFG_ERR_INVALID_ARG;
+    const int m = mode & MFG_MODE_MASK;
+    if (m < 0 || m >= MFG_NUM_MODES || kind_of(m) < 0 || m == MFG_BF16_SPLIT6) return MFG_ERR_UNSUPPORTED;
+    const int kind = kind_of(m);
+    int tiles[2];
+    const int ntiles = grouped_tiles(kind, tiles);
+    int64_t total = 0;
+    std::vector<int64_t> roff((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        if (probs[i].M < 0 || probs[i].N < 0) return MFG_ERR_INVALID_ARG;
+        roff[(size_t)i] = total;
+        total += probs[i].M * probs[i].N;
+    }
+    float* ref = nullptr;
+    unsigned long long* cnt = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    mfg_grouped_plan* plan = nullptr;
+    auto cleanup = [&]() {
+        if (plan) plan_free(plan);
+        if (ref) (void)hipFree(ref);
+        if (cnt) (void)hipFree(cnt);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&ref, (size_t)std::max<int64_t>(total, 1) * sizeof(float)) != hipSuccess ||
+        hipMalloc(&cnt, (size_t)count * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return MFG_ERR_NO_MEMORY;
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return MFG_ERR_HIP;
+    }
+    int st = MFG_OK, best = 0;
+    float bms = 3.4e38f;
+    std::vector<unsigned long long> bad((size_t)count);
+    for (int c = 0; c < ntiles && st == MFG_OK; ++c) {
+        if (plan) plan_free(plan), plan = nullptr;
+        st = plan_create_impl(count, probs, mode, &plan, tiles[c]);
+        if (st != MFG_OK) break;
+        st = plan_launch(plan, 1.f, 0.f, s);  // warm-up, and the outputs checked below
+        float total_ms = 0.f;
+        for (int r = 0; r < reps && st == MFG_OK; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) st = MFG_ERR_HIP;
+            if (st == MFG_OK) st = plan_launch(plan, 1.f, 0.f, s);
+            if (st == MFG_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                st = MFG_ERR_HIP;
+            float ms = 0.f;
+            if (st == MFG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MFG_ERR_HIP;
+            total_ms += ms;
+        }
+        for (int64_t i = 0; i < count && st == MFG_OK; ++i) {
+            const mfg_problem& p = probs[i];
+            if (p.M == 0 || p.N == 0) continue;
+            float* r = ref + roff[(size_t)i];
+            if (c == 0) {
+                if (hipMemcpy2DAsync(r, (size_t)p.N * 4, p.C, (size_t)p.ldc * 4, (size_t)p.N * 4, (size_t)p.M,
+                                     hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    st = MFG_ERR_HIP;
+            } else {
+                st = launch_count_mismatch(p.M, p.N, static_cast<const float*>(p.C), p.ldc, r, p.N, cnt + i, s);
+            }
+        }
+        if (st != MFG_OK) break;
+        bool same = true;
+        if (c > 0) {
+            if (hipMemcpyAsync(bad.data(), cnt, (size_t)count * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                st = MFG_ERR_HIP;
+                break;
+            }
+            for (int64_t i = 0; i < count; ++i)
+                if (probs[i].M > 0 && probs[i].N > 0 && bad[(size_t)i] != 0) same = false;
+        }
+        const float avg = total_ms / reps;
+        if (same && avg < bms) bms = avg, best = tiles[c];
+    }
+    cleanup();
+    if (st != MFG_OK) return st;
+    for (int64_t i = 0; i < count; ++i) tuned_store(kGroupedTuneBase + m, probs[i].M, probs[i].N, probs[i].K, best);
+    if (best_tile) *best_tile = best;
+    if (best_ms) *best_ms = bms;
+    return MFG_OK;
+}
+
+extern "C" int mfg_grouped_autotune(int64_t count, const mfg_problem* problems, int mode, int reps, int* best_tile,
+                                    float* best_ms, void* stream) {
+    MFG_GUARD(grouped_autotune_impl(count, problems, mode, reps, best_tile, best_ms, (hipStream_t)stream));
+}
+
+// The tile classes a plan launches and their work items.
+extern "C" int mfg_grouped_plan_classes(const mfg_grouped_plan* plan, int* tiles, int64_t* items, int max) {
+    if (!plan || max < 0 || (max > 0 && (!tiles || !items))) return MFG_ERR_INVALID_ARG;
+    for (int c = 0; c < plan->nclass && c < max; ++c) {
+        tiles[c] = plan->tile[c];
+        items[c] = plan->split[c].off[0][kXcds] - plan->split[c].off[0][0] + plan->split[c].off[1][kXcds] -
+                   plan->split[c].off[1][0];
+    }
+    return plan->nclass;
+}
+
+// Tile classes of a mode's grouped kernel (sides, the default first).
+extern "C" int mfg_grouped_tile_classes(int mode, int* tiles, int max) {
+    const int m = mode & MFG_MODE_MASK;
+    if (!tiles || max < 1 || m < 0 || m >= MFG_NUM_MODES) return MFG_ERR_INVALID_ARG;
+    const int kind = kind_of(m);
+    if (kind < 0 || m == MFG_BF16_SPLIT6) return MFG_ERR_UNSUPPORTED;
+    int t[2];
+    const int n = grouped_tiles(kind, t);
+    for (int i = 0; i < n && i < max; ++i) tiles[i] = t[i];
+    return n;
 }
 
 extern "C" int mfg_grouped_run(mfg_grouped_plan* plan, float alpha, float beta, void* stream) {

@@ -185,10 +185,18 @@ inline bool operand_ld_ok(int64_t lda, int64_t ldb) { return lda < kOperandLdLim
 // up to 256 rows per tile).
 constexpr int64_t kF8LdLimit = int64_t(1) << 24;
 
-constexpr int kGroupedTile = 128;        // output tile of a grouped work item (one workgroup): F16, BF16
-constexpr int kGroupedTileRefined = 64;  // REFINE_A, SPLIT3, SPLIT4 (two operand planes in LDS)
+// Output tile classes of the grouped kernel (one workgroup per tile): 128 or
+// 64 a side.  Without a tuned entry a problem takes its kind's default.
+constexpr int kGroupedTile = 128;        // default for F16, BF16
+constexpr int kGroupedTileRefined = 64;  // default for REFINE_A, SPLIT3, SPLIT4, BF16_SPLIT3 (two planes in LDS)
 inline int grouped_tile(int kind) { return kind >= K_REFINE_A ? kGroupedTileRefined : kGroupedTile; }
-// One kGroupedTile x kGroupedTile output tile with everything its workgroup
+bool grouped_tile_ok(int kind, int tile);
+// The classes of a kind, its default first; returns their number (<= 2).
+int grouped_tiles(int kind, int* tiles);
+// Tuned-table entries of grouped tile classes use mode kGroupedTuneBase + mode
+// (config = tile side).
+constexpr int kGroupedTuneBase = 32;
+// One tile x tile output tile with everything its workgroup
 // reads (16 dwords, so that 16 lanes fetch one record with one load each).
 struct GroupedWork {
     const uint16_t* A;  // row m0 of the problem's A
@@ -213,13 +221,14 @@ struct GroupedSplit {
 // `tile`: the output tile side of the kind that will run the list (grouped_tile).
 void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<GroupedWork>& work, GroupedSplit& split,
                         std::vector<int64_t>* planes = nullptr, int tile = kGroupedTile);
-// One launch per non-empty list (the grid of each from grouped_grid).  The
-// refined kinds (REFINE_A, SPLIT3, SPLIT4) need `planes` in device memory,
-// as build_grouped_work wrote it; F16 / BF16 ignore it (may be null).
-int grouped_launch(int kind, const GroupedWork* work, const int64_t* planes, const GroupedSplit& split, float alpha,
-                   float beta, hipStream_t s);
+// One launch per non-empty list (the grid of each from grouped_grid) of the
+// tile class `tile` (the one the list was built for).  The refined kinds need
+// `planes` in device memory, as build_grouped_work wrote it; F16 / BF16
+// ignore it (may be null).
+int grouped_launch(int kind, int tile, const GroupedWork* work, const int64_t* planes, const GroupedSplit& split,
+                   float alpha, float beta, hipStream_t s);
 // Workgroups of a list's launch (a multiple of kXcds).
-int grouped_grid(const GroupedSplit& split, int list, int kind);
+int grouped_grid(const GroupedSplit& split, int list, int kind, int tile);
 
 // Validation (validate.cpp; pure host code).
 int validate_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,

@@ -188,8 +188,10 @@ static int load_table_locked(const char* path) {
     char line[256];
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
-        if (std::sscanf(line, "%d %d %d %d %d", &mode, &mb, &nb, &kb, &cfg) != 5 || mode < 0 ||
-            mode >= MFG_NUM_MODES || cfg < 0) {
+        const int got = std::sscanf(line, "%d %d %d %d %d", &mode, &mb, &nb, &kb, &cfg);
+        const bool mode_ok = got == 5 && ((mode >= 0 && mode < MFG_NUM_MODES) ||
+                                          (mode >= kGroupedTuneBase && mode < kGroupedTuneBase + MFG_NUM_MODES));
+        if (!mode_ok || cfg < 0) {
             rc = MFG_ERR_INVALID_ARG;
             continue;
         }

@@ -391,7 +391,7 @@ int mfg_server::run_grouped(Slot& sl, const std::vector<Req*>& g) {
         MFG_HIP_CHECK(hipMemcpyAsync(sl.d_planes, sl.h_planes, sizeof(int64_t) * 2 * nw, hipMemcpyHostToDevice,
                                      sl.stream));
     }
-    return grouped_launch(kind, sl.d_work, two_a ? sl.d_planes : nullptr, split, g.front()->r.alpha,
+    return grouped_launch(kind, grouped_tile(kind), sl.d_work, two_a ? sl.d_planes : nullptr, split, g.front()->r.alpha,
                           g.front()->r.beta, sl.stream);
 }
 

@@ -118,6 +118,66 @@ def test_config_menus_and_names():
         assert mfg.lib().mfg_config_name(capi.MODE_BY_NAME[mode], n, ctypes.create_string_buffer(64), 64) != 0
 
 
+def test_grouped_tile_classes_and_tuned_entries(tmp_path):
+    L = mfg.lib()
+    assert mfg.grouped_tile_classes("f16") == [128, 64] and mfg.grouped_tile_classes("bf16") == [128, 64]
+    for m in ("refine_a", "split3", "bf16_split3"):
+        assert mfg.grouped_tile_classes(m) == [64, 128]
+    assert mfg.grouped_tile_classes("split4") == [64]
+    t = (ctypes.c_int * 2)()
+    for m in ("f32", "fp8", "bf16_split6"):
+        assert L.mfg_grouped_tile_classes(capi.MODE_BY_NAME[m], t, 2) == capi.MFG_ERR_UNSUPPORTED
+    assert L.mfg_grouped_tile_classes(capi.MFG_F16, None, 2) == capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_grouped_tile_classes(capi.MFG_F16, t, 0) == capi.MFG_ERR_INVALID_ARG
+    # grouped entries live at mode 32 + mode; modes beyond either range are rejected
+    L.mfg_tune_clear()
+    good = tmp_path / "g.txt"
+    good.write_text(f"{32 + capi.MFG_F16} 6 6 7 64\n{32 + capi.MFG_F16_SPLIT3} 8 8 8 128\n")
+    assert L.mfg_tune_load(str(good).encode()) == 0
+    out = tmp_path / "o.txt"
+    assert L.mfg_tune_save(str(out).encode()) == 0
+    rows = [ln.split() for ln in out.read_text().splitlines() if ln.strip() and not ln.startswith("#")]
+    assert ["33", "6", "6", "7", "64"] in rows and ["36", "8", "8", "8", "128"] in rows
+    for bad_mode in (31, 32 + capi.MFG_NUM_MODES):
+        bad = tmp_path / f"b{bad_mode}.txt"
+        bad.write_text(f"{bad_mode} 1 1 1 64\n")
+        assert L.mfg_tune_load(str(bad).encode()) == capi.MFG_ERR_INVALID_ARG
+    L.mfg_tune_clear()
+    # the tuner's argument checks come before any device work
+    best, ms = ctypes.c_int(), ctypes.c_float()
+    arr = (capi.mfg_problem * 1)()
+    assert L.mfg_grouped_autotune(0, arr, capi.MFG_F16, 3, ctypes.byref(best), ctypes.byref(ms), None) == \
+        capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_grouped_autotune(1, arr, capi.MFG_F16, 0, ctypes.byref(best), ctypes.byref(ms), None) == \
+        capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_grouped_autotune(1, arr, capi.MFG_F32, 3, ctypes.byref(best), ctypes.byref(ms), None) == \
+        capi.MFG_ERR_UNSUPPORTED
+
+
+def test_shipped_tuned_table_loads_and_names_valid_configs():
+    """The table shipped with the package (written on an MI355X by
+    bench.py --write-tune-table) loads, and every entry it holds names a
+    configuration (GEMM) or tile class (grouped) the mode has."""
+    import os
+    path = os.path.join(os.path.dirname(mfg.__file__), "tuned", "mi355x_gfx950.txt")
+    L = mfg.lib()
+    L.mfg_tune_clear()
+    assert L.mfg_tune_load(path.encode()) == 0
+    L.mfg_tune_clear()
+    n_gemm = n_grouped = 0
+    for ln in open(path):
+        if not ln.strip() or ln.startswith("#"):
+            continue
+        mode, mb, nb, kb, cfg = (int(x) for x in ln.split())
+        if mode >= 32:
+            assert cfg in mfg.grouped_tile_classes(mode - 32)
+            n_grouped += 1
+        else:
+            assert 0 <= cfg < mfg.num_configs(mode)
+            n_gemm += 1
+    assert n_gemm >= 4 and n_grouped >= 2
+
+
 def test_tuned_table_round_trip(tmp_path):
     L = mfg.lib()
     L.mfg_tune_clear()
