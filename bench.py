@@ -316,6 +316,47 @@ def fused_legs(dev, sizes=(2048, 4096, 8192), reps: int = 8) -> dict:
     return out
 
 
+def solve_legs(dev, sizes=(2048, 8192), modes=("f32", "split3", "f16")) -> dict:
+    """The iterative-refinement solver on the GEMM (mfg_solve_ir): FP64 A of
+    condition ~1e3 (Q1 diag(s) Q2^T, s log-spaced; n = 2048) or normal(0, 1)
+    plus sqrt(n) I (n = 8192: orthogonal factors of that size take minutes on
+    the host), one normal right-hand side, tolerance 2^-50; per mode the
+    wall time of one solve (after one untimed), of the LU alone, the
+    corrections made and the final backward error."""
+    import torch
+
+    import paper_1803_04014_amd as mfg
+    import workloads
+
+    out = {}
+    for n in sizes:
+        if n <= 2048:
+            A = torch.from_numpy(workloads.conditioned(5, n, 1e3)).to(dev)
+        else:
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(n)
+            A = torch.randn((n, n), dtype=torch.float64, device=dev, generator=gen)
+            A += n ** 0.5 * torch.eye(n, dtype=torch.float64, device=dev)
+        B = torch.randn((n, 1), dtype=torch.float64, device=dev)
+        for mode in modes:
+            X = torch.zeros((n, 1), dtype=torch.float64, device=dev)
+            mfg.solve_ir(A, B, X, mode=mode, max_iter=30)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = mfg.solve_ir(A, B, X, mode=mode, max_iter=30)
+            t1 = time.perf_counter()
+            a32 = A.float()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            mfg.lu_factor(a32, mode)
+            t3 = time.perf_counter()
+            out[f"{mode}_n{n}"] = {"solve_ms": round((t1 - t0) * 1e3, 1), "lu_ms": round((t3 - t2) * 1e3, 1),
+                                   "corrections": r["iters"], "backward_error": r["berr"]}
+            del a32
+        del A, B
+    return out
+
+
 def kernel_only(mode: str, n: int, steps: int, warmup: int) -> int:
     """`steps` launches of one mode's GEMM at n^3 on operands already in the
     mode's preconverted form (C = A B + C, alpha = beta = 1): the run the MFMA
@@ -781,6 +822,7 @@ def main() -> int:
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--grouped-only", action="store_true", help="only the grouped-plan legs (one JSON line)")
     ap.add_argument("--write-tune-table", metavar="PATH", help="only tune and save the shipped tuned table")
+    ap.add_argument("--solve-only", action="store_true", help="only the iterative-refinement solve legs")
     ap.add_argument("--fused-only", action="store_true",
                     help="only the refined modes from FP32: two-pass against the fused kernel (one JSON line)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving legs (one JSON line)")
@@ -821,6 +863,11 @@ def main() -> int:
         return 0
     if args.write_tune_table:
         return write_tune_table(args.write_tune_table)
+    if args.solve_only:
+        import torch
+
+        print(json.dumps({"solve_ir": solve_legs(torch.device("cuda", 0))}), flush=True)
+        return 0
     if args.fused_only:
         import torch
 
@@ -1048,6 +1095,8 @@ def main() -> int:
         # refinement study inputs (normal, sign * 2^u) at 4096 and 8192
         log("bench: precision study")
         ex["precision_fp32_in"] = precision_legs(dev, not args.no_cpu)
+        log("bench: iterative-refinement solve")
+        ex["solve_ir"] = solve_legs(dev)
         # refined modes from FP32: two-pass against the fused split-while-staging kernel
         log("bench: fused split")
         ex["fused_fp32_in"] = fused_legs(dev, sizes=(4096, 8192))

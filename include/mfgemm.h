@@ -279,6 +279,51 @@ int mfg_grouped_plan_classes(const mfg_grouped_plan* plan, int* tiles, int64_t* 
 int mfg_grouped_autotune(int64_t count, const mfg_problem* problems, int mode, int reps, int* best_tile,
                          float* best_ms, void* stream);
 
+/* ------------------------------------------- linear solve (a GEMM consumer)
+ * Mixed-precision iterative refinement for A X = B, the technique the paper
+ * sets its precision refinement beside (Sec. V): an LU factorisation whose
+ * O(n^3) trailing updates run through mfg_gemm in a chosen mode (the
+ * factorisation's precision), corrections solved in FP32 from FP64
+ * residuals, the solution accumulated in FP64.  Row-major throughout.
+ *
+ * mfg_lu_factor -- in-place LU with partial pivoting of the n x n FP32
+ * matrix A (device, lda >= max(1, n)): P A = L U with L unit lower (below
+ * the diagonal) and U upper (on and above it), right-looking by panels of
+ * 64 columns; each trailing update A22 -= L21 U12 is one mfg_gemm call with
+ * `mode` (any MFG_* mode without flags: MFG_F32 for an FP32 factorisation,
+ * MFG_F16 for the paper's half-precision products, a refined mode for
+ * FP32-level accuracy at matrix-core speed).  ipiv (device, n int32):
+ * row i was swapped with row ipiv[i] (0-based, in order i = 0 .. n-1).
+ * info (host, may be NULL): 0, or the 1-based index of the first exactly
+ * zero pivot (the factorisation is then complete but U is singular).  The
+ * call synchronises `stream` before it returns.
+ * Errors: MFG_ERR_INVALID_ARG (n < 0, lda < max(1, n), NULL pointers with
+ * n > 0, a mode with flags); MFG_ERR_UNSUPPORTED for n > 2^31 - 1; those
+ * of mfg_gemm. */
+int mfg_lu_factor(int64_t n, float* A, int64_t lda, int32_t* ipiv, int64_t* info, int mode, void* stream);
+/* mfg_lu_solve -- B = (L U)^-1 P B in place for the n x nrhs FP32 B (device,
+ * ldb >= max(1, nrhs)) with the factors and pivots of mfg_lu_factor: the
+ * permutation, then forward and backward substitution by 64-row blocks
+ * (off-diagonal updates by FP32 mfg_gemm).  Synchronises `stream`. */
+int mfg_lu_solve(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, const int32_t* ipiv, float* B, int64_t ldb,
+                 void* stream);
+/* mfg_solve_ir -- X (n x nrhs FP64, device, ldx >= max(1, nrhs)) solving
+ * A X = B for the FP64 n x n A and n x nrhs B (device): an FP32 copy of A
+ * is factored by mfg_lu_factor(mode); x0 = the FP32 solve of B; then while
+ * the normwise backward error max_j |b_j - A x_j|_inf / (|A|_inf |x_j|_inf
+ * + |b_j|_inf), residuals in FP64, exceeds `tol` and fewer than `max_iter`
+ * corrections were made: d = the FP32 solve of the residual, x += d in
+ * FP64.  iters (host, may be NULL): corrections made; berr (host, may be
+ * NULL): the final backward error; info (host, may be NULL): as for
+ * mfg_lu_factor (when nonzero nothing is solved and X is unchanged).
+ * Device workspace (n^2 FP32 + O(n nrhs)) is allocated and freed inside
+ * the call, which synchronises `stream`.
+ * Errors: as mfg_lu_factor, plus MFG_ERR_INVALID_ARG for nrhs < 0,
+ * ldb, ldx < max(1, nrhs), max_iter < 0, tol < 0 or NaN; MFG_ERR_NO_MEMORY. */
+int mfg_solve_ir(int64_t n, int64_t nrhs, const double* A, int64_t lda, const double* B, int64_t ldb, double* X,
+                 int64_t ldx, int mode, int max_iter, double tol, int* iters, double* berr, int64_t* info,
+                 void* stream);
+
 /* ----------------------------------------------------- operand conversion
  * The paper rounds FP32 inputs to half precision before the matrix-unit
  * GEMM and leaves that step out of its timings (Sec. VI).  These calls do

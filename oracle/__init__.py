@@ -19,6 +19,9 @@ What it computes (all in FP64 on the host):
   underflows into FP16 subnormals for |a| < 2^-3).
 * bounds: the kernel-parity tolerance and an a-priori bound on the
   distance of each mode from the exact product.
+* linear solve: LU with partial pivoting written out, the FP64 solve and
+  the normwise backward error, the references of the iterative-refinement
+  solver built on the GEMM (the technique Sec. V cites).
 
 The rounding rules and the FP64 GEMM live in ``oracle.c`` (built into
 ``liboracle.so``); everything here composes them.
@@ -402,6 +405,59 @@ def representation_bound(mode: str, A, B, alpha: float = 1.0, rows=None) -> np.n
     if extra is not None:
         bnd = bnd + gemm(extra[0], extra[1], rows=rows)
     return abs(alpha) * bnd
+
+
+# --------------------------------------------------------------------------
+# Linear solve (the consumer of Sec. V's refinement: iterative refinement)
+# --------------------------------------------------------------------------
+def lu_partial_pivot(A):
+    """Gaussian elimination with partial pivoting in FP64, written out: for each
+    column k the row of largest |value| on or below the diagonal (the first on
+    ties) is swapped into row k, the column below is divided by the pivot and
+    the trailing matrix gets the rank-1 update.  Returns (LU, piv): L unit lower
+    below the diagonal, U on and above it, piv[k] the row swapped with row k."""
+    a = np.array(A, dtype=np.float64)
+    n = a.shape[0]
+    piv = np.zeros(n, dtype=np.int64)
+    for k in range(n):
+        p = k + int(np.argmax(np.abs(a[k:, k])))  # argmax returns the first maximum
+        piv[k] = p
+        if p != k:
+            a[[k, p], :] = a[[p, k], :]
+        if a[k, k] != 0.0:
+            a[k + 1:, k] /= a[k, k]
+            a[k + 1:, k + 1:] -= np.outer(a[k + 1:, k], a[k, k + 1:])
+    return a, piv
+
+
+def apply_pivots(piv, X):
+    """P X for the sequential row swaps piv (row k with row piv[k], k = 0, 1, ...)."""
+    x = np.array(X, dtype=np.float64, copy=True)
+    for k, p in enumerate(piv):
+        if p != k:
+            x[[k, int(p)]] = x[[int(p), k]]
+    return x
+
+
+def solve(A, B):
+    """The solution of A X = B in FP64 (LAPACK's LU solve through numpy)."""
+    return np.linalg.solve(np.asarray(A, dtype=np.float64), np.asarray(B, dtype=np.float64))
+
+
+def backward_error(A, X, B) -> float:
+    """Normwise backward error of X: max over columns j of
+    |b_j - A x_j|_inf / (|A|_inf |x_j|_inf + |b_j|_inf), in FP64."""
+    A = np.asarray(A, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64).reshape(A.shape[0], -1)
+    B = np.asarray(B, dtype=np.float64).reshape(A.shape[0], -1)
+    R = B - A @ X
+    anorm = np.max(np.sum(np.abs(A), axis=1)) if A.size else 0.0
+    worst = 0.0
+    for j in range(X.shape[1]):
+        den = anorm * np.max(np.abs(X[:, j])) + np.max(np.abs(B[:, j]))
+        num = np.max(np.abs(R[:, j]))
+        worst = max(worst, num / den if den > 0 else (np.inf if num > 0 else 0.0))
+    return float(worst)
 
 
 def error_norms(C, Cref) -> dict:

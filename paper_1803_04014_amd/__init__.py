@@ -87,6 +87,34 @@ def gemm_batched(A, B, C, alpha: float = 1.0, beta: float = 0.0, mode="f16", pre
     check("mfg_gemm_batched", st)
 
 
+def lu_factor(A, mode="f32", stream=None):
+    """mfg_lu_factor on a square FP32 device tensor, in place: returns (ipiv int32 device tensor, info)."""
+    import torch
+
+    n = A.shape[0]
+    ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    info = ctypes.c_int64()
+    check("mfg_lu_factor", lib().mfg_lu_factor(n, _ptr(A), _ld(A), _ptr(ipiv), ctypes.byref(info), mode_of(mode),
+                                               ctypes.c_void_p(_stream(stream))))
+    return ipiv[:n], info.value
+
+
+def lu_solve(LU, ipiv, B, stream=None):
+    """mfg_lu_solve: B (n x nrhs FP32 device tensor) = (L U)^-1 P B in place."""
+    check("mfg_lu_solve", lib().mfg_lu_solve(LU.shape[0], B.shape[1], _ptr(LU), _ld(LU), _ptr(ipiv), _ptr(B), _ld(B),
+                                             ctypes.c_void_p(_stream(stream))))
+
+
+def solve_ir(A, B, X, mode="f32", max_iter=10, tol=2.0 ** -50, stream=None):
+    """mfg_solve_ir on FP64 device tensors A (n x n), B and X (n x nrhs): returns
+    {"iters", "berr", "info"}."""
+    it, be, info = ctypes.c_int(), ctypes.c_double(), ctypes.c_int64()
+    check("mfg_solve_ir", lib().mfg_solve_ir(A.shape[0], B.shape[1], _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(X), _ld(X),
+                                             mode_of(mode), int(max_iter), float(tol), ctypes.byref(it),
+                                             ctypes.byref(be), ctypes.byref(info), ctypes.c_void_p(_stream(stream))))
+    return {"iters": it.value, "berr": be.value, "info": info.value}
+
+
 def _problems(problems):
     """(A, B, C) device tensors -> a ctypes mfg_problem array."""
     arr = (capi.mfg_problem * len(problems))()

@@ -117,6 +117,9 @@ SIGNATURES = {
     "mfg_version": (ctypes.c_char_p, []),
     "mfg_validate_gemm": (i32, [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32]),
     "mfg_fault_inject": (i32, [i64, i64]),
+    "mfg_lu_factor": (i32, [i64, vp, i64, vp, P(i64), i32, vp]),
+    "mfg_lu_solve": (i32, [i64, i64, vp, i64, vp, vp, i64, vp]),
+    "mfg_solve_ir": (i32, [i64, i64, vp, i64, vp, i64, vp, i64, i32, i32, f64, P(i32), P(f64), P(i64), vp]),
     "mfg_probe_mfma": (i32, [i32, vp, i64, i64, vp, P(f64), vp]),
 }
 

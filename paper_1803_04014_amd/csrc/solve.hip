@@ -1,0 +1,649 @@
+// solve.hip -- a consumer of the GEMM: mixed-precision iterative refinement
+// for A X = B (the technique the paper puts its precision refinement next
+// to, Sec. V), with the O(n^3) work of the factorisation on the matrix
+// cores through mfg_gemm.
+//
+//   LU:  right-looking blocked LU with partial pivoting of an FP32 copy of
+//        A, panels of kNb = 64 columns: the panel is factored by one
+//        workgroup (column by column: pivot search, row swap, scaling,
+//        rank-1 update of the panel), its row swaps are applied to the rest
+//        of the matrix, the block row is solved with the panel's unit lower
+//        triangle (U12 = L11^-1 A12), and the trailing matrix is updated
+//        A22 -= L21 U12 by one mfg_gemm call in the caller's mode (F32, F16,
+//        or a refined split: the precision of the factorisation).
+//   solve with the factors: the row permutation (one gather), then forward
+//        and backward substitution by blocks of kNb rows: a diagonal block by
+//        one workgroup, the rest of the right-hand side updated by an FP32
+//        mfg_gemm.
+//   refinement: x0 from the factors; then r = b - A x in FP64, the normwise
+//        backward error max_j |r_j|_inf / (|A|_inf |x_j|_inf + |b_j|_inf),
+//        and while it is above the tolerance a correction d solved in FP32
+//        from r and x += d in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+#include "runtime.h"
+
+namespace mfg {
+
+namespace {
+
+constexpr int kNb = 64;
+constexpr int kPanelThreads = 1024;
+
+// One panel A[j:n, j:j+w] (w <= kNb), factored in place with partial pivoting.
+// ipiv[j + c] receives the row swapped with row j + c (0-based); info (if no
+// earlier column had one) the 1-based index of the first exactly-zero pivot.
+__global__ __launch_bounds__(kPanelThreads) void lu_panel(int64_t n, float* A, int64_t lda, int64_t j, int w,
+                                                         int32_t* ipiv, int32_t* info) {
+    __shared__ float prow[kNb];
+    __shared__ float wv[kPanelThreads / 64];
+    __shared__ int64_t wi[kPanelThreads / 64];
+    __shared__ int64_t piv;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int c = 0; c < w; ++c) {
+        const int64_t col = j + c;
+        // pivot: the largest |A[r, col]| over r >= col, the first such row on ties
+        float best = -1.0f;
+        int64_t bi = n;
+        for (int64_t r = col + tid; r < n; r += kPanelThreads) {
+            const float v = fabsf(A[r * lda + col]);
+            if (v > best) best = v, bi = r;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const float ov = __shfl_xor(best, off);
+            const int64_t oi = __shfl_xor(bi, off);
+            if (ov > best || (ov == best && oi < bi)) best = ov, bi = oi;
+        }
+        if (lane == 0) wv[wave] = best, wi[wave] = bi;
+        __syncthreads();
+        if (tid == 0) {
+            float b = wv[0];
+            int64_t i = wi[0];
+            for (int q = 1; q < kPanelThreads / 64; ++q)
+                if (wv[q] > b || (wv[q] == b && wi[q] < i)) b = wv[q], i = wi[q];
+            if (i >= n) i = col;  // (a column of NaNs only: keep the diagonal)
+            piv = i;
+            ipiv[col] = (int32_t)i;
+            if (A[i * lda + col] == 0.0f && *info == 0) *info = (int32_t)(col + 1);
+        }
+        __syncthreads();
+        const int64_t p = piv;
+        if (p != col && tid < w) {
+            const float t = A[col * lda + j + tid];
+            A[col * lda + j + tid] = A[p * lda + j + tid];
+            A[p * lda + j + tid] = t;
+        }
+        __syncthreads();
+        if (tid < w) prow[tid] = A[col * lda + j + tid];
+        __syncthreads();
+        const float pv = prow[c];
+        if (pv != 0.0f) {
+            for (int64_t r = col + 1 + tid; r < n; r += kPanelThreads) {
+                float* row = A + r * lda + j;
+                const float l = row[c] / pv;
+                row[c] = l;
+                for (int cc = c + 1; cc < w; ++cc) row[cc] = __builtin_fmaf(-l, prow[cc], row[cc]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// A narrow panel A[j:n, j:j+w] (w <= 8) held in registers for all of its
+// columns: thread t owns rows j + t + kP8Threads q, q < kP8Rows (so
+// n - j <= kP8Threads kP8Rows).  Per column: the pivot (largest |value|,
+// first on ties) by a workgroup reduction, the swap of the two rows through
+// LDS, then scaling and the rank-1 update of each owned row in registers.
+// Same arithmetic, operation by operation, as lu_panel.
+constexpr int kP8 = 8, kP8Threads = 512, kP8Rows = 16;
+
+__global__ __launch_bounds__(kP8Threads) void lu_panel8(int64_t n, float* A, int64_t lda, int64_t j, int w,
+                                                       int32_t* ipiv, int32_t* info) {
+    __shared__ float pr[kP8], dr[kP8];
+    __shared__ float wv[kP8Threads / 64];
+    __shared__ int64_t wi[kP8Threads / 64];
+    __shared__ int64_t piv;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float x[kP8Rows][kP8];
+#pragma unroll
+    for (int q = 0; q < kP8Rows; ++q) {
+        const int64_t r = j + tid + (int64_t)kP8Threads * q;
+#pragma unroll
+        for (int c = 0; c < kP8; ++c) x[q][c] = (r < n && c < w) ? A[r * lda + j + c] : 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < kP8; ++c) {
+        if (c >= w) break;
+        const int64_t col = j + c;
+        float best = -1.0f;
+        int64_t bi = n;
+#pragma unroll
+        for (int q = 0; q < kP8Rows; ++q) {
+            const int64_t r = j + tid + (int64_t)kP8Threads * q;
+            const float v = fabsf(x[q][c]);
+            if (r >= col && r < n && v > best) best = v, bi = r;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const float ov = __shfl_xor(best, off);
+            const int64_t oi = __shfl_xor(bi, off);
+            if (ov > best || (ov == best && oi < bi)) best = ov, bi = oi;
+        }
+        if (lane == 0) wv[wave] = best, wi[wave] = bi;
+        __syncthreads();
+        if (tid == 0) {
+            float b = wv[0];
+            int64_t i = wi[0];
+            for (int q = 1; q < kP8Threads / 64; ++q)
+                if (wv[q] > b || (wv[q] == b && wi[q] < i)) b = wv[q], i = wi[q];
+            if (i >= n) i = col;
+            piv = i;
+            ipiv[col] = (int32_t)i;
+        }
+        __syncthreads();
+        const int64_t p = piv;
+        // rows col and p: the owners publish them, then take each other's
+#pragma unroll
+        for (int q = 0; q < kP8Rows; ++q) {
+            const int64_t r = j + tid + (int64_t)kP8Threads * q;
+            if (r == p)
+#pragma unroll
+                for (int cc = 0; cc < kP8; ++cc) pr[cc] = x[q][cc];
+            if (r == col)
+#pragma unroll
+                for (int cc = 0; cc < kP8; ++cc) dr[cc] = x[q][cc];
+        }
+        __syncthreads();
+        if (p != col) {
+#pragma unroll
+            for (int q = 0; q < kP8Rows; ++q) {
+                const int64_t r = j + tid + (int64_t)kP8Threads * q;
+                if (r == p)
+#pragma unroll
+                    for (int cc = 0; cc < kP8; ++cc) x[q][cc] = dr[cc];
+                if (r == col)
+#pragma unroll
+                    for (int cc = 0; cc < kP8; ++cc) x[q][cc] = pr[cc];
+            }
+        }
+        const float pv = pr[c];  // the pivot row is now row col
+        if (tid == 0 && pv == 0.0f && *info == 0) *info = (int32_t)(col + 1);
+        if (pv != 0.0f) {
+#pragma unroll
+            for (int q = 0; q < kP8Rows; ++q) {
+                const int64_t r = j + tid + (int64_t)kP8Threads * q;
+                if (r > col && r < n) {
+                    const float l = x[q][c] / pv;
+                    x[q][c] = l;
+#pragma unroll
+                    for (int cc = c + 1; cc < kP8; ++cc) x[q][cc] = __builtin_fmaf(-l, pr[cc], x[q][cc]);
+                }
+            }
+        }
+        __syncthreads();  // pr / dr are rewritten by the next column
+    }
+#pragma unroll
+    for (int q = 0; q < kP8Rows; ++q) {
+        const int64_t r = j + tid + (int64_t)kP8Threads * q;
+#pragma unroll
+        for (int c = 0; c < kP8; ++c)
+            if (r < n && c < w) A[r * lda + j + c] = x[q][c];
+    }
+}
+
+// Row swaps ipiv[k], k in [k0, k0 + w), on the columns [c0, c1) except
+// [e0, e1), one thread per column, swaps in order.
+__global__ __launch_bounds__(256) void lu_laswp_range(float* A, int64_t lda, int64_t k0, int w, const int32_t* ipiv,
+                                                      int64_t c0, int64_t c1, int64_t e0, int64_t e1) {
+    const int64_t col = c0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (col >= c1 || (col >= e0 && col < e1)) return;
+    for (int c = 0; c < w; ++c) {
+        const int64_t k = k0 + c, p = ipiv[k];
+        if (p != k) {
+            const float t = A[k * lda + col];
+            A[k * lda + col] = A[p * lda + col];
+            A[p * lda + col] = t;
+        }
+    }
+}
+
+// U12 = L11^-1 A12 for rows [j, j + kP8) and columns [j + kP8, c1): L11 the
+// unit lower kP8 x kP8 block at (j, j).
+__global__ __launch_bounds__(256) void lu_trsm8(float* A, int64_t lda, int64_t j, int64_t c1) {
+    __shared__ float L[kP8][kP8];
+    if (threadIdx.x < kP8 * kP8) L[threadIdx.x / kP8][threadIdx.x % kP8] =
+        A[(j + threadIdx.x / kP8) * lda + j + threadIdx.x % kP8];
+    __syncthreads();
+    const int64_t col = j + kP8 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (col >= c1) return;
+    float x[kP8];
+#pragma unroll
+    for (int i = 0; i < kP8; ++i) x[i] = A[(j + i) * lda + col];
+#pragma unroll
+    for (int i = 1; i < kP8; ++i)
+#pragma unroll
+        for (int k = 0; k < i; ++k) x[i] = __builtin_fmaf(-L[i][k], x[k], x[i]);
+#pragma unroll
+    for (int i = 0; i < kP8; ++i) A[(j + i) * lda + col] = x[i];
+}
+
+// The panel's row swaps (rows j .. j+w-1 with ipiv[.]) on every column
+// outside the panel, one thread per column, swaps in order.
+__global__ __launch_bounds__(256) void lu_laswp(int64_t n, float* A, int64_t lda, int64_t j, int w,
+                                                const int32_t* ipiv) {
+    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (col >= n || (col >= j && col < j + w)) return;
+    for (int c = 0; c < w; ++c) {
+        const int64_t k = j + c, p = ipiv[k];
+        if (p != k) {
+            const float t = A[k * lda + col];
+            A[k * lda + col] = A[p * lda + col];
+            A[p * lda + col] = t;
+        }
+    }
+}
+
+// U12 = L11^-1 A12 for the block row A[j:j+kNb, j+kNb:n] (L11 unit lower,
+// kept in LDS), one thread per column, the column in registers.
+__global__ __launch_bounds__(256) void lu_trsm(int64_t n, float* A, int64_t lda, int64_t j) {
+    __shared__ float L[kNb][kNb + 1];
+    for (int e = threadIdx.x; e < kNb * kNb; e += 256) L[e / kNb][e % kNb] = A[(j + e / kNb) * lda + j + e % kNb];
+    __syncthreads();
+    const int64_t col = j + kNb + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (col >= n) return;
+    float x[kNb];
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) x[i] = A[(j + i) * lda + col];
+#pragma unroll
+    for (int i = 1; i < kNb; ++i)
+#pragma unroll
+        for (int k = 0; k < i; ++k) x[i] = __builtin_fmaf(-L[i][k], x[k], x[i]);
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) A[(j + i) * lda + col] = x[i];
+}
+
+// Diagonal block [s, s+w) of the factors solved for the right-hand sides
+// V[s:s+w, 0:nrhs] in place: unit lower (forward) or upper (backward, with
+// the diagonal).  One workgroup per right-hand side, thread i holding row i;
+// each finished unknown is passed to the others through LDS.
+template <bool LOWER>
+__global__ __launch_bounds__(kNb) void lu_trsv_block(const float* LU, int64_t ldlu, int64_t s, int w, float* V,
+                                                     int64_t ldv) {
+    __shared__ float xs[kNb];
+    const int i = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    const float* row = LU + (s + (i < w ? i : 0)) * ldlu + s;
+    float xi = i < w ? V[(s + i) * ldv + q] : 0.0f;
+    if constexpr (LOWER) {
+        for (int k = 0; k < w; ++k) {
+            if (i == k) xs[k] = xi;
+            __syncthreads();
+            if (i > k && i < w) xi = __builtin_fmaf(-row[k], xs[k], xi);
+        }
+    } else {
+        for (int k = w - 1; k >= 0; --k) {
+            if (i == k) xi = xi / row[k], xs[k] = xi;
+            __syncthreads();
+            if (i < k) xi = __builtin_fmaf(-row[k], xs[k], xi);
+        }
+    }
+    if (i < w) V[(s + i) * ldv + q] = xi;
+}
+
+// dst[i, :] = src[perm[i], :] (rows of nrhs FP32 values).
+__global__ __launch_bounds__(256) void gather_rows(int64_t n, int64_t nrhs, const int32_t* perm, const float* src,
+                                                   int64_t lds, float* dst, int64_t ldd) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * nrhs) return;
+    const int64_t i = e / nrhs, q = e % nrhs;
+    dst[i * ldd + q] = src[(int64_t)perm[i] * lds + q];
+}
+
+__global__ __launch_bounds__(256) void f64_to_f32(int64_t rows, int64_t cols, const double* X, int64_t ldx, float* Y,
+                                                  int64_t ldy) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= rows * cols) return;
+    const int64_t i = e / cols, q = e % cols;
+    Y[i * ldy + q] = (float)X[i * ldx + q];
+}
+
+// X = D (first) or X += D, X FP64, D FP32.
+__global__ __launch_bounds__(256) void accumulate_f64(int64_t rows, int64_t cols, const float* D, int64_t ldd,
+                                                      double* X, int64_t ldx, int first) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= rows * cols) return;
+    const int64_t i = e / cols, q = e % cols;
+    const double d = (double)D[i * ldd + q];
+    X[i * ldx + q] = first ? d : X[i * ldx + q] + d;
+}
+
+// R = B - A X in FP64: one wavefront per (row, right-hand side), lanes over K.
+__global__ __launch_bounds__(256) void residual_f64(int64_t n, int64_t nrhs, const double* A, int64_t lda,
+                                                   const double* X, int64_t ldx, const double* B, int64_t ldb,
+                                                   double* R, int64_t ldr) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= n * nrhs) return;
+    const int64_t i = w / nrhs, q = w % nrhs;
+    double acc = 0.0;
+    for (int64_t k = lane; k < n; k += 64) acc = fma(A[i * lda + k], X[k * ldx + q], acc);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) R[i * ldr + q] = B[i * ldb + q] - acc;
+}
+
+// Row sums of |A| (FP64), one wavefront per row.
+__global__ __launch_bounds__(256) void abs_row_sums(int64_t n, const double* A, int64_t lda, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int64_t k = lane; k < n; k += 64) acc += fabs(A[i * lda + k]);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) out[i] = acc;
+}
+
+// out[q] = max_i |V[i, q]| for each of the nrhs columns of V (one workgroup
+// per column); with rows_only (nrhs = 1 of a vector v), the max of v.
+__global__ __launch_bounds__(256) void col_abs_max(int64_t n, int64_t nrhs, const double* V, int64_t ldv,
+                                                   double* out) {
+    __shared__ double red[256];
+    const int64_t q = blockIdx.x;
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(V[i * ldv + q]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = red[0];
+}
+
+unsigned blocks(int64_t work, int per) { return (unsigned)std::max<int64_t>(1, (work + per - 1) / per); }
+
+bool factor_mode_ok(int mode) {
+    const int m = mode & MFG_MODE_MASK;
+    return (mode & ~MFG_MODE_MASK) == 0 && m >= 0 && m < MFG_NUM_MODES;
+}
+
+}  // namespace
+
+// Blocked LU (see the file comment).  A, ipiv, info: device.  A 64-wide
+// panel is itself factored by 8-column sub-panels held in registers
+// (lu_panel8), the sub-panel's swaps applied across the panel, its block
+// row solved and the rest of the panel updated by an FP32 mfg_gemm (K = 8):
+// the same elimination, with the panel's updates blocked.  Panels taller
+// than lu_panel8 holds go column by column (lu_panel).
+int lu_factor_impl(int64_t n, float* A, int64_t lda, int32_t* ipiv, int32_t* info, int mode, hipStream_t s) {
+    MFG_HIP_CHECK(hipMemsetAsync(info, 0, sizeof(int32_t), s));
+    for (int64_t j = 0; j < n; j += kNb) {
+        const int w = (int)std::min<int64_t>(kNb, n - j);
+        if (n - j <= (int64_t)kP8Threads * kP8Rows) {
+            for (int64_t jj = j; jj < j + w; jj += kP8) {
+                const int wi = (int)std::min<int64_t>(kP8, j + w - jj);
+                hipLaunchKernelGGL(lu_panel8, dim3(1), dim3(kP8Threads), 0, s, n, A, lda, jj, wi, ipiv, info);
+                MFG_LAUNCH_CHECK();
+                hipLaunchKernelGGL(lu_laswp_range, dim3(1), dim3(256), 0, s, A, lda, jj, wi, ipiv, j, j + w, jj,
+                                   jj + wi);
+                MFG_LAUNCH_CHECK();
+                const int64_t right = j + w - (jj + wi);  // columns of the panel right of the sub-panel
+                if (right <= 0) continue;                 // wi == kP8 from here on
+                hipLaunchKernelGGL(lu_trsm8, dim3(1), dim3(256), 0, s, A, lda, jj, j + w);
+                MFG_LAUNCH_CHECK();
+                const int64_t below = n - jj - wi;
+                if (below > 0) {
+                    const int st = mfg_gemm(below, right, wi, A + (jj + wi) * lda + jj, lda, A + jj * lda + jj + wi,
+                                            lda, A + (jj + wi) * lda + jj + wi, lda, -1.0f, 1.0f, MFG_F32, (void*)s);
+                    if (st != MFG_OK) return st;
+                }
+            }
+        } else {
+            hipLaunchKernelGGL(lu_panel, dim3(1), dim3(kPanelThreads), 0, s, n, A, lda, j, w, ipiv, info);
+            MFG_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(lu_laswp, dim3(blocks(n, 256)), dim3(256), 0, s, n, A, lda, j, w, ipiv);
+        MFG_LAUNCH_CHECK();
+        const int64_t rest = n - j - w;
+        if (rest <= 0) continue;  // w == kNb from here on
+        hipLaunchKernelGGL(lu_trsm, dim3(blocks(rest, 256)), dim3(256), 0, s, n, A, lda, j);
+        MFG_LAUNCH_CHECK();
+        // A22 -= L21 U12 on the matrix cores, in the factorisation's mode
+        float* a22 = A + (j + w) * lda + j + w;
+        const int st = mfg_gemm(rest, rest, w, A + (j + w) * lda + j, lda, A + j * lda + j + w, lda, a22, lda, -1.0f,
+                                1.0f, mode, (void*)s);
+        if (st != MFG_OK) return st;
+    }
+    return MFG_OK;
+}
+
+// The row permutation of the sequential swaps in ipiv (device), on the host.
+static int permutation(int64_t n, const int32_t* ipiv, std::vector<int32_t>& perm, hipStream_t s) {
+    std::vector<int32_t> piv((size_t)n);
+    MFG_HIP_CHECK(hipMemcpyAsync(piv.data(), ipiv, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+    MFG_HIP_CHECK(hipStreamSynchronize(s));
+    perm.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) perm[(size_t)i] = (int32_t)i;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t p = piv[(size_t)i];
+        if (p < i || p >= n) return MFG_ERR_INVALID_ARG;  // not a pivot sequence of a factorisation
+        std::swap(perm[(size_t)i], perm[(size_t)p]);
+    }
+    return MFG_OK;
+}
+
+// V = U^-1 L^-1 V (V: n x nrhs FP32, already permuted), FP32.
+static int lu_substitute(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, float* V, int64_t ldv,
+                         hipStream_t s) {
+    const dim3 g((unsigned)nrhs);
+    for (int64_t b = 0; b < n; b += kNb) {  // forward, unit lower
+        const int w = (int)std::min<int64_t>(kNb, n - b);
+        hipLaunchKernelGGL(lu_trsv_block<true>, g, dim3(kNb), 0, s, LU, ldlu, b, w, V, ldv);
+        MFG_LAUNCH_CHECK();
+        if (b + w < n) {
+            const int st = mfg_gemm(n - b - w, nrhs, w, LU + (b + w) * ldlu + b, ldlu, V + b * ldv, ldv,
+                                    V + (b + w) * ldv, ldv, -1.0f, 1.0f, MFG_F32, (void*)s);
+            if (st != MFG_OK) return st;
+        }
+    }
+    for (int64_t b = ((n - 1) / kNb) * kNb; b >= 0; b -= kNb) {  // backward, upper
+        const int w = (int)std::min<int64_t>(kNb, n - b);
+        hipLaunchKernelGGL(lu_trsv_block<false>, g, dim3(kNb), 0, s, LU, ldlu, b, w, V, ldv);
+        MFG_LAUNCH_CHECK();
+        if (b > 0) {
+            const int st = mfg_gemm(b, nrhs, w, LU + b, ldlu, V + b * ldv, ldv, V, ldv, -1.0f, 1.0f, MFG_F32,
+                                    (void*)s);
+            if (st != MFG_OK) return st;
+        }
+    }
+    return MFG_OK;
+}
+
+// X = (LU)^-1 P B with B, X n x nrhs FP32 (X may not alias B).
+static int lu_solve_impl(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, const int32_t* dperm, const float* B,
+                         int64_t ldb, float* X, int64_t ldx, hipStream_t s) {
+    hipLaunchKernelGGL(gather_rows, dim3(blocks(n * nrhs, 256)), dim3(256), 0, s, n, nrhs, dperm, B, ldb, X, ldx);
+    MFG_LAUNCH_CHECK();
+    return lu_substitute(n, nrhs, LU, ldlu, X, ldx, s);
+}
+
+}  // namespace mfg
+
+using namespace mfg;
+
+namespace {
+
+// Device buffers of one call, freed on every return path.
+struct Buffers {
+    std::vector<void*> ptrs;
+    template <class T>
+    int get(T** p, size_t count) {
+        *p = nullptr;
+        if (count == 0) count = 1;
+        if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return MFG_ERR_NO_MEMORY;
+        }
+        ptrs.push_back(*p);
+        return MFG_OK;
+    }
+    ~Buffers() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+};
+
+int lu_factor_api(int64_t n, float* A, int64_t lda, int32_t* ipiv, int64_t* info, int mode, hipStream_t s) {
+    if (n < 0 || lda < std::max<int64_t>(1, n) || (n > 0 && (!A || !ipiv)) || !factor_mode_ok(mode))
+        return MFG_ERR_INVALID_ARG;
+    if (n > INT32_MAX) return MFG_ERR_UNSUPPORTED;
+    if (info) *info = 0;
+    if (n == 0) return MFG_OK;
+    Buffers buf;
+    int32_t* dinfo = nullptr;
+    int st = buf.get(&dinfo, 1);
+    if (st == MFG_OK) st = lu_factor_impl(n, A, lda, ipiv, dinfo, mode, s);
+    if (st != MFG_OK) return st;
+    int32_t h = 0;
+    MFG_HIP_CHECK(hipMemcpyAsync(&h, dinfo, sizeof(h), hipMemcpyDeviceToHost, s));
+    MFG_HIP_CHECK(hipStreamSynchronize(s));  // before dinfo is freed
+    if (info) *info = h;
+    return MFG_OK;
+}
+
+int lu_solve_api(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, const int32_t* ipiv, float* B, int64_t ldb,
+                 hipStream_t s) {
+    if (n < 0 || nrhs < 0 || ldlu < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, nrhs) ||
+        (n > 0 && (!LU || !ipiv)) || (n > 0 && nrhs > 0 && !B))
+        return MFG_ERR_INVALID_ARG;
+    if (nrhs > INT32_MAX) return MFG_ERR_UNSUPPORTED;
+    if (n == 0 || nrhs == 0) return MFG_OK;
+    std::vector<int32_t> perm;
+    int st = permutation(n, ipiv, perm, s);
+    if (st != MFG_OK) return st;
+    Buffers buf;
+    int32_t* dperm = nullptr;
+    float* tmp = nullptr;
+    if ((st = buf.get(&dperm, (size_t)n)) != MFG_OK || (st = buf.get(&tmp, (size_t)(n * nrhs))) != MFG_OK) return st;
+    MFG_HIP_CHECK(hipMemcpyAsync(dperm, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    if ((st = lu_solve_impl(n, nrhs, LU, ldlu, dperm, B, ldb, tmp, nrhs, s)) != MFG_OK) return st;
+    MFG_HIP_CHECK(hipMemcpy2DAsync(B, (size_t)ldb * 4, tmp, (size_t)nrhs * 4, (size_t)nrhs * 4, (size_t)n,
+                                   hipMemcpyDeviceToDevice, s));
+    MFG_HIP_CHECK(hipStreamSynchronize(s));  // before the buffers are freed
+    return MFG_OK;
+}
+
+int solve_ir_api(int64_t n, int64_t nrhs, const double* A, int64_t lda, const double* B, int64_t ldb, double* X,
+                 int64_t ldx, int mode, int max_iter, double tol, int* iters, double* berr, int64_t* info,
+                 hipStream_t s) {
+    if (n < 0 || nrhs < 0 || lda < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, nrhs) ||
+        ldx < std::max<int64_t>(1, nrhs) || (n > 0 && !A) || (n > 0 && nrhs > 0 && (!B || !X)) ||
+        !factor_mode_ok(mode) || max_iter < 0 || !(tol >= 0.0))
+        return MFG_ERR_INVALID_ARG;
+    if (n > INT32_MAX || nrhs > INT32_MAX) return MFG_ERR_UNSUPPORTED;
+    if (iters) *iters = 0;
+    if (berr) *berr = 0.0;
+    if (info) *info = 0;
+    if (n == 0 || nrhs == 0) return MFG_OK;
+    Buffers buf;
+    float *A32 = nullptr, *v = nullptr, *d = nullptr;
+    double *R = nullptr, *rows = nullptr, *nrm = nullptr;
+    int32_t *ipiv = nullptr, *dperm = nullptr, *dinfo = nullptr;
+    int st;
+    if ((st = buf.get(&A32, (size_t)(n * n))) != MFG_OK || (st = buf.get(&v, (size_t)(n * nrhs))) != MFG_OK ||
+        (st = buf.get(&d, (size_t)(n * nrhs))) != MFG_OK || (st = buf.get(&R, (size_t)(n * nrhs))) != MFG_OK ||
+        (st = buf.get(&rows, (size_t)n)) != MFG_OK || (st = buf.get(&nrm, (size_t)(3 * nrhs + 1))) != MFG_OK ||
+        (st = buf.get(&ipiv, (size_t)n)) != MFG_OK || (st = buf.get(&dperm, (size_t)n)) != MFG_OK ||
+        (st = buf.get(&dinfo, 1)) != MFG_OK)
+        return st;
+    // the factorisation of the FP32 copy, in the given mode
+    hipLaunchKernelGGL(f64_to_f32, dim3(blocks(n * n, 256)), dim3(256), 0, s, n, n, A, lda, A32, n);
+    MFG_LAUNCH_CHECK();
+    if ((st = lu_factor_impl(n, A32, n, ipiv, dinfo, mode, s)) != MFG_OK) return st;
+    int32_t hinfo = 0;
+    MFG_HIP_CHECK(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> perm;
+    if ((st = permutation(n, ipiv, perm, s)) != MFG_OK) return st;  // synchronises
+    if (info) *info = hinfo;
+    if (hinfo != 0) {
+        MFG_HIP_CHECK(hipStreamSynchronize(s));
+        return MFG_OK;  // exactly singular factor: no solve (info says where)
+    }
+    MFG_HIP_CHECK(hipMemcpyAsync(dperm, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    // |A|_inf and |b_j|_inf, once
+    hipLaunchKernelGGL(abs_row_sums, dim3(blocks(n, 4)), dim3(256), 0, s, n, A, lda, rows);
+    MFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(col_abs_max, dim3(1), dim3(256), 0, s, n, (int64_t)1, rows, (int64_t)1, nrm + 3 * nrhs);
+    MFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(col_abs_max, dim3((unsigned)nrhs), dim3(256), 0, s, n, nrhs, B, ldb, nrm + nrhs);
+    MFG_LAUNCH_CHECK();
+    // x0 from the factors
+    hipLaunchKernelGGL(f64_to_f32, dim3(blocks(n * nrhs, 256)), dim3(256), 0, s, n, nrhs, B, ldb, v, nrhs);
+    MFG_LAUNCH_CHECK();
+    if ((st = lu_solve_impl(n, nrhs, A32, n, dperm, v, nrhs, d, nrhs, s)) != MFG_OK) return st;
+    hipLaunchKernelGGL(accumulate_f64, dim3(blocks(n * nrhs, 256)), dim3(256), 0, s, n, nrhs, d, nrhs, X, ldx, 1);
+    MFG_LAUNCH_CHECK();
+    std::vector<double> h((size_t)(3 * nrhs + 1));
+    double be = INFINITY;
+    int it = 0;
+    for (;; ++it) {
+        // r = b - A x (FP64) and the backward error of x
+        hipLaunchKernelGGL(residual_f64, dim3(blocks(n * nrhs, 4)), dim3(256), 0, s, n, nrhs, A, lda, X, ldx, B, ldb,
+                           R, nrhs);
+        MFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(col_abs_max, dim3((unsigned)nrhs), dim3(256), 0, s, n, nrhs, R, nrhs, nrm);
+        MFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(col_abs_max, dim3((unsigned)nrhs), dim3(256), 0, s, n, nrhs, X, ldx, nrm + 2 * nrhs);
+        MFG_LAUNCH_CHECK();
+        MFG_HIP_CHECK(hipMemcpyAsync(h.data(), nrm, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        MFG_HIP_CHECK(hipStreamSynchronize(s));
+        be = 0.0;
+        const double anorm = h[(size_t)(3 * nrhs)];
+        for (int64_t q = 0; q < nrhs; ++q) {
+            const double den = anorm * h[(size_t)(2 * nrhs + q)] + h[(size_t)(nrhs + q)];
+            const double e = den > 0.0 ? h[(size_t)q] / den : (h[(size_t)q] > 0.0 ? INFINITY : 0.0);
+            be = std::max(be, e);
+        }
+        if (!(be > tol) || it >= max_iter) break;
+        // correction: d = (LU)^-1 P r in FP32, x += d in FP64
+        hipLaunchKernelGGL(f64_to_f32, dim3(blocks(n * nrhs, 256)), dim3(256), 0, s, n, nrhs, R, nrhs, v, nrhs);
+        MFG_LAUNCH_CHECK();
+        if ((st = lu_solve_impl(n, nrhs, A32, n, dperm, v, nrhs, d, nrhs, s)) != MFG_OK) return st;
+        hipLaunchKernelGGL(accumulate_f64, dim3(blocks(n * nrhs, 256)), dim3(256), 0, s, n, nrhs, d, nrhs, X, ldx, 0);
+        MFG_LAUNCH_CHECK();
+    }
+    if (iters) *iters = it;
+    if (berr) *berr = be;
+    return MFG_OK;
+}
+
+}  // namespace
+
+#define MFG_SOLVE_GUARD(expr)                \
+    try {                                    \
+        return (expr);                       \
+    } catch (const std::bad_alloc&) {        \
+        return MFG_ERR_NO_MEMORY;            \
+    } catch (...) {                          \
+        return MFG_ERR_INTERNAL;             \
+    }
+
+extern "C" int mfg_lu_factor(int64_t n, float* A, int64_t lda, int32_t* ipiv, int64_t* info, int mode,
+                             void* stream) {
+    MFG_SOLVE_GUARD(lu_factor_api(n, A, lda, ipiv, info, mode, (hipStream_t)stream));
+}
+
+extern "C" int mfg_lu_solve(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, const int32_t* ipiv, float* B,
+                            int64_t ldb, void* stream) {
+    MFG_SOLVE_GUARD(lu_solve_api(n, nrhs, LU, ldlu, ipiv, B, ldb, (hipStream_t)stream));
+}
+
+extern "C" int mfg_solve_ir(int64_t n, int64_t nrhs, const double* A, int64_t lda, const double* B, int64_t ldb,
+                            double* X, int64_t ldx, int mode, int max_iter, double tol, int* iters, double* berr,
+                            int64_t* info, void* stream) {
+    MFG_SOLVE_GUARD(solve_ir_api(n, nrhs, A, lda, B, ldb, X, ldx, mode, max_iter, tol, iters, berr, info,
+                                 (hipStream_t)stream));
+}

@@ -12,7 +12,10 @@ Workload recipes (all row-major, leading dimension = number of columns):
 * refinement study: normal(0, 1), and sign * 2^u with u uniform in [-10, 10];
 * batched study (Sec. IV.B, Sec. VI): many 16x16x16 problems, plus 64^3 and a
   grouped set whose M, N, K are log-uniform in [16, 512];
-* serving: Poisson arrivals, sizes log-uniform in [32, 4096].
+* serving: Poisson arrivals, sizes log-uniform in [32, 4096];
+* linear solves: A = Q1 diag(s) Q2^T with Q1, Q2 the orthogonal factors of
+  normal(0, 1) matrices and s log-spaced from 1 to the requested condition
+  number (2-norm), right-hand sides normal(0, 1).
 """
 from __future__ import annotations
 
@@ -100,3 +103,13 @@ def serving_trace(seed: int, rate: float, n: int, lo: int = 32, hi: int = 4096,
         reqs.append({"t": float(t[i]), "M": M, "N": N, "K": K, "mode": modes[mode_idx[i]],
                      "a_off": (a_r, a_c), "b_off": (b_r, b_c)})
     return reqs
+
+
+def conditioned(seed: int, n: int, cond: float) -> np.ndarray:
+    """An n x n FP64 matrix of 2-norm condition number `cond`: Q1 diag(s) Q2^T,
+    Q1 and Q2 orthogonal (QR of normal(0, 1) matrices), s log-spaced 1 .. cond."""
+    g = _rng(seed)
+    q1, _ = np.linalg.qr(g.standard_normal((n, n)))
+    q2, _ = np.linalg.qr(g.standard_normal((n, n)))
+    s = np.logspace(0.0, np.log10(cond), n) if n > 1 else np.ones(1)
+    return (q1 * s) @ q2.T
