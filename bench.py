@@ -565,10 +565,11 @@ def sustained_clock(step, flops: float, seconds: float) -> dict:
 
     def sampler():
         while not stop[0]:
+            ts = time.perf_counter()
             x = smi_sample()
             if x is None:
                 return
-            samples.append(x)
+            samples.append((ts, time.perf_counter(), x))
             time.sleep(0.05)
 
     th = threading.Thread(target=sampler, daemon=True)
@@ -587,12 +588,13 @@ def sustained_clock(step, flops: float, seconds: float) -> dict:
     stop[0] = True
     th.join(timeout=15)
     out = {"seconds": round(el, 2), "launches": k, "tflops": round(flops * k / el / 1e12, 1)}
-    mid = samples[len(samples) // 4:] if len(samples) >= 4 else samples
+    # readings taken wholly inside the loaded interval, past its first quarter
+    mid = [x for (a, b, x) in samples if a >= t0 + 0.25 * el and b <= t0 + el]
     if mid:
-        clks = [c for s_ in mid for c in s_["sclk_mhz"]]
-        out.update({"sclk_mhz_mean": round(sum(clks) / len(clks), 1), "sclk_mhz_min": min(clks),
-                    "sclk_mhz_max": max(clks), "power_w_mean": round(sum(s_["power_w"] for s_ in mid) / len(mid), 1),
-                    "samples": len(mid)})
+        clks = sorted(c for s_ in mid for c in s_["sclk_mhz"])
+        out.update({"sclk_mhz_mean": round(sum(clks) / len(clks), 1), "sclk_mhz_median": clks[len(clks) // 2],
+                    "sclk_mhz_min": clks[0], "sclk_mhz_max": clks[-1],
+                    "power_w_mean": round(sum(s_["power_w"] for s_ in mid) / len(mid), 1), "samples": len(mid)})
     return out
 
 
