@@ -205,20 +205,26 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
 // with a stride over its XCD's range of the work list; wavefront (wm, wn)
 // computes the quarter (wm, wn).  The work
 // list is denormalised: each record carries the tile's operand pointers,
-// leading dimensions and extent, and 16 lanes of one load fetch one record,
-// so one load brings four records; two such windows are kept ahead of the
-// item being computed.
+// leading dimensions and extent (one 64-byte scalar load).
 //
 // The items' 64-deep K blocks form one stream per workgroup.  Block s + 2 is
-// loaded (16-byte pieces, 2 of A and 2 of B per lane: whole 128-byte rows of
-// the A and B tiles) while block s is multiplied, and written into the LDS
-// buffer of block s + 1's parity after it -- across item boundaries, so a
-// short item's loads overlap its predecessor's MFMAs and C stores.  One
-// barrier per block.  A rows sit in LDS as 8 XOR-swizzled 16-byte pieces; B
+// loaded into registers (16-byte pieces, TT / 32 of A and of B per lane and
+// plane: whole 128-byte rows of the A and B tiles) while block s is
+// multiplied, and block s + 1 is written into the LDS buffer of its parity
+// after it -- across item boundaries, so a short item's loads overlap its
+// predecessor's MFMAs and C stores.  One barrier per block.  (A third
+// register set, loads three blocks ahead, measured no faster on the
+// 4096-problem set: the kernel is bound by the memory system's mixed
+// read/write throughput, not by the latency of its loads.)  A rows sit in LDS as 8 XOR-swizzled 16-byte pieces; B
 // as 16 x 32 slabs read back transposed.  Every wavefront runs the 32x32x16
 // MFMA on 16-deep chunks in K order from zero, with zeros beyond K: the
 // operands and order of the simple kernel on that tile.
 constexpr int kGroupedBK = 64;  // K per block: 128-byte A and B rows
+// Extent of the operand buffer resources and the offset of pieces outside
+// an item (at the extent: the load returns zeros).  Piece offsets are below
+// TT * kOperandLdLimit * 2 <= 2^30.
+constexpr uint32_t kGroupedOob = 0x7FFFFFF0u;
+static_assert(128 * kOperandLdLimit * 2 < (int64_t)kGroupedOob, "piece offsets below the out-of-range offset");
 // 16 zero bytes in device memory: the load source of lanes with nothing to load
 typedef __attribute__((address_space(1))) const uint16_t g_u16;
 typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
@@ -250,16 +256,20 @@ struct GItem {
     int rows, cols, K, vec;
 };
 
-// Record q (0..3) of a window: dword f of it sits in lane 16 q + f.
-__device__ __forceinline__ GItem window_item(uint32_t win, int q) {
-    auto dw = [&](int f) { return (uint32_t)__builtin_amdgcn_readlane((int)win, 16 * q + f); };
-    auto qw = [&](int f) { return (uint64_t)dw(f) | ((uint64_t)dw(f + 1) << 32); };
+// Work records are read with scalar loads (through the constant address
+// space: the list is not written while the kernel runs).  They land in
+// SGPRs and are counted by lgkmcnt, apart from the operand loads' vmcnt, so
+// reading the next record never waits for operand blocks still in flight.
+typedef __attribute__((address_space(4))) const GroupedWork c_work;
+typedef __attribute__((address_space(4))) const int64_t c_i64;
+__device__ __forceinline__ GItem load_item(const c_work* w, int64_t i) {
+    const c_work& r = w[i];
     GItem t;
-    t.A = (const g_u16*)qw(0);
-    t.B = (const g_u16*)qw(2);
-    t.C = (g_f32*)qw(4);
-    t.lda = (int64_t)qw(6), t.ldb = (int64_t)qw(8), t.ldc = (int64_t)qw(10);
-    t.rows = (int)dw(12), t.cols = (int)dw(13), t.K = (int)dw(14), t.vec = (int)dw(15);
+    t.A = (const g_u16*)r.A;
+    t.B = (const g_u16*)r.B;
+    t.C = (g_f32*)r.C;
+    t.lda = r.lda, t.ldb = r.ldb, t.ldc = r.ldc;
+    t.rows = r.rows, t.cols = r.cols, t.K = r.K, t.vec = r.vec;
     return t;
 }
 
@@ -285,6 +295,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
     constexpr int PA = TT / 32, PB = TT / 32;       // 16-byte pieces per thread and block: A, B
     constexpr int BPR = TT / 8;                     // pieces per B row
     constexpr int NA = KT<KIND>::NPA, NB = KT<KIND>::NPB;  // operand planes (head, residual)
+    constexpr int NR = 2;  // register sets: blocks s + 1 and s + 2 in flight while block s is multiplied
     const int64_t* off = split.off[VEC ? 0 : 1];
     // per plane and buffer: A TT rows x 64, B 4 chunks x TT/32 column slabs x (16 x 32)
     __shared__ __attribute__((aligned(16))) uint16_t As[NA][2][TT * 64];
@@ -296,18 +307,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
     const int64_t first = off[xcd] + blockIdx.x / kXcds, end = off[xcd + 1];
     if (first >= end) return;
     const int64_t count = (end - first + stride - 1) / stride;  // items of this workgroup
-    // record windows: items w0 .. w0 + 3 and w0 + 4 .. w0 + 7 of this workgroup
-    const g_u32* wbase = (const g_u32*)work;
-    auto load_window = [&](int64_t w) -> uint32_t {
-        const int64_t it = first + (w + (lane >> 4)) * stride;
-        return it < end ? wbase[it * 16 + (lane & 15)] : 0u;
-    };
-    int64_t w0 = 0;
-    uint32_t win0 = load_window(0), win1 = load_window(4);
-    auto item_at = [&](int64_t i) {  // i in [w0, w0 + 8)
-        const int64_t d = i - w0;
-        return window_item(d < 4 ? win0 : win1, (int)(d & 3));
-    };
+    const c_work* cw = (const c_work*)work;
+    auto item_at = [&](int64_t i) { return load_item(cw, first + i * stride); };
 
     // This thread's pieces of each operand block (piece p = tid + 256 j: A row
     // p / 8, K columns 8 (p % 8) ..; B K row p / BPR, columns 8 (p % BPR) ..).
@@ -319,32 +320,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
     // registers; B's columns at or beyond the tile's width only reach
     // discarded outputs.  Pieces wholly outside the item (A rows beyond the
     // tile, B rows or A columns at or beyond K, B columns beyond the tile)
-    // are zero in registers and issue no memory request: their lanes sit out
-    // the load, so a small item costs requests for its own data only.
+    // are zero and cost no memory traffic: every lane issues its buffer load
+    // (one resource per plane from the block's first column of A / first
+    // row of B), those lanes with an offset past the resource's end, which
+    // the hardware answers with zeros.  The loads are thus issued
+    // unconditionally, the same number every block, so the compiler's wait
+    // before a block's LDS store counts the block loaded after it and lets
+    // it stay in flight (with loads behind branches it has to assume none
+    // were issued and waits for all).  Offsets stay below 2^31: the VEC list
+    // holds only lda, ldb < kOperandLdLimit.
     // Unaligned items load element by element.
     // Residual planes sit at element offsets pa (A) and pb (B) from the head
     // planes of the item being loaded (refined kinds; read with the item).
     int64_t pa = 0, pb = 0;
     auto load_block = [&](const GItem& t, int kb0, u32x4 (&a)[NA][PA], u32x4 (&b)[NB][PB], int (&nv)[PA]) {
         if constexpr (VEC) {
+            const uint32_t lda32 = (uint32_t)t.lda, ldb32 = (uint32_t)t.ldb;
+            uint32_t oa[PA], ob[PB];
 #pragma unroll
             for (int j = 0; j < PA; ++j) {
                 const int p = tid + 256 * j, row = p >> 3, ka = kb0 + 8 * (p & 7);
                 const bool fa = row < t.rows && ka < t.K;
-                const int64_t o = row * t.lda + ka;
-#pragma unroll
-                for (int q = 0; q < NA; ++q)  // pieces outside the item issue no request
-                    a[q][j] = fa ? *(const g_u32x4*)(t.A + (q ? pa : 0) + o) : zero4();
+                oa[j] = fa ? ((uint32_t)row * lda32 + (uint32_t)(8 * (p & 7))) * 2u : kGroupedOob;
                 nv[j] = t.K - ka;  // valid elements of the A piece (masked when it is stored)
             }
 #pragma unroll
             for (int j = 0; j < PB; ++j) {
-                const int p = tid + 256 * j, kr = kb0 + p / BPR, cb = 8 * (p % BPR);
-                const bool fb = kr < t.K && cb < t.cols;
-                const int64_t o = kr * t.ldb + cb;
+                const int p = tid + 256 * j, kr = p / BPR, cb = 8 * (p % BPR);
+                const bool fb = kb0 + kr < t.K && cb < t.cols;
+                ob[j] = fb ? ((uint32_t)kr * ldb32 + (uint32_t)cb) * 2u : kGroupedOob;
+            }
 #pragma unroll
-                for (int q = 0; q < NB; ++q)
-                    b[q][j] = fb ? *(const g_u32x4*)(t.B + (q ? pb : 0) + o) : zero4();
+            for (int q = 0; q < NA; ++q) {
+                const __amdgpu_buffer_rsrc_t rs =
+                    buffer_rsrc((const void*)(t.A + (q ? pa : 0) + kb0), kGroupedOob);
+#pragma unroll
+                for (int j = 0; j < PA; ++j) a[q][j] = __builtin_amdgcn_raw_buffer_load_b128(rs, oa[j], 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const __amdgpu_buffer_rsrc_t rs =
+                    buffer_rsrc((const void*)(t.B + (q ? pb : 0) + (int64_t)kb0 * t.ldb), kGroupedOob);
+#pragma unroll
+                for (int j = 0; j < PB; ++j) b[q][j] = __builtin_amdgcn_raw_buffer_load_b128(rs, ob[j], 0, 0);
             }
         } else {
 #pragma unroll
@@ -404,12 +422,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
     auto item_planes = [&](int64_t i) {  // residual-plane offsets of this workgroup's item i
         if constexpr (NA > 1 || NB > 1) {
             const int64_t it = first + i * stride;
-            pa = planes[2 * it], pb = planes[2 * it + 1];
+            const c_i64* pl = (const c_i64*)planes;
+            pa = pl[2 * it], pb = pl[2 * it + 1];
         }
     };
 
     // cursors: the computed block (item ci, block cb) and the loaded one,
-    // two blocks ahead (item li, block lb); both advance through the stream
+    // NR blocks ahead (item li, block lb); both advance through the stream
     int64_t ci = 0, li = 0;
     int cbk = 0, lbk = 0;
     GItem cur = item_at(0), ld = cur;
@@ -426,14 +445,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
             }
         }
     };
-    u32x4 ra[2][NA][PA], rb[2][NB][PB];  // register sets of the two blocks in flight
-    int rn[2][PA];
-    // prologue: block 0 into LDS buffer 0, block 1 into registers
+    u32x4 ra[NR][NA][PA], rb[NR][NB][PB];  // register sets of the blocks in flight
+    int rn[NR][PA];
+    // prologue: block 0 into LDS buffer 0, blocks 1 .. NR - 1 into registers
     load_block(ld, 0, ra[0], rb[0], rn[0]);
     store_block(0, ra[0], rb[0], rn[0]);
     advance_load();
-    load_block(ld, lbk * kGroupedBK, ra[1], rb[1], rn[1]);
-    advance_load();
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
+        load_block(ld, lbk * kGroupedBK, ra[r], rb[r], rn[r]);
+        advance_load();
+    }
     grouped_barrier();
 
     f32x16 hi[FM][FN], lo[FM][FN], rr[FM][FN];
@@ -444,13 +466,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
             for (int j = 0; j < FN; ++j) hi[i][j] = f32x16{}, lo[i][j] = f32x16{}, rr[i][j] = f32x16{};
     };
     clear();
-    // one block of the stream; BUF: its LDS buffer and register set (block
-    // parity).  Returns true after the last item's last block.
-    auto step = [&](auto bufc) -> bool {
-        constexpr int buf = decltype(bufc)::value;
-        // loads of block s + 2 into the register set block s used (kept
+    // one block s of the stream; BUF: its LDS buffer (s % 2), SET: the
+    // register set it arrived in (s % NR).  Returns true after the last
+    // item's last block.
+    auto step = [&](auto bufc, auto setc) -> bool {
+        constexpr int buf = decltype(bufc)::value, set = decltype(setc)::value, nset = (set + 1) % NR;
+        // loads of block s + NR into the register set block s used (kept
         // ahead of everything below: the compiler would otherwise sink them)
-        load_block(ld, lbk * kGroupedBK, ra[buf], rb[buf], rn[buf]);
+        load_block(ld, lbk * kGroupedBK, ra[set], rb[set], rn[set]);
+        asm volatile("" ::: "memory");  // the IR passes would otherwise sink the buffer loads to their use
         __builtin_amdgcn_sched_barrier(0);
         const int kb0 = cbk * kGroupedBK;
 #pragma unroll
@@ -476,8 +500,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
 #pragma unroll
                 for (int fn = 0; fn < FN; ++fn) mma_step<KIND>(aa[fm], bb[fn], hi[fm][fn], lo[fm][fn], rr[fm][fn]);
         }
-        // block s + 1 (loaded during block s - 1) into the other buffer
-        store_block(buf ^ 1, ra[buf ^ 1], rb[buf ^ 1], rn[buf ^ 1]);
+        // block s + 1 (loaded during block s + 1 - NR) into the other buffer
+        store_block(buf ^ 1, ra[nset], rb[nset], rn[nset]);
         advance_load();
         bool done = false;
         if (cbk + 1 >= grouped_blocks(cur.K)) {  // the item's last block: its C, then the next item
@@ -503,11 +527,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
             if (++ci >= count) {
                 done = true;
             } else {
-                if (ci >= w0 + 4) {  // window 1 becomes window 0; fetch the four records after it
-                    w0 += 4;
-                    win0 = win1;
-                    win1 = load_window(w0 + 4);
-                }
                 cur = item_at(ci);
             }
         } else {
@@ -517,9 +536,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grouped_wg_
         grouped_barrier();
         return false;
     };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
     for (;;) {
-        if (step(std::integral_constant<int, 0>{})) break;
-        if (step(std::integral_constant<int, 1>{})) break;
+        if (step(I0{}, I0{})) break;
+        if (step(I1{}, I1{})) break;
     }
 }
 
@@ -538,8 +559,10 @@ void build_grouped_work(const GroupedDesc* descs, int64_t n, std::vector<Grouped
     };
     work.clear();
     if (planes) planes->clear();
-    for (int list = 0; list < 2; ++list) {  // 0: aligned problems with ldc < kBufferLdcLimit, 1: the rest
-        auto in_list = [&](const GroupedDesc& d) { return (d.vec != 0 && buffer_ldc_ok(d.ldc)) == (list == 0); };
+    for (int list = 0; list < 2; ++list) {  // 0: aligned problems, ldc and operand ld within the 32-bit offset bounds; 1: the rest
+        auto in_list = [&](const GroupedDesc& d) {
+            return (d.vec != 0 && buffer_ldc_ok(d.ldc) && operand_ld_ok(d.lda, d.ldb)) == (list == 0);
+        };
         double total = 0.0;
         for (int64_t i = 0; i < n; ++i)
             if (in_list(descs[i])) total += 2.0 * (double)descs[i].M * (double)descs[i].N * (double)descs[i].K;

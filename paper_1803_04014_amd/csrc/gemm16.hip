@@ -149,6 +149,7 @@ static const Cfg16 kCfgSplit[] = {
     {"f128x128k64w2x2g8dma", 128, 128, 8, 2, 2, 2},
     {"q128x128k64s2w2x2g8", 128, 128, 8, 7, 2, 2},
     {"q128x128k64s2w2x2g8e", 128, 128, 8, 8, 2, 2},
+    {"q192x128k64s2w2x2g8e", 192, 128, 8, 8, 2, 2},
 };
 static const Cfg16 kCfgSplit4[] = {
     {"simple32", 0, 0, 0},
@@ -238,6 +239,8 @@ static int launch_kind(int cfg, const Gemm16Args& a, int64_t batch, bool vec_ok,
             if (c.bm == 256 && c.bn == 128) return launch_pipe64<KIND, 256, 128, 2, 2, 3, 2, true>(a, batch, c.group_m, s);
         } else {
             if (c.bm == 128 && c.bn == 128) return launch_pipe64<KIND, 128, 128, 2, 2, 2, 2, true>(a, batch, c.group_m, s);
+            if constexpr (KIND != K_SPLIT4)
+                if (c.bm == 192 && c.bn == 128) return launch_pipe64<KIND, 192, 128, 2, 2, 2, 2, true>(a, batch, c.group_m, s);
         }
         return MFG_ERR_INTERNAL;
     }

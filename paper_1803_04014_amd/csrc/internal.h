@@ -214,7 +214,7 @@ int launch_batched_small(int kind, const Gemm16Args& a, int64_t count, bool vec_
 // so its operands are fetched into one L2.
 constexpr int kXcds = 8;
 struct GroupedSplit {
-    int64_t off[2][kXcds + 1];  // list 0: aligned rows (vec) and ldc < kBufferLdcLimit, list 1: the rest
+    int64_t off[2][kXcds + 1];  // list 0: aligned rows (vec), ldc < kBufferLdcLimit, lda and ldb < kOperandLdLimit; list 1: the rest
 };
 // `planes` (if not null) receives two int64 per work item, in work order:
 // the problem's residual-plane offsets pa, pb.

@@ -30,6 +30,11 @@ int pick_config16(int kind, int64_t M, int64_t N, int64_t K, bool vec_ok) {
         if (fast && t128 >= 64) return 3;    // f128x128k32w2x2g8dma
         return big ? 2 : 0;                  // t64x64k32w2x2g8
     }
+    // 192 x 128: two 64-deep stages fill the 160 KB of LDS and each MFMA
+    // needs 17% fewer operand bytes than on 128 x 128 (N = 8192: SPLIT3
+    // 2.74 vs 2.96 ms, BF16_SPLIT3 2.63 vs 2.87, REFINE_A 2.16 vs 2.27); at
+    // N = 4096 the partial last wave of 192-row tiles makes it a tie
+    if (fast && cdiv(M, 192) * cdiv(N, 128) >= 1024) return 9;  // q192x128k64s2w2x2g8e
     if (fast && t128 >= 256) return 7;       // q128x128k64s2w2x2g8
     if (fast && t128 >= 64) return 6;        // f128x128k64w2x2g8dma
     return big ? 3 : 0;                      // t64x64k32w2x2g8
