@@ -221,6 +221,10 @@ int mfg_gemm_batched(int64_t count, int64_t M, int64_t N, int64_t K,
  * Each problem's result is bitwise that of mfg_gemm on the problem alone in
  * the same mode (preconverted, or from FP32 respectively).  The descriptor array is host memory; the plan copies it
  * to the device, so it may be freed after mfg_grouped_plan_create.
+ * The grouped GEMM is a plan, not one call taking the problem list and a
+ * plan in/out argument: mfg_grouped_plan_create validates the list and
+ * builds the work list once, and mfg_grouped_run (or mfg_grouped_graph_launch, a
+ * captured replay) executes it with a given alpha, beta as often as needed.
  */
 typedef struct mfg_problem {
     int64_t M, N, K;
@@ -244,7 +248,9 @@ typedef struct mfg_grouped_plan mfg_grouped_plan;
  * the refined modes.  A run launches the grouped kernel once per class
  * present; a class that would carry under a quarter of the plan's flops
  * runs in the other class instead (each launch adds its own tail).  Rows of A and B that are 16-byte
- * aligned with ld a multiple of 8 are read in whole 16-byte pieces, which may
+ * aligned with ld a multiple of 8 (and lda, ldb < 2^22, ldc < 2^24; other
+ * problems are read element by element in a second launch of their class)
+ * are read in whole 16-byte pieces, which may
  * touch up to 14 bytes past a row's last element (inside the same aligned 16
  * bytes, never another page); those bytes never reach a result.
  * `out` receives the plan (host). */
