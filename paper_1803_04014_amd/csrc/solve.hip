@@ -95,103 +95,162 @@ __global__ __launch_bounds__(kPanelThreads) void lu_panel(int64_t n, float* A, i
 }
 
 // A narrow panel A[j:n, j:j+w] (w <= 8) held in registers for all of its
-// columns: thread t owns rows j + t + kP8Threads q, q < kP8Rows (so
-// n - j <= kP8Threads kP8Rows).  Per column: the pivot (largest |value|,
-// first on ties) by a workgroup reduction, the swap of the two rows through
-// LDS, then scaling and the rank-1 update of each owned row in registers.
-// Same arithmetic, operation by operation, as lu_panel.
-constexpr int kP8 = 8, kP8Threads = 512, kP8Rows = 16;
+// columns: thread t owns panel rows i = t + kP8Threads q (row j + i), q <
+// kP8Rows (so n - j <= kP8Threads kP8Rows).  One barrier per column c:
+//   - each wavefront finds its largest |value| among its rows at or below the
+//     diagonal (first row on ties); the lane owning that row writes the value,
+//     the row index and the row's values to the wavefront's LDS slot, and
+//     thread c (owner of the diagonal row, q = 0) writes that row;
+//   - after the barrier every thread reduces the slots by the same rule, so
+//     each knows the pivot row p and both rows to exchange; their owners swap
+//     them in registers, and every owned row below the diagonal is scaled by
+//     the pivot and gets the rank-1 update of the columns to its right.
+// The slots alternate between two LDS buffers by column parity: a buffer is
+// written again two columns later, by threads that passed the barrier of the
+// column in between, which every thread reaches only after reading it.  Rows
+// move as two 16-byte pieces when A, lda and j allow (vec), else element by
+// element.  Same arithmetic, operation by operation, as lu_panel.
+constexpr int kP8 = 8, kP8Threads = 512, kP8Rows = 16, kP8Waves = kP8Threads / 64;
+
+// One step of a (value, row) max across lanes: the partner lane given by the
+// DPP control CTRL; the larger value wins, the lower row on ties.
+template <int CTRL>
+__device__ __forceinline__ void p8_dpp_max(float& best, int& bi) {
+    const float ov = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, best), CTRL, 0xF, 0xF, false));
+    const int oi = __builtin_amdgcn_mov_dpp(bi, CTRL, 0xF, 0xF, false);
+    if (ov > best || (ov == best && oi < bi)) best = ov, bi = oi;
+}
+
 
 __global__ __launch_bounds__(kP8Threads) void lu_panel8(int64_t n, float* A, int64_t lda, int64_t j, int w,
-                                                       int32_t* ipiv, int32_t* info) {
-    __shared__ float pr[kP8], dr[kP8];
-    __shared__ float wv[kP8Threads / 64];
-    __shared__ int64_t wi[kP8Threads / 64];
-    __shared__ int64_t piv;
+                                                       int32_t* ipiv, int32_t* info, int vec) {
+    __shared__ float sv[2][kP8Waves];
+    __shared__ int si[2][kP8Waves];
+    __shared__ float srow[2][kP8Waves][kP8];
+    __shared__ float sdiag[2][kP8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rows = (int)(n - j);
     float x[kP8Rows][kP8];
 #pragma unroll
     for (int q = 0; q < kP8Rows; ++q) {
-        const int64_t r = j + tid + (int64_t)kP8Threads * q;
+        const int i = tid + kP8Threads * q;
+        const float* rp = A + (j + i) * lda + j;
+        if (i < rows && vec) {
+            const float4 u = *reinterpret_cast<const float4*>(rp), v = *reinterpret_cast<const float4*>(rp + 4);
+            x[q][0] = u.x, x[q][1] = u.y, x[q][2] = u.z, x[q][3] = u.w;
+            x[q][4] = v.x, x[q][5] = v.y, x[q][6] = v.z, x[q][7] = v.w;
+        } else {
 #pragma unroll
-        for (int c = 0; c < kP8; ++c) x[q][c] = (r < n && c < w) ? A[r * lda + j + c] : 0.0f;
+            for (int c = 0; c < kP8; ++c) x[q][c] = (i < rows && c < w) ? rp[c] : 0.0f;
+        }
     }
+    // (value, row) pairs: the larger value wins, the lower row on ties; rows
+    // with no candidate carry (-1, rows)
+    auto better = [](float ov, int oi, float bv, int bx) { return ov > bv || (ov == bv && oi < bx); };
 #pragma unroll
     for (int c = 0; c < kP8; ++c) {
         if (c >= w) break;
-        const int64_t col = j + c;
+        const int buf = c & 1;
         float best = -1.0f;
-        int64_t bi = n;
+        int bi = rows;
 #pragma unroll
         for (int q = 0; q < kP8Rows; ++q) {
-            const int64_t r = j + tid + (int64_t)kP8Threads * q;
+            const int i = tid + kP8Threads * q;
             const float v = fabsf(x[q][c]);
-            if (r >= col && r < n && v > best) best = v, bi = r;
+            const bool take = (q > 0 || i >= c) && i < rows && v > best;
+            best = take ? v : best;
+            bi = take ? i : bi;
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const float ov = __shfl_xor(best, off);
-            const int64_t oi = __shfl_xor(bi, off);
-            if (ov > best || (ov == best && oi < bi)) best = ov, bi = oi;
+        // wavefront reduction: DPP inside each 16-lane row (xor 1, xor 2,
+        // rotate 4, rotate 8 cover the row), then the four rows by readlane
+        p8_dpp_max<0xB1>(best, bi);   // quad_perm [1,0,3,2]
+        p8_dpp_max<0x4E>(best, bi);   // quad_perm [2,3,0,1]
+        p8_dpp_max<0x124>(best, bi);  // row_ror 4
+        p8_dpp_max<0x128>(best, bi);  // row_ror 8
+        float wb = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, best), 0));
+        int wi = __builtin_amdgcn_readlane(bi, 0);
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            const float ob = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, best), 16 * r));
+            const int oi = __builtin_amdgcn_readlane(bi, 16 * r);
+            if (better(ob, oi, wb, wi)) wb = ob, wi = oi;
         }
-        if (lane == 0) wv[wave] = best, wi[wave] = bi;
+        // the wavefront's candidate: value, row and the row's values, written
+        // by the lane owning it (slot wi / kP8Threads, uniform)
+        if (lane == 0) sv[buf][wave] = wb, si[buf][wave] = wi;
+        if (wi < rows && (wi & (kP8Threads - 1)) == tid) {
+#pragma unroll
+            for (int q = 0; q < kP8Rows; ++q)
+                if (q == wi / kP8Threads)
+#pragma unroll
+                    for (int cc = 0; cc < kP8; ++cc) srow[buf][wave][cc] = x[q][cc];
+        }
+        if (tid == c)
+#pragma unroll
+            for (int cc = 0; cc < kP8; ++cc) sdiag[buf][cc] = x[0][cc];
         __syncthreads();
-        if (tid == 0) {
-            float b = wv[0];
-            int64_t i = wi[0];
-            for (int q = 1; q < kP8Threads / 64; ++q)
-                if (wv[q] > b || (wv[q] == b && wi[q] < i)) b = wv[q], i = wi[q];
-            if (i >= n) i = col;
-            piv = i;
-            ipiv[col] = (int32_t)i;
+        float pb = sv[buf][0];
+        int pi = si[buf][0], pw = 0;
+#pragma unroll
+        for (int q = 1; q < kP8Waves; ++q) {
+            const float ov = sv[buf][q];
+            const int oi = si[buf][q];
+            if (better(ov, oi, pb, pi)) pb = ov, pi = oi, pw = q;
         }
-        __syncthreads();
-        const int64_t p = piv;
-        // rows col and p: the owners publish them, then take each other's
+        if (pi >= rows) pi = c, pw = -1;  // no candidate (every |value| NaN): the diagonal row
+        pi = __builtin_amdgcn_readfirstlane(pi);
+        pw = __builtin_amdgcn_readfirstlane(pw);
+        float pr[kP8], dr[kP8];
 #pragma unroll
-        for (int q = 0; q < kP8Rows; ++q) {
-            const int64_t r = j + tid + (int64_t)kP8Threads * q;
-            if (r == p)
-#pragma unroll
-                for (int cc = 0; cc < kP8; ++cc) pr[cc] = x[q][cc];
-            if (r == col)
-#pragma unroll
-                for (int cc = 0; cc < kP8; ++cc) dr[cc] = x[q][cc];
+        for (int cc = 0; cc < kP8; ++cc) {
+            dr[cc] = sdiag[buf][cc];
+            pr[cc] = pw >= 0 ? srow[buf][pw][cc] : dr[cc];
         }
-        __syncthreads();
-        if (p != col) {
+        if (tid == 0) ipiv[j + c] = (int32_t)(j + pi);
+        if (pi != c) {  // two lanes exchange rows j + c (slot 0 of thread c) and j + pi
+            if (tid == (pi & (kP8Threads - 1))) {
 #pragma unroll
-            for (int q = 0; q < kP8Rows; ++q) {
-                const int64_t r = j + tid + (int64_t)kP8Threads * q;
-                if (r == p)
+                for (int q = 0; q < kP8Rows; ++q)
+                    if (q == pi / kP8Threads)
 #pragma unroll
-                    for (int cc = 0; cc < kP8; ++cc) x[q][cc] = dr[cc];
-                if (r == col)
-#pragma unroll
-                    for (int cc = 0; cc < kP8; ++cc) x[q][cc] = pr[cc];
+                        for (int cc = 0; cc < kP8; ++cc) x[q][cc] = dr[cc];
             }
+            if (tid == c)
+#pragma unroll
+                for (int cc = 0; cc < kP8; ++cc) x[0][cc] = pr[cc];
         }
-        const float pv = pr[c];  // the pivot row is now row col
-        if (tid == 0 && pv == 0.0f && *info == 0) *info = (int32_t)(col + 1);
+        const float pv = pr[c];  // the pivot row is now row j + c
+        if (tid == 0 && pv == 0.0f && *info == 0) *info = (int32_t)(j + c + 1);
         if (pv != 0.0f) {
+            // rows below the diagonal; rows past the matrix hold zeros, take the
+            // update harmlessly (or skip it with their wavefront) and are never
+            // stored or chosen as pivots
 #pragma unroll
             for (int q = 0; q < kP8Rows; ++q) {
-                const int64_t r = j + tid + (int64_t)kP8Threads * q;
-                if (r > col && r < n) {
-                    const float l = x[q][c] / pv;
-                    x[q][c] = l;
+                if (kP8Threads * q + 64 * wave >= rows) continue;  // the wavefront's rows of slot q are all past the matrix
+                const bool below = q > 0 || tid > c;
+                const float l = x[q][c] / pv;
+                x[q][c] = below ? l : x[q][c];
 #pragma unroll
-                    for (int cc = c + 1; cc < kP8; ++cc) x[q][cc] = __builtin_fmaf(-l, pr[cc], x[q][cc]);
+                for (int cc = c + 1; cc < kP8; ++cc) {
+                    const float u = __builtin_fmaf(-l, pr[cc], x[q][cc]);
+                    x[q][cc] = below ? u : x[q][cc];
                 }
             }
         }
-        __syncthreads();  // pr / dr are rewritten by the next column
     }
 #pragma unroll
     for (int q = 0; q < kP8Rows; ++q) {
-        const int64_t r = j + tid + (int64_t)kP8Threads * q;
+        const int i = tid + kP8Threads * q;
+        float* rp = A + (j + i) * lda + j;
+        if (i < rows && vec) {
+            *reinterpret_cast<float4*>(rp) = make_float4(x[q][0], x[q][1], x[q][2], x[q][3]);
+            *reinterpret_cast<float4*>(rp + 4) = make_float4(x[q][4], x[q][5], x[q][6], x[q][7]);
+        } else {
 #pragma unroll
-        for (int c = 0; c < kP8; ++c)
-            if (r < n && c < w) A[r * lda + j + c] = x[q][c];
+            for (int c = 0; c < kP8; ++c)
+                if (i < rows && c < w) rp[c] = x[q][c];
+        }
     }
 }
 
@@ -385,7 +444,8 @@ int lu_factor_impl(int64_t n, float* A, int64_t lda, int32_t* ipiv, int32_t* inf
         if (n - j <= (int64_t)kP8Threads * kP8Rows) {
             for (int64_t jj = j; jj < j + w; jj += kP8) {
                 const int wi = (int)std::min<int64_t>(kP8, j + w - jj);
-                hipLaunchKernelGGL(lu_panel8, dim3(1), dim3(kP8Threads), 0, s, n, A, lda, jj, wi, ipiv, info);
+                const int vec = wi == kP8 && lda % 4 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0;
+                hipLaunchKernelGGL(lu_panel8, dim3(1), dim3(kP8Threads), 0, s, n, A, lda, jj, wi, ipiv, info, vec);
                 MFG_LAUNCH_CHECK();
                 hipLaunchKernelGGL(lu_laswp_range, dim3(1), dim3(256), 0, s, A, lda, jj, wi, ipiv, j, j + w, jj,
                                    jj + wi);
