@@ -133,6 +133,29 @@ def test_grouped_equals_solo_and_graph_replays():
     plan.close()
 
 
+def test_grouped_large_operand_ld_equals_solo():
+    """Aligned problems with lda or ldb >= 2^22 go to the element-wise work list
+    (the aligned kernel addresses its pieces with 32-bit offsets): each is
+    bitwise equal to its solo run, beside ordinary problems in the same plan."""
+    big = (1 << 22) + 8
+    specs = [(3, 40, 24, big, None), (70, 33, 5, None, big), (130, 136, 72, None, None), (9, 17, 100, None, None)]
+    probs = []
+    for i, (m, n, k, lda, ldb) in enumerate(specs):
+        A, B = workloads.uniform(4000 + i, [(m, k), (k, n)])
+        a = torch.zeros((m, lda or -(-k // 8) * 8), dtype=torch.float16, device=DEV)
+        b = torch.zeros((k, ldb or -(-n // 8) * 8), dtype=torch.float16, device=DEV)
+        a[:, :k] = dev(A).half()
+        b[:, :n] = dev(B).half()
+        probs.append((a[:, :k], b[:, :n], torch.zeros((m, n), dtype=torch.float32, device=DEV)))
+    plan = mfg.GroupedPlan(probs, "f16")
+    plan.run(1.0, 0.0)
+    for i, (a, b, c) in enumerate(probs):
+        solo = torch.zeros_like(c)
+        mfg.gemm(a, b, solo, 1.0, 0.0, mode="f16", preconverted=True)
+        assert np.array_equal(host(c).view(np.uint32), host(solo).view(np.uint32)), f"problem {specs[i]}"
+    plan.close()
+
+
 def test_grouped_rejects_unsupported_mode():
     probs, _ = _grouped_problems(4, 16, 64, 9)
     for mode in ("f32", "fp8"):
