@@ -395,9 +395,11 @@ def kernel_only(mode: str, n: int, steps: int, warmup: int) -> int:
 
 
 def mfma_ceiling(dev, iters: int = 2048, workgroups_per_cu: int = 2) -> dict:
-    """Register-only MFMA loops (mfg_probe_mfma) on random and on all-zero FP16
-    operands, both MFMA shapes: the matrix-core rate the chip sustains with no
-    memory traffic, i.e. the ceiling the GEMM kernels work against."""
+    """Register-only MFMA loops (mfg_probe_mfma) on random and on all-zero
+    operands: both FP16 MFMA shapes (uniform[-1, 1] values) and the FP8 E4M3
+    32x32x64 instruction (uniform[-1, 1] rounded to E4M3): the matrix-core rate
+    the chip sustains with no memory traffic, i.e. the ceiling the GEMM kernels
+    work against."""
     import ctypes
 
     import torch
@@ -408,10 +410,13 @@ def mfma_ceiling(dev, iters: int = 2048, workgroups_per_cu: int = 2) -> dict:
     wg = ncu * workgroups_per_cu
     rnd = torch.empty(8192, dtype=torch.float16, device=dev).uniform_(-1, 1)
     zero = torch.zeros(8192, dtype=torch.float16, device=dev)
+    rnd8 = torch.empty(16384, dtype=torch.float32, device=dev).uniform_(-1, 1).to(torch.float8_e4m3fn).view(torch.uint8)
+    zero8 = torch.zeros(16384, dtype=torch.uint8, device=dev)
     out = torch.empty(wg * 256, dtype=torch.float32, device=dev)
     res = {}
-    for shape, sname in ((0, "32x32x16"), (1, "16x16x32")):
-        for ops, oname in ((rnd, "random"), (zero, "zero")):
+    for shape, sname, ops_r, ops_z in ((0, "32x32x16", rnd, zero), (1, "16x16x32", rnd, zero),
+                                       (2, "32x32x64_e4m3", rnd8, zero8)):
+        for ops, oname in ((ops_r, "random"), (ops_z, "zero")):
             fl = ctypes.c_double()
 
             def launch():

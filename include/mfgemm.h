@@ -475,9 +475,11 @@ int mfg_validate_gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t ld
 /* Matrix-core ceiling probe (measurement aid for the roofline of the GEMM
  * kernels, not part of the GEMM path): `workgroups` workgroups of four
  * wavefronts each issue iters x 8 independent MFMAs from registers, with no
- * memory traffic.  shape 0: v_mfma_f32_32x32x16_f16, 1: 16x16x32_f16.
- * operands (device): 4096 dwords of 16-bit values that every wavefront loads
- * once (random bits or zeros: the sustained clock depends on them).  out
+ * memory traffic.  shape 0: v_mfma_f32_32x32x16_f16, 1: 16x16x32_f16,
+ * 2: v_mfma_scale_f32_32x32x64_f8f6f4 on E4M3 codes with unit scales (the
+ * FP8 GEMM's instruction).  operands (device): 4096 dwords of 16-bit values
+ * (shapes 0, 1) or E4M3 codes (shape 2) that every wavefront loads once
+ * (random values or zeros: the sustained clock depends on them).  out
  * (device): workgroups * 256 floats (the accumulators' sums).  flops (host,
  * may be NULL) receives the matrix flops of the launch.  Time it with
  * events on `stream`. */

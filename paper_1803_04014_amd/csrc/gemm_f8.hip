@@ -211,10 +211,21 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
     nt = nt < ntiles ? nt : ntiles - 1;
     const float* sa_row = p.sa + mt * ktiles;
     const float* sb_col = p.sb + nt;
+    // Stage t's scale values (one 128-wide scale tile per stage).  A step
+    // loads the next stage's values at its start and turns them into codes
+    // only at its end, behind a scheduling barrier: extracted at once, the
+    // codes made the wait for those loads (vmcnt 0) also wait for the stage
+    // loads in flight, at every stage.
+    auto scale_vals = [&](int64_t t, float& va, float& vb) {
+        const int64_t kt = t < KTN ? t : KTN - 1;
+        va = sa_row[kt];
+        vb = sb_col[kt * ntiles];
+    };
     auto scale_codes = [&](int64_t t, int& ca, int& cb) {
-        const int64_t kt = t < KTN ? t : KTN - 1;  // stage = one 128-wide scale tile
-        ca = e8m0_code(sa_row[kt]);
-        cb = e8m0_code(sb_col[kt * ntiles]);
+        float va, vb;
+        scale_vals(t, va, vb);
+        ca = e8m0_code(va);
+        cb = e8m0_code(vb);
     };
 
     f32x16 acc[FM][FN];
@@ -227,7 +238,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
     ld.init(p.A, p.Bt, p.lda, p.ldbt, M, N, m0, n0, wid, lane);
 #pragma unroll
     for (int s = 0; s < S; ++s) ld.load(kclamp(s), stage(s));
-    int ca, cb, na, nb;
+    int ca, cb;
+    float va, vb;
     scale_codes(0, ca, cb);
     F f[2];
     wait_vmcnt<G::LOADS * (S - 1)>();
@@ -242,7 +254,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
     };
     auto step = [&](auto ucst, int64_t t) {
         constexpr int u = decltype(ucst)::value;
-        scale_codes(t + 1, na, nb);  // next stage's scales, early
+        scale_vals(t + 1, va, vb);  // next stage's scale values, early
         f8_read<BM, BN, WM, WN, S>(stage(u), 1, wm, wn, lane, f[1]);
         mma(f[0], ca, cb);
         if constexpr (EVEN) pipe_interleave_even<G::READS, G::MFMAS>();
@@ -254,10 +266,12 @@ __global__ __launch_bounds__(64 * WM * WN) void gemmf8_pipe(GemmF8Args p, int ti
         ld.load(kclamp(t + S), stage(u));
         f8_read<BM, BN, WM, WN, S>(stage((u + 1) % S), 0, wm, wn, lane, f[0]);
         mma(f[1], ca, cb);
-        if constexpr (EVEN) pipe_interleave_even<G::READS, G::MFMAS>();
-        else pipe_interleave<G::READS, G::MFMAS>();
+        // the stage's global->LDS loads spread over the MFMAs as well: issued in
+        // one burst they back up in the texture-address unit and hold the wave
+        if constexpr (EVEN) pipe_interleave_loads_even<G::READS, G::LOADS, G::MFMAS>();
+        else pipe_interleave_loads<G::READS, G::LOADS, G::MFMAS>();
         __builtin_amdgcn_sched_barrier(0);
-        ca = na, cb = nb;
+        ca = e8m0_code(va), cb = e8m0_code(vb);
     };
     const int64_t KFULL = KTN - KTN % S;
     for (int64_t t0 = 0; t0 < KFULL; t0 += S) {

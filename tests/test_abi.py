@@ -251,7 +251,8 @@ def test_fault_inject_arguments():
 def test_probe_mfma_arguments():
     L = mfg.lib()
     f = ctypes.c_double()
-    assert L.mfg_probe_mfma(2, P, 1, 1, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_probe_mfma(3, P, 1, 1, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG
+    assert L.mfg_probe_mfma(-1, P, 1, 1, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG
     assert L.mfg_probe_mfma(0, None, 1, 1, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG
     assert L.mfg_probe_mfma(0, P, 0, 1, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG
     assert L.mfg_probe_mfma(1, P, 1, 0, P, ctypes.byref(f), None) == capi.MFG_ERR_INVALID_ARG
