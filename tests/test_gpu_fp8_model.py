@@ -3,8 +3,10 @@ seen through the library's FP8 mode (preconverted codes, tile scales 1).
 
 The instruction multiplies E4M3 codes exactly but does not add its 64
 products exactly in FP32 (448 + 2^-9 comes back as 448).  Measured over
-random codes its error stays below 2^-12 of the sum of |products|; the FP8
-parity tolerance of the other tests is derived from this figure.
+random codes its error stays below 2^-12 of the sum of |products|; the value
+already in the accumulator is added without that loss, so a dot product of
+many instructions keeps the same bound.  The FP8 parity tolerance of the
+other tests is derived from these figures.
 """
 import numpy as np
 import pytest
@@ -69,3 +71,46 @@ def test_error_below_2_to_minus_12_of_abs_sum():
     rel = np.abs(C - exact) / np.maximum(absum, 1e-300)
     print(f"max |C - exact| / sum|p| = 2^{np.log2(rel.max()):.2f}")
     assert rel.max() <= 2.0 ** -11.75
+
+
+def _draw(rng, dist, M, K, N):
+    codes = np.arange(256, dtype=np.uint8)
+    vals = oracle.e4m3_decode(codes)
+    if dist == "codes":            # every finite code equally likely (magnitudes 2^-9 .. 448)
+        pool = codes[np.isfinite(vals)]
+    else:                          # magnitudes in [1/8, 8], both signs: sums that cancel
+        pool = codes[np.isfinite(vals) & (np.abs(vals) >= 0.125) & (np.abs(vals) <= 8.0)]
+    return rng.choice(pool, size=(M, K)).astype(np.uint8), rng.choice(pool, size=(K, N)).astype(np.uint8)
+
+
+@pytest.mark.parametrize("K", [64, 1024])
+@pytest.mark.parametrize("dist", ["codes", "cancel"])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_error_bound_over_draws_and_depths(seed, dist, K):
+    """The bound the FP8 parity bar rests on, over more draws: one instruction
+    (K = 64) stays below 2^-11.75 of the sum of |products|; a dot product of 16
+    instructions accumulated in one FP32 register stays below the bar's 2^-11."""
+    rng = np.random.default_rng(100 * seed + K)
+    qa, qb = _draw(rng, dist, 128, K, 128)
+    C = _fp8_gemm(qa, qb)
+    a, b = oracle.e4m3_decode(qa), oracle.e4m3_decode(qb)
+    exact = oracle.gemm(a, b)
+    absum = oracle.gemm(np.abs(a), np.abs(b))
+    rel = np.abs(C - exact) / np.maximum(absum, 1e-300)
+    print(f"seed {seed} {dist} K={K}: max |C - exact| / sum|p| = 2^{np.log2(max(rel.max(), 2.0**-60)):.2f}")
+    assert rel.max() <= (2.0 ** -11.75 if K == 64 else 2.0 ** -11)
+
+
+def test_accumulated_value_bounds_the_next_instruction():
+    """A second instruction adding 2^-9 to an accumulator holding 448: whatever
+    the instruction keeps, the error is within 2^-12 of the dot product's sum
+    of |products| (the per-instruction bound with the accumulator counted)."""
+    qa = np.zeros((32, 128), np.uint8)
+    qb = np.zeros((128, 32), np.uint8)
+    qa[0, 0], qa[0, 64] = _code(448.0), _code(2.0 ** -9)
+    qb[0, 0], qb[64, 0] = _code(1.0), _code(1.0)
+    C = _fp8_gemm(qa, qb)
+    exact = 448.0 + 2.0 ** -9
+    print(f"448 then 2^-9 in the next instruction: C = {C[0, 0]!r}")
+    assert abs(C[0, 0] - exact) <= 2.0 ** -12 * exact
+    assert np.count_nonzero(C) == 1
