@@ -302,10 +302,12 @@ int mfg_grouped_autotune(int64_t count, const mfg_problem* problems, int mode, i
  * row i was swapped with row ipiv[i] (0-based, in order i = 0 .. n-1).
  * info (host, may be NULL): 0, or the 1-based index of the first exactly
  * zero pivot (the factorisation is then complete but U is singular).  The
- * call synchronises `stream` before it returns.
+ * call allocates (and frees) a status word and a min(n, 8192) x 8 FP32
+ * copy of the current 8-column sub-panel, and synchronises `stream` before
+ * it returns.
  * Errors: MFG_ERR_INVALID_ARG (n < 0, lda < max(1, n), NULL pointers with
- * n > 0, a mode with flags); MFG_ERR_UNSUPPORTED for n > 2^31 - 1; those
- * of mfg_gemm. */
+ * n > 0, a mode with flags); MFG_ERR_NO_MEMORY if those allocations fail;
+ * MFG_ERR_UNSUPPORTED for n > 2^31 - 1; those of mfg_gemm. */
 int mfg_lu_factor(int64_t n, float* A, int64_t lda, int32_t* ipiv, int64_t* info, int mode, void* stream);
 /* mfg_lu_solve -- B = (L U)^-1 P B in place for the n x nrhs FP32 B (device,
  * ldb >= max(1, nrhs)) with the factors and pivots of mfg_lu_factor: the

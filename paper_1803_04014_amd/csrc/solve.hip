@@ -5,7 +5,8 @@
 //
 //   LU:  right-looking blocked LU with partial pivoting of an FP32 copy of
 //        A, panels of kNb = 64 columns: the panel is factored by one
-//        workgroup (column by column: pivot search, row swap, scaling,
+//        workgroup (column by column: pivot search, row swap, scaling by
+//        the pivot's reciprocal as in LAPACK's unblocked LU,
 //        rank-1 update of the panel), its row swaps are applied to the rest
 //        of the matrix, the block row is solved with the panel's unit lower
 //        triangle (U12 = L11^-1 A12), and the trailing matrix is updated
@@ -83,9 +84,10 @@ __global__ __launch_bounds__(kPanelThreads) void lu_panel(int64_t n, float* A, i
         __syncthreads();
         const float pv = prow[c];
         if (pv != 0.0f) {
+            const float rp = 1.0f / pv;  // the column is scaled by the pivot's reciprocal
             for (int64_t r = col + 1 + tid; r < n; r += kPanelThreads) {
                 float* row = A + r * lda + j;
-                const float l = row[c] / pv;
+                const float l = row[c] * rp;
                 row[c] = l;
                 for (int cc = c + 1; cc < w; ++cc) row[cc] = __builtin_fmaf(-l, prow[cc], row[cc]);
             }
@@ -94,9 +96,10 @@ __global__ __launch_bounds__(kPanelThreads) void lu_panel(int64_t n, float* A, i
     }
 }
 
-// A narrow panel A[j:n, j:j+w] (w <= 8) held in registers for all of its
-// columns: thread t owns panel rows i = t + kP8Threads q (row j + i), q <
-// kP8Rows (so n - j <= kP8Threads kP8Rows).  One barrier per column c:
+// A narrow panel A[j:n, j:j+w] (w <= 8), copied by lu_gather8 into the
+// contiguous rows x 8 array W, held in registers for all of its columns:
+// thread t owns panel rows i = t + kP8Threads q (row j + i), q < kP8Rows (so
+// rows = n - j <= kP8Threads kP8Rows).  One barrier per column c:
 //   - each wavefront finds its largest |value| among its rows at or below the
 //     diagonal (first row on ties); the lane owning that row writes the value,
 //     the row index and the row's values to the wavefront's LDS slot, and
@@ -108,8 +111,8 @@ __global__ __launch_bounds__(kPanelThreads) void lu_panel(int64_t n, float* A, i
 // The slots alternate between two LDS buffers by column parity: a buffer is
 // written again two columns later, by threads that passed the barrier of the
 // column in between, which every thread reaches only after reading it.  Rows
-// move as two 16-byte pieces when A, lda and j allow (vec), else element by
-// element.  Same arithmetic, operation by operation, as lu_panel.
+// move in and out of W as two 16-byte pieces; lu_subpanel_post writes the
+// factored columns back.  Same arithmetic, operation by operation, as lu_panel.
 constexpr int kP8 = 8, kP8Threads = 512, kP8Rows = 16, kP8Waves = kP8Threads / 64;
 
 // One step of a (value, row) max across lanes: the partner lane given by the
@@ -122,27 +125,24 @@ __device__ __forceinline__ void p8_dpp_max(float& best, int& bi) {
 }
 
 
-__global__ __launch_bounds__(kP8Threads) void lu_panel8(int64_t n, float* A, int64_t lda, int64_t j, int w,
-                                                       int32_t* ipiv, int32_t* info, int vec) {
+__global__ __launch_bounds__(kP8Threads) void lu_panel8(int rows, float* W, int64_t j, int w, int32_t* ipiv,
+                                                       int32_t* info) {
     __shared__ float sv[2][kP8Waves];
     __shared__ int si[2][kP8Waves];
     __shared__ float srow[2][kP8Waves][kP8];
     __shared__ float sdiag[2][kP8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rows = (int)(n - j);
     float x[kP8Rows][kP8];
 #pragma unroll
     for (int q = 0; q < kP8Rows; ++q) {
         const int i = tid + kP8Threads * q;
-        const float* rp = A + (j + i) * lda + j;
-        if (i < rows && vec) {
-            const float4 u = *reinterpret_cast<const float4*>(rp), v = *reinterpret_cast<const float4*>(rp + 4);
-            x[q][0] = u.x, x[q][1] = u.y, x[q][2] = u.z, x[q][3] = u.w;
-            x[q][4] = v.x, x[q][5] = v.y, x[q][6] = v.z, x[q][7] = v.w;
-        } else {
-#pragma unroll
-            for (int c = 0; c < kP8; ++c) x[q][c] = (i < rows && c < w) ? rp[c] : 0.0f;
+        float4 u = make_float4(0.0f, 0.0f, 0.0f, 0.0f), v = u;
+        if (i < rows) {
+            const float4* rp = reinterpret_cast<const float4*>(W + (int64_t)i * kP8);
+            u = rp[0], v = rp[1];
         }
+        x[q][0] = u.x, x[q][1] = u.y, x[q][2] = u.z, x[q][3] = u.w;
+        x[q][4] = v.x, x[q][5] = v.y, x[q][6] = v.z, x[q][7] = v.w;
     }
     // (value, row) pairs: the larger value wins, the lower row on ties; rows
     // with no candidate carry (-1, rows)
@@ -225,11 +225,12 @@ __global__ __launch_bounds__(kP8Threads) void lu_panel8(int64_t n, float* A, int
             // rows below the diagonal; rows past the matrix hold zeros, take the
             // update harmlessly (or skip it with their wavefront) and are never
             // stored or chosen as pivots
+            const float rp = 1.0f / pv;
 #pragma unroll
             for (int q = 0; q < kP8Rows; ++q) {
                 if (kP8Threads * q + 64 * wave >= rows) continue;  // the wavefront's rows of slot q are all past the matrix
                 const bool below = q > 0 || tid > c;
-                const float l = x[q][c] / pv;
+                const float l = x[q][c] * rp;
                 x[q][c] = below ? l : x[q][c];
 #pragma unroll
                 for (int cc = c + 1; cc < kP8; ++cc) {
@@ -242,52 +243,90 @@ __global__ __launch_bounds__(kP8Threads) void lu_panel8(int64_t n, float* A, int
 #pragma unroll
     for (int q = 0; q < kP8Rows; ++q) {
         const int i = tid + kP8Threads * q;
-        float* rp = A + (j + i) * lda + j;
-        if (i < rows && vec) {
-            *reinterpret_cast<float4*>(rp) = make_float4(x[q][0], x[q][1], x[q][2], x[q][3]);
-            *reinterpret_cast<float4*>(rp + 4) = make_float4(x[q][4], x[q][5], x[q][6], x[q][7]);
-        } else {
-#pragma unroll
-            for (int c = 0; c < kP8; ++c)
-                if (i < rows && c < w) rp[c] = x[q][c];
+        if (i < rows) {
+            float4* rp = reinterpret_cast<float4*>(W + (int64_t)i * kP8);
+            rp[0] = make_float4(x[q][0], x[q][1], x[q][2], x[q][3]);
+            rp[1] = make_float4(x[q][4], x[q][5], x[q][6], x[q][7]);
         }
     }
 }
 
-// Row swaps ipiv[k], k in [k0, k0 + w), on the columns [c0, c1) except
-// [e0, e1), one thread per column, swaps in order.
-__global__ __launch_bounds__(256) void lu_laswp_range(float* A, int64_t lda, int64_t k0, int w, const int32_t* ipiv,
-                                                      int64_t c0, int64_t c1, int64_t e0, int64_t e1) {
-    const int64_t col = c0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (col >= c1 || (col >= e0 && col < e1)) return;
-    for (int c = 0; c < w; ++c) {
-        const int64_t k = k0 + c, p = ipiv[k];
+// The sub-panel A[j:j+rows, j:j+w] (w <= kP8) copied into W (rows x kP8,
+// row-major, 16-byte aligned; columns from w on zero) and back, one thread
+// per row over as many workgroups as it takes: A's rows are lda apart, and
+// one workgroup fetching them all (each row a separate line and page) took
+// most of the panel kernel's time.  vec: w == kP8 and A's rows 16-byte
+// aligned at column j (two 16-byte pieces per row), else element by element.
+__global__ __launch_bounds__(256) void lu_gather8(const float* A, int64_t lda, int64_t j, int rows, int w, int vec,
+                                                  float* W) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= rows) return;
+    const float* rp = A + (j + i) * lda + j;
+    float4* wp = reinterpret_cast<float4*>(W + (int64_t)i * kP8);
+    if (vec) {
+        wp[0] = *reinterpret_cast<const float4*>(rp);
+        wp[1] = *reinterpret_cast<const float4*>(rp + 4);
+    } else {
+        float v[kP8];
+#pragma unroll
+        for (int c = 0; c < kP8; ++c) v[c] = c < w ? rp[c] : 0.0f;
+        wp[0] = make_float4(v[0], v[1], v[2], v[3]);
+        wp[1] = make_float4(v[4], v[5], v[6], v[7]);
+    }
+}
+
+// After lu_panel8 on the sub-panel at column jj of the panel [c0, c1):
+// blocks 0 .. nb-1 write the factored sub-panel back from W, one thread per
+// row (as lu_gather8 read it); block nb gives each column of the panel
+// outside the sub-panel one thread, which applies the sub-panel's row swaps
+// to its column in order and, right of the sub-panel, solves the 8 rows jj ..
+// jj+7 of its column with the unit lower block L11 (U12 = L11^-1 A12, L11
+// from W).  The columns are independent, so swaps and solve need no barrier
+// between them, and the write-back touches none of their elements.
+__global__ __launch_bounds__(256) void lu_subpanel_post(float* A, int64_t lda, int64_t jj, int rows, int wi, int vec,
+                                                        const float* W, const int32_t* ipiv, int64_t c0, int64_t c1,
+                                                        int nb) {
+    if ((int)blockIdx.x < nb) {
+        const int i = blockIdx.x * 256 + threadIdx.x;
+        if (i >= rows) return;
+        float* rp = A + (jj + i) * lda + jj;
+        const float4* wp = reinterpret_cast<const float4*>(W + (int64_t)i * kP8);
+        if (vec) {
+            *reinterpret_cast<float4*>(rp) = wp[0];
+            *reinterpret_cast<float4*>(rp + 4) = wp[1];
+        } else {
+            const float4 u = wp[0], v = wp[1];
+            const float e[kP8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int c = 0; c < kP8; ++c)
+                if (c < wi) rp[c] = e[c];
+        }
+        return;
+    }
+    __shared__ float L[kP8][kP8];
+    if (threadIdx.x < kP8 * kP8) L[threadIdx.x / kP8][threadIdx.x % kP8] = W[threadIdx.x];
+    __syncthreads();
+    const int64_t col = c0 + threadIdx.x;  // c1 - c0 <= kNb < 256
+    if (col >= c1 || (col >= jj && col < jj + wi)) return;
+    for (int c = 0; c < wi; ++c) {
+        const int64_t k = jj + c, p = ipiv[k];
         if (p != k) {
             const float t = A[k * lda + col];
             A[k * lda + col] = A[p * lda + col];
             A[p * lda + col] = t;
         }
     }
-}
-
-// U12 = L11^-1 A12 for rows [j, j + kP8) and columns [j + kP8, c1): L11 the
-// unit lower kP8 x kP8 block at (j, j).
-__global__ __launch_bounds__(256) void lu_trsm8(float* A, int64_t lda, int64_t j, int64_t c1) {
-    __shared__ float L[kP8][kP8];
-    if (threadIdx.x < kP8 * kP8) L[threadIdx.x / kP8][threadIdx.x % kP8] =
-        A[(j + threadIdx.x / kP8) * lda + j + threadIdx.x % kP8];
-    __syncthreads();
-    const int64_t col = j + kP8 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (col >= c1) return;
+    if (col < jj + wi) return;  // left of the sub-panel: swaps only
+    // right of it (then wi == kP8: only the panel's last sub-panel is narrower)
     float x[kP8];
 #pragma unroll
-    for (int i = 0; i < kP8; ++i) x[i] = A[(j + i) * lda + col];
+    for (int i = 0; i < kP8; ++i) x[i] = A[(jj + i) * lda + col];
 #pragma unroll
     for (int i = 1; i < kP8; ++i)
 #pragma unroll
         for (int k = 0; k < i; ++k) x[i] = __builtin_fmaf(-L[i][k], x[k], x[i]);
 #pragma unroll
-    for (int i = 0; i < kP8; ++i) A[(j + i) * lda + col] = x[i];
+    for (int i = 0; i < kP8; ++i) A[(jj + i) * lda + col] = x[i];
 }
 
 // The panel's row swaps (rows j .. j+w-1 with ipiv[.]) on every column
@@ -431,13 +470,23 @@ bool factor_mode_ok(int mode) {
 
 }  // namespace
 
-// Blocked LU (see the file comment).  A, ipiv, info: device.  A 64-wide
-// panel is itself factored by 8-column sub-panels held in registers
-// (lu_panel8), the sub-panel's swaps applied across the panel, its block
-// row solved and the rest of the panel updated by an FP32 mfg_gemm (K = 8):
-// the same elimination, with the panel's updates blocked.  Panels taller
-// than lu_panel8 holds go column by column (lu_panel).
-int lu_factor_impl(int64_t n, float* A, int64_t lda, int32_t* ipiv, int32_t* info, int mode, hipStream_t s) {
+// Floats of the sub-panel copy W that lu_factor_impl needs (at least the
+// 8 x 8 diagonal block lu_subpanel_post reads).
+int64_t lu_scratch_floats(int64_t n) {
+    return std::max<int64_t>(std::min<int64_t>(n, (int64_t)kP8Threads * kP8Rows), kP8) * kP8;
+}
+
+// Blocked LU (see the file comment).  A, ipiv, info, W (lu_scratch_floats(n)
+// floats): device.  A 64-wide panel is itself factored by 8-column
+// sub-panels: each copied into W (lu_gather8), factored there in registers
+// (lu_panel8), written back with its swaps applied across the panel and its
+// block row solved (lu_subpanel_post), and the rest of the panel updated by
+// an FP32 mfg_gemm (K = 8, L21 read from W): the same elimination, with the
+// panel's updates blocked.  Panels taller than lu_panel8 holds go column by
+// column (lu_panel).
+
+int lu_factor_impl(int64_t n, float* A, int64_t lda, int32_t* ipiv, int32_t* info, float* W, int mode,
+                   hipStream_t s) {
     MFG_HIP_CHECK(hipMemsetAsync(info, 0, sizeof(int32_t), s));
     for (int64_t j = 0; j < n; j += kNb) {
         const int w = (int)std::min<int64_t>(kNb, n - j);
@@ -445,19 +494,20 @@ int lu_factor_impl(int64_t n, float* A, int64_t lda, int32_t* ipiv, int32_t* inf
             for (int64_t jj = j; jj < j + w; jj += kP8) {
                 const int wi = (int)std::min<int64_t>(kP8, j + w - jj);
                 const int vec = wi == kP8 && lda % 4 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0;
-                hipLaunchKernelGGL(lu_panel8, dim3(1), dim3(kP8Threads), 0, s, n, A, lda, jj, wi, ipiv, info, vec);
+                const int rows = (int)(n - jj);
+                hipLaunchKernelGGL(lu_gather8, dim3(blocks(rows, 256)), dim3(256), 0, s, A, lda, jj, rows, wi, vec, W);
                 MFG_LAUNCH_CHECK();
-                hipLaunchKernelGGL(lu_laswp_range, dim3(1), dim3(256), 0, s, A, lda, jj, wi, ipiv, j, j + w, jj,
-                                   jj + wi);
+                hipLaunchKernelGGL(lu_panel8, dim3(1), dim3(kP8Threads), 0, s, rows, W, jj, wi, ipiv, info);
+                MFG_LAUNCH_CHECK();
+                const unsigned nb = blocks(rows, 256);
+                hipLaunchKernelGGL(lu_subpanel_post, dim3(nb + 1), dim3(256), 0, s, A, lda, jj, rows, wi, vec, W, ipiv,
+                                   j, j + w, (int)nb);
                 MFG_LAUNCH_CHECK();
                 const int64_t right = j + w - (jj + wi);  // columns of the panel right of the sub-panel
-                if (right <= 0) continue;                 // wi == kP8 from here on
-                hipLaunchKernelGGL(lu_trsm8, dim3(1), dim3(256), 0, s, A, lda, jj, j + w);
-                MFG_LAUNCH_CHECK();
                 const int64_t below = n - jj - wi;
-                if (below > 0) {
-                    const int st = mfg_gemm(below, right, wi, A + (jj + wi) * lda + jj, lda, A + jj * lda + jj + wi,
-                                            lda, A + (jj + wi) * lda + jj + wi, lda, -1.0f, 1.0f, MFG_F32, (void*)s);
+                if (right > 0 && below > 0) {  // wi == kP8; L21 read from W's rows below the diagonal block
+                    const int st = mfg_gemm(below, right, wi, W + (int64_t)wi * kP8, kP8, A + jj * lda + jj + wi, lda,
+                                            A + (jj + wi) * lda + jj + wi, lda, -1.0f, 1.0f, MFG_F32, (void*)s);
                     if (st != MFG_OK) return st;
                 }
             }
@@ -564,8 +614,10 @@ int lu_factor_api(int64_t n, float* A, int64_t lda, int32_t* ipiv, int64_t* info
     if (n == 0) return MFG_OK;
     Buffers buf;
     int32_t* dinfo = nullptr;
+    float* W = nullptr;
     int st = buf.get(&dinfo, 1);
-    if (st == MFG_OK) st = lu_factor_impl(n, A, lda, ipiv, dinfo, mode, s);
+    if (st == MFG_OK) st = buf.get(&W, (size_t)lu_scratch_floats(n));
+    if (st == MFG_OK) st = lu_factor_impl(n, A, lda, ipiv, dinfo, W, mode, s);
     if (st != MFG_OK) return st;
     int32_t h = 0;
     MFG_HIP_CHECK(hipMemcpyAsync(&h, dinfo, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -609,7 +661,7 @@ int solve_ir_api(int64_t n, int64_t nrhs, const double* A, int64_t lda, const do
     if (info) *info = 0;
     if (n == 0 || nrhs == 0) return MFG_OK;
     Buffers buf;
-    float *A32 = nullptr, *v = nullptr, *d = nullptr;
+    float *A32 = nullptr, *v = nullptr, *d = nullptr, *W = nullptr;
     double *R = nullptr, *rows = nullptr, *nrm = nullptr;
     int32_t *ipiv = nullptr, *dperm = nullptr, *dinfo = nullptr;
     int st;
@@ -617,12 +669,12 @@ int solve_ir_api(int64_t n, int64_t nrhs, const double* A, int64_t lda, const do
         (st = buf.get(&d, (size_t)(n * nrhs))) != MFG_OK || (st = buf.get(&R, (size_t)(n * nrhs))) != MFG_OK ||
         (st = buf.get(&rows, (size_t)n)) != MFG_OK || (st = buf.get(&nrm, (size_t)(3 * nrhs + 1))) != MFG_OK ||
         (st = buf.get(&ipiv, (size_t)n)) != MFG_OK || (st = buf.get(&dperm, (size_t)n)) != MFG_OK ||
-        (st = buf.get(&dinfo, 1)) != MFG_OK)
+        (st = buf.get(&dinfo, 1)) != MFG_OK || (st = buf.get(&W, (size_t)lu_scratch_floats(n))) != MFG_OK)
         return st;
     // the factorisation of the FP32 copy, in the given mode
     hipLaunchKernelGGL(f64_to_f32, dim3(blocks(n * n, 256)), dim3(256), 0, s, n, n, A, lda, A32, n);
     MFG_LAUNCH_CHECK();
-    if ((st = lu_factor_impl(n, A32, n, ipiv, dinfo, mode, s)) != MFG_OK) return st;
+    if ((st = lu_factor_impl(n, A32, n, ipiv, dinfo, W, mode, s)) != MFG_OK) return st;
     int32_t hinfo = 0;
     MFG_HIP_CHECK(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
     std::vector<int32_t> perm;
