@@ -366,27 +366,40 @@ __global__ __launch_bounds__(256) void lu_trsm(int64_t n, float* A, int64_t lda,
 
 // Diagonal block [s, s+w) of the factors solved for the right-hand sides
 // V[s:s+w, 0:nrhs] in place: unit lower (forward) or upper (backward, with
-// the diagonal).  One workgroup per right-hand side, thread i holding row i;
-// each finished unknown is passed to the others through LDS.
+// the diagonal).  One wavefront per right-hand side, lane i holding row i:
+// the lane's row of the block is loaded into registers once (every load in
+// flight together), and each finished unknown reaches the other lanes by
+// readlane, so the w dependent steps wait on no memory and no barrier.
+static_assert(kNb == 64, "one wavefront per diagonal block");
 template <bool LOWER>
 __global__ __launch_bounds__(kNb) void lu_trsv_block(const float* LU, int64_t ldlu, int64_t s, int w, float* V,
                                                      int64_t ldv) {
-    __shared__ float xs[kNb];
     const int i = threadIdx.x;
     const int64_t q = blockIdx.x;
     const float* row = LU + (s + (i < w ? i : 0)) * ldlu + s;
+    float r[kNb];
+#pragma unroll
+    for (int k = 0; k < kNb; ++k) r[k] = k < w ? row[k] : 0.0f;
     float xi = i < w ? V[(s + i) * ldv + q] : 0.0f;
+    auto lane_value = [](float v, int k) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+    };
     if constexpr (LOWER) {
-        for (int k = 0; k < w; ++k) {
-            if (i == k) xs[k] = xi;
-            __syncthreads();
-            if (i > k && i < w) xi = __builtin_fmaf(-row[k], xs[k], xi);
+#pragma unroll
+        for (int k = 0; k < kNb; ++k) {
+            if (k < w) {
+                const float xk = lane_value(xi, k);
+                if (i > k && i < w) xi = __builtin_fmaf(-r[k], xk, xi);
+            }
         }
     } else {
-        for (int k = w - 1; k >= 0; --k) {
-            if (i == k) xi = xi / row[k], xs[k] = xi;
-            __syncthreads();
-            if (i < k) xi = __builtin_fmaf(-row[k], xs[k], xi);
+#pragma unroll
+        for (int k = kNb - 1; k >= 0; --k) {
+            if (k < w) {
+                if (i == k) xi = xi / r[k];
+                const float xk = lane_value(xi, k);
+                if (i < k) xi = __builtin_fmaf(-r[k], xk, xi);
+            }
         }
     }
     if (i < w) V[(s + i) * ldv + q] = xi;
