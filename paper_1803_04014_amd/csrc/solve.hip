@@ -101,9 +101,10 @@ __global__ __launch_bounds__(kPanelThreads) void lu_panel(int64_t n, float* A, i
 // thread t owns panel rows i = t + kP8Threads q (row j + i), q < kP8Rows (so
 // rows = n - j <= kP8Threads kP8Rows).  One barrier per column c:
 //   - each wavefront finds its largest |value| among its rows at or below the
-//     diagonal (first row on ties); the lane owning that row writes the value,
-//     the row index and the row's values to the wavefront's LDS slot, and
-//     thread c (owner of the diagonal row, q = 0) writes that row;
+//     diagonal (first row on ties; value and row packed in one key); lane 0
+//     writes the key and the lane owning that row the row's values to the
+//     wavefront's LDS slot, and thread c (owner of the diagonal row, q = 0)
+//     writes that row;
 //   - after the barrier every thread reduces the slots by the same rule, so
 //     each knows the pivot row p and both rows to exchange; their owners swap
 //     them in registers, and every owned row below the diagonal is scaled by
@@ -115,22 +116,36 @@ __global__ __launch_bounds__(kPanelThreads) void lu_panel(int64_t n, float* A, i
 // factored columns back.  Same arithmetic, operation by operation, as lu_panel.
 constexpr int kP8 = 8, kP8Threads = 512, kP8Rows = 16, kP8Waves = kP8Threads / 64;
 
-// One step of a (value, row) max across lanes: the partner lane given by the
-// DPP control CTRL; the larger value wins, the lower row on ties.
-template <int CTRL>
-__device__ __forceinline__ void p8_dpp_max(float& best, int& bi) {
-    const float ov = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, best), CTRL, 0xF, 0xF, false));
-    const int oi = __builtin_amdgcn_mov_dpp(bi, CTRL, 0xF, 0xF, false);
-    if (ov > best || (ov == best && oi < bi)) best = ov, bi = oi;
+// Pivot candidates as one 64-bit key: the bits of |value| (non-negative
+// floats order as their bit patterns) above the complement of the row, so
+// the larger value wins and the lower row on ties in one unsigned compare;
+// 0 is "no candidate" (a NaN, a row above the diagonal or past the matrix).
+using P8Key = unsigned long long;
+__device__ __forceinline__ P8Key p8_key(float a, int i) {
+    return ((P8Key)__builtin_bit_cast(uint32_t, a) << 32) | (P8Key)(~(uint32_t)i);
 }
 
+// One step of the key max across lanes: the partner lane given by the DPP
+// control CTRL.
+template <int CTRL>
+__device__ __forceinline__ void p8_dpp_max(P8Key& k) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)k, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(k >> 32), CTRL, 0xF, 0xF, false);
+    const P8Key o = ((P8Key)hi << 32) | lo;
+    k = o > k ? o : k;
+}
+
+__device__ __forceinline__ P8Key p8_lane_key(P8Key k, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), lane);
+    return ((P8Key)hi << 32) | lo;
+}
 
 __global__ __launch_bounds__(kP8Threads) void lu_panel8(int rows, float* W, int64_t j, int w, int32_t* ipiv,
                                                        int32_t* info) {
-    __shared__ float sv[2][kP8Waves];
-    __shared__ int si[2][kP8Waves];
-    __shared__ float srow[2][kP8Waves][kP8];
-    __shared__ float sdiag[2][kP8];
+    __shared__ P8Key skey[2][kP8Waves];
+    __shared__ __attribute__((aligned(16))) float srow[2][kP8Waves][kP8];
+    __shared__ __attribute__((aligned(16))) float sdiag[2][kP8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     float x[kP8Rows][kP8];
 #pragma unroll
@@ -144,41 +159,40 @@ __global__ __launch_bounds__(kP8Threads) void lu_panel8(int rows, float* W, int6
         x[q][0] = u.x, x[q][1] = u.y, x[q][2] = u.z, x[q][3] = u.w;
         x[q][4] = v.x, x[q][5] = v.y, x[q][6] = v.z, x[q][7] = v.w;
     }
-    // (value, row) pairs: the larger value wins, the lower row on ties; rows
-    // with no candidate carry (-1, rows)
-    auto better = [](float ov, int oi, float bv, int bx) { return ov > bv || (ov == bv && oi < bx); };
 #pragma unroll
     for (int c = 0; c < kP8; ++c) {
         if (c >= w) break;
         const int buf = c & 1;
-        float best = -1.0f;
-        int bi = rows;
+        // the thread's keys, then their max by a tree (depth 4, not a chain of 16)
+        P8Key kq[kP8Rows];
 #pragma unroll
         for (int q = 0; q < kP8Rows; ++q) {
             const int i = tid + kP8Threads * q;
             const float v = fabsf(x[q][c]);
-            const bool take = (q > 0 || i >= c) && i < rows && v > best;
-            best = take ? v : best;
-            bi = take ? i : bi;
+            kq[q] = ((q > 0 || i >= c) && i < rows && v == v) ? p8_key(v, i) : 0;
         }
+#pragma unroll
+        for (int h = kP8Rows / 2; h > 0; h /= 2)
+#pragma unroll
+            for (int q = 0; q < h; ++q) kq[q] = kq[q + h] > kq[q] ? kq[q + h] : kq[q];
+        P8Key best = kq[0];
         // wavefront reduction: DPP inside each 16-lane row (xor 1, xor 2,
         // rotate 4, rotate 8 cover the row), then the four rows by readlane
-        p8_dpp_max<0xB1>(best, bi);   // quad_perm [1,0,3,2]
-        p8_dpp_max<0x4E>(best, bi);   // quad_perm [2,3,0,1]
-        p8_dpp_max<0x124>(best, bi);  // row_ror 4
-        p8_dpp_max<0x128>(best, bi);  // row_ror 8
-        float wb = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, best), 0));
-        int wi = __builtin_amdgcn_readlane(bi, 0);
+        p8_dpp_max<0xB1>(best);   // quad_perm [1,0,3,2]
+        p8_dpp_max<0x4E>(best);   // quad_perm [2,3,0,1]
+        p8_dpp_max<0x124>(best);  // row_ror 4
+        p8_dpp_max<0x128>(best);  // row_ror 8
+        P8Key wk = p8_lane_key(best, 0);
 #pragma unroll
         for (int r = 1; r < 4; ++r) {
-            const float ob = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, best), 16 * r));
-            const int oi = __builtin_amdgcn_readlane(bi, 16 * r);
-            if (better(ob, oi, wb, wi)) wb = ob, wi = oi;
+            const P8Key o = p8_lane_key(best, 16 * r);
+            wk = o > wk ? o : wk;
         }
-        // the wavefront's candidate: value, row and the row's values, written
-        // by the lane owning it (slot wi / kP8Threads, uniform)
-        if (lane == 0) sv[buf][wave] = wb, si[buf][wave] = wi;
-        if (wi < rows && (wi & (kP8Threads - 1)) == tid) {
+        // the wavefront's candidate key and the row's values, written by the
+        // lane owning it (slot wi / kP8Threads, uniform)
+        if (lane == 0) skey[buf][wave] = wk;
+        const int wi = (int)~(uint32_t)wk;
+        if (wk != 0 && (wi & (kP8Threads - 1)) == tid) {
 #pragma unroll
             for (int q = 0; q < kP8Rows; ++q)
                 if (q == wi / kP8Threads)
@@ -189,23 +203,26 @@ __global__ __launch_bounds__(kP8Threads) void lu_panel8(int rows, float* W, int6
 #pragma unroll
             for (int cc = 0; cc < kP8; ++cc) sdiag[buf][cc] = x[0][cc];
         __syncthreads();
-        float pb = sv[buf][0];
-        int pi = si[buf][0], pw = 0;
+        P8Key pk = skey[buf][0];
+        int pw = 0;
 #pragma unroll
         for (int q = 1; q < kP8Waves; ++q) {
-            const float ov = sv[buf][q];
-            const int oi = si[buf][q];
-            if (better(ov, oi, pb, pi)) pb = ov, pi = oi, pw = q;
+            const P8Key o = skey[buf][q];
+            if (o > pk) pk = o, pw = q;
         }
-        if (pi >= rows) pi = c, pw = -1;  // no candidate (every |value| NaN): the diagonal row
+        int pi = (int)~(uint32_t)pk;
+        if (pk == 0) pi = c, pw = -1;  // no candidate (every |value| NaN): the diagonal row
         pi = __builtin_amdgcn_readfirstlane(pi);
         pw = __builtin_amdgcn_readfirstlane(pw);
-        float pr[kP8], dr[kP8];
+        // both rows read whole and at once (one LDS round trip), then chosen
+        const float4* dp = reinterpret_cast<const float4*>(sdiag[buf]);
+        const float4* sp = reinterpret_cast<const float4*>(srow[buf][pw >= 0 ? pw : 0]);
+        const float4 d0 = dp[0], d1 = dp[1], s0 = sp[0], s1 = sp[1];
+        const float dr[kP8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+        const float sr[kP8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+        float pr[kP8];
 #pragma unroll
-        for (int cc = 0; cc < kP8; ++cc) {
-            dr[cc] = sdiag[buf][cc];
-            pr[cc] = pw >= 0 ? srow[buf][pw][cc] : dr[cc];
-        }
+        for (int cc = 0; cc < kP8; ++cc) pr[cc] = pw >= 0 ? sr[cc] : dr[cc];
         if (tid == 0) ipiv[j + c] = (int32_t)(j + pi);
         if (pi != c) {  // two lanes exchange rows j + c (slot 0 of thread c) and j + pi
             if (tid == (pi & (kP8Threads - 1))) {
