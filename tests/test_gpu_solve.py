@@ -110,6 +110,19 @@ def test_solve_ir_large_on_refined_products():
     assert oracle.backward_error(A, X, B) <= 2 * TOL
 
 
+def test_solve_ir_tall_first_panel():
+    """n = 8200: the first panel has more rows than the register-resident
+    sub-panel kernel holds (8192) and is factored column by column in global
+    memory; the later panels take the sub-panel path."""
+    n = 8200
+    A = workloads.normal(79, [(n, n)])[0].astype(np.float64)
+    B = workloads.normal(80, [(n, 1)])[0].astype(np.float64)
+    dX = torch.zeros((n, 1), dtype=torch.float64, device=DEV)
+    r = mfg.solve_ir(dev(A), dev(B), dX, mode="f32", max_iter=10, tol=TOL)
+    assert r["info"] == 0 and r["berr"] <= TOL, r
+    assert oracle.backward_error(A, host(dX), B) <= 2 * TOL
+
+
 def test_singular_and_empty():
     n = 70
     A = workloads.normal(5, [(n, n)])[0].astype(np.float64)
