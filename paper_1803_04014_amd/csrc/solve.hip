@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kPanelThreads) void lu_panel(int64_t n, float* A, i
 // thread t owns panel rows i = t + kP8Threads q (row j + i), q < kP8Rows (so
 // rows = n - j <= kP8Threads kP8Rows).  One barrier per column c:
 //   - each wavefront finds its largest |value| among its rows at or below the
-//     diagonal (first row on ties; value and row packed in one key); lane 0
+//     diagonal (first row on ties; value and row then packed in one key); lane 0
 //     writes the key and the lane owning that row the row's values to the
 //     wavefront's LDS slot, and thread c (owner of the diagonal row, q = 0)
 //     writes that row;
@@ -163,19 +163,21 @@ __global__ __launch_bounds__(kP8Threads) void lu_panel8(int rows, float* W, int6
     for (int c = 0; c < kP8; ++c) {
         if (c >= w) break;
         const int buf = c & 1;
-        // the thread's keys, then their max by a tree (depth 4, not a chain of 16)
-        P8Key kq[kP8Rows];
+        // the thread's candidate: its largest |value| at or below the diagonal
+        // (fmaxf ignores NaN; the row of slot 0 above the diagonal counts as
+        // -1), then the first of its rows holding it; rows past the matrix
+        // hold zeros and come after all real rows, so they are taken only
+        // when the thread has no real candidate, and are then rejected
+        const float v0 = tid >= c ? fabsf(x[0][c]) : -1.0f;
+        float m = v0;
 #pragma unroll
-        for (int q = 0; q < kP8Rows; ++q) {
-            const int i = tid + kP8Threads * q;
-            const float v = fabsf(x[q][c]);
-            kq[q] = ((q > 0 || i >= c) && i < rows && v == v) ? p8_key(v, i) : 0;
-        }
+        for (int q = 1; q < kP8Rows; ++q) m = fmaxf(m, fabsf(x[q][c]));
+        int qs = kP8Rows;
 #pragma unroll
-        for (int h = kP8Rows / 2; h > 0; h /= 2)
-#pragma unroll
-            for (int q = 0; q < h; ++q) kq[q] = kq[q + h] > kq[q] ? kq[q + h] : kq[q];
-        P8Key best = kq[0];
+        for (int q = kP8Rows - 1; q > 0; --q) qs = fabsf(x[q][c]) == m ? q : qs;
+        qs = v0 == m ? 0 : qs;
+        const int is = tid + kP8Threads * qs;
+        P8Key best = (qs < kP8Rows && is < rows && m >= 0.0f) ? p8_key(m, is) : 0;
         // wavefront reduction: DPP inside each 16-lane row (xor 1, xor 2,
         // rotate 4, rotate 8 cover the row), then the four rows by readlane
         p8_dpp_max<0xB1>(best);   // quad_perm [1,0,3,2]

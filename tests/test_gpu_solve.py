@@ -64,6 +64,19 @@ def test_lu_pivots_match_oracle_when_unambiguous():
     assert info == 0 and np.array_equal(host(ipiv).astype(np.int64), piv)
 
 
+def test_lu_pivot_takes_first_of_equal_maxima_and_skips_nan():
+    """Column 0 holds |5| at rows 1042, 530, 1030, 700 (530 and 1042 in one
+    thread's registers, 1030 in another thread of its wavefront, 700 in another
+    wavefront) and a NaN at row 20: the pivot is row 530, the first of the
+    largest (the oracle's argmax rule), and the NaN is never taken."""
+    n = 1100
+    A = 0.1 * workloads.normal(81, [(n, n)])[0]
+    A[[1042, 530, 1030, 700], 0] = [5.0, -5.0, 5.0, -5.0]
+    A[20, 0] = np.nan
+    ipiv, _ = mfg.lu_factor(dev(A), "f32")
+    assert int(host(ipiv)[0]) == 530
+
+
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (64, 3), (130, 1), (500, 2)])
 def test_lu_solve_fp32_accuracy(n, nrhs):
     A = workloads.conditioned(900 + n, n, 100.0)
