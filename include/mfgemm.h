@@ -312,7 +312,10 @@ int mfg_lu_factor(int64_t n, float* A, int64_t lda, int32_t* ipiv, int64_t* info
 /* mfg_lu_solve -- B = (L U)^-1 P B in place for the n x nrhs FP32 B (device,
  * ldb >= max(1, nrhs)) with the factors and pivots of mfg_lu_factor: the
  * permutation, then forward and backward substitution by 64-row blocks
- * (off-diagonal updates by FP32 mfg_gemm).  Synchronises `stream`. */
+ * (each block's solve and the update of the rows still to be solved in one
+ * launch; beyond 65535 right-hand sides, the updates by FP32 mfg_gemm).
+ * Allocates an n x nrhs FP32 work array and the permutation; B's contents
+ * are unspecified after an error.  Synchronises `stream`. */
 int mfg_lu_solve(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, const int32_t* ipiv, float* B, int64_t ldb,
                  void* stream);
 /* mfg_solve_ir -- X (n x nrhs FP64, device, ldx >= max(1, nrhs)) solving

@@ -13,9 +13,9 @@
 //        A22 -= L21 U12 by one mfg_gemm call in the caller's mode (F32, F16,
 //        or a refined split: the precision of the factorisation).
 //   solve with the factors: the row permutation (one gather), then forward
-//        and backward substitution by blocks of kNb rows: a diagonal block by
-//        one workgroup, the rest of the right-hand side updated by an FP32
-//        mfg_gemm.
+//        and backward substitution by blocks of kNb rows, one launch per
+//        block: the diagonal block solved in every workgroup, the rest of
+//        the right-hand side updated in the same launch.
 //   refinement: x0 from the factors; then r = b - A x in FP64, the normwise
 //        backward error max_j |r_j|_inf / (|A|_inf |x_j|_inf + |b_j|_inf),
 //        and while it is above the tolerance a correction d solved in FP32
@@ -348,6 +348,64 @@ __global__ __launch_bounds__(256) void lu_subpanel_post(float* A, int64_t lda, i
     for (int i = 0; i < kP8; ++i) A[(jj + i) * lda + col] = x[i];
 }
 
+// The rest of the panel after a factored sub-panel [jj, jj + 8): A[r, c] -=
+// sum_k L21[r, k] U12[k, c] for rows r in [jj + 8, jj + 8 + below) and
+// columns c in [jj + 8, c1), L21 from the sub-panel's copy W (its rows from 8
+// on) and U12 = A[jj:jj+8, c] (solved by lu_subpanel_post), summed over k in
+// order by fused multiply-adds.  One thread per row and group of 8 columns
+// (threads of one row adjacent, so a row's groups are read and written
+// together).  The first group is the next sub-panel: its updated values also
+// go to that sub-panel's copy Wn (row r at r - jj - 8, columns from wn on
+// zero), so it needs no gather.  vec: A's rows 16-byte aligned at these
+// columns.
+__global__ __launch_bounds__(256) void lu_subpanel_update(float* A, int64_t lda, int64_t jj, int below, int64_t c1,
+                                                          const float* W, float* Wn, int wn, int vec) {
+    __shared__ float U[kP8][kNb];
+    const int cols = (int)(c1 - jj - kP8);  // 1 .. kNb - kP8
+    for (int e = threadIdx.x; e < kP8 * cols; e += 256) U[e / cols][e % cols] = A[(jj + e / cols) * lda + jj + kP8 + e % cols];
+    __syncthreads();
+    const int groups = (cols + kP8 - 1) / kP8;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int r = (int)(t / groups), g = (int)(t % groups);
+    if (r >= below) return;
+    const int cg = g * kP8;                          // first column of the group, from jj + 8
+    const int nc = cols - cg < kP8 ? cols - cg : kP8;  // columns in the group
+    const float4* lp = reinterpret_cast<const float4*>(W + (int64_t)(kP8 + r) * kP8);
+    const float4 l0 = lp[0], l1 = lp[1];
+    const float l[kP8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+    float* cp = A + (jj + kP8 + r) * lda + jj + kP8 + cg;
+    float acc[kP8];
+    if (vec && nc == kP8) {
+        const float4 a0 = reinterpret_cast<const float4*>(cp)[0], a1 = reinterpret_cast<const float4*>(cp)[1];
+        acc[0] = a0.x, acc[1] = a0.y, acc[2] = a0.z, acc[3] = a0.w;
+        acc[4] = a1.x, acc[5] = a1.y, acc[6] = a1.z, acc[7] = a1.w;
+    } else {
+#pragma unroll
+        for (int cc = 0; cc < kP8; ++cc) acc[cc] = cc < nc ? cp[cc] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kP8; ++k)
+#pragma unroll
+        for (int cc = 0; cc < kP8; ++cc)
+            if (cc < nc) acc[cc] = __builtin_fmaf(-l[k], U[k][cg + cc], acc[cc]);
+    if (vec && nc == kP8) {
+        reinterpret_cast<float4*>(cp)[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        reinterpret_cast<float4*>(cp)[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+    } else {
+#pragma unroll
+        for (int cc = 0; cc < kP8; ++cc)
+            if (cc < nc) cp[cc] = acc[cc];
+    }
+    if (g == 0) {
+        float4* wp = reinterpret_cast<float4*>(Wn + (int64_t)r * kP8);
+        float v[kP8];
+#pragma unroll
+        for (int cc = 0; cc < kP8; ++cc) v[cc] = cc < wn ? acc[cc] : 0.0f;
+        wp[0] = make_float4(v[0], v[1], v[2], v[3]);
+        wp[1] = make_float4(v[4], v[5], v[6], v[7]);
+    }
+}
+
 // The panel's row swaps (rows j .. j+w-1 with ipiv[.]) on every column
 // outside the panel, one thread per column, swaps in order.
 __global__ __launch_bounds__(256) void lu_laswp(int64_t n, float* A, int64_t lda, int64_t j, int w,
@@ -422,6 +480,73 @@ __global__ __launch_bounds__(kNb) void lu_trsv_block(const float* LU, int64_t ld
         }
     }
     if (i < w) V[(s + i) * ldv + q] = xi;
+}
+
+// One block step of the substitution, for right-hand side q = blockIdx.y:
+// the diagonal block [s, s+w) of the factors solved (unit lower, forward, or
+// upper with the diagonal, backward) from In[s:s+w, q] by the first
+// wavefront of every workgroup, as in lu_trsv_block (each workgroup solves
+// the same small system, so none waits for another); workgroup 0 writes the
+// solution to Out[s:s+w, q]; and the rows still to be solved (forward: below
+// the block, backward: above it), one per thread, are updated in place,
+// In[r, q] -= LU[r, s:s+w] . x, by multiply-adds in column order.  In and
+// Out are distinct arrays, so no workgroup overwrites right-hand sides
+// another still reads.  vec: LU's rows 16-byte aligned at column s.
+template <bool LOWER>
+__global__ __launch_bounds__(256) void lu_subst_step(const float* LU, int64_t ldlu, int64_t n, int64_t s, int w,
+                                                     float* In, int64_t ldi, float* Out, int64_t ldo, int vec) {
+    __shared__ float xs[kNb];
+    const int64_t q = blockIdx.y;
+    if (threadIdx.x < kNb) {
+        const int i = threadIdx.x;
+        const float* row = LU + (s + (i < w ? i : 0)) * ldlu + s;
+        float r[kNb];
+#pragma unroll
+        for (int k = 0; k < kNb; ++k) r[k] = k < w ? row[k] : 0.0f;
+        float xi = i < w ? In[(s + i) * ldi + q] : 0.0f;
+        auto lane_value = [](float v, int k) {
+            return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+        };
+        if constexpr (LOWER) {
+#pragma unroll
+            for (int k = 0; k < kNb; ++k) {
+                if (k < w) {
+                    const float xk = lane_value(xi, k);
+                    if (i > k && i < w) xi = __builtin_fmaf(-r[k], xk, xi);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = kNb - 1; k >= 0; --k) {
+                if (k < w) {
+                    if (i == k) xi = xi / r[k];
+                    const float xk = lane_value(xi, k);
+                    if (i < k) xi = __builtin_fmaf(-r[k], xk, xi);
+                }
+            }
+        }
+        xs[i] = xi;  // 0 for i >= w
+        if (blockIdx.x == 0 && i < w) Out[(s + i) * ldo + q] = xi;
+    }
+    __syncthreads();
+    const int64_t r0 = LOWER ? s + w : 0, r1 = LOWER ? n : s;
+    const int64_t rr = r0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (rr >= r1) return;
+    const float* lr = LU + rr * ldlu + s;
+    float acc = In[rr * ldi + q];
+    if (vec && w == kNb) {
+#pragma unroll
+        for (int k4 = 0; k4 < kNb / 4; ++k4) {
+            const float4 a = reinterpret_cast<const float4*>(lr)[k4];
+            acc = __builtin_fmaf(-a.x, xs[4 * k4], acc);
+            acc = __builtin_fmaf(-a.y, xs[4 * k4 + 1], acc);
+            acc = __builtin_fmaf(-a.z, xs[4 * k4 + 2], acc);
+            acc = __builtin_fmaf(-a.w, xs[4 * k4 + 3], acc);
+        }
+    } else {
+        for (int k = 0; k < w; ++k) acc = __builtin_fmaf(-lr[k], xs[k], acc);
+    }
+    In[rr * ldi + q] = acc;
 }
 
 // dst[i, :] = src[perm[i], :] (rows of nrhs FP32 values).
@@ -502,20 +627,23 @@ bool factor_mode_ok(int mode) {
 
 }  // namespace
 
-// Floats of the sub-panel copy W that lu_factor_impl needs (at least the
-// 8 x 8 diagonal block lu_subpanel_post reads).
-int64_t lu_scratch_floats(int64_t n) {
+// Floats of the two sub-panel copies that lu_factor_impl needs (each at
+// least the 8 x 8 diagonal block lu_subpanel_post reads).
+int64_t lu_copy_floats(int64_t n) {
     return std::max<int64_t>(std::min<int64_t>(n, (int64_t)kP8Threads * kP8Rows), kP8) * kP8;
 }
+int64_t lu_scratch_floats(int64_t n) { return 2 * lu_copy_floats(n); }
 
 // Blocked LU (see the file comment).  A, ipiv, info, W (lu_scratch_floats(n)
 // floats): device.  A 64-wide panel is itself factored by 8-column
-// sub-panels: each copied into W (lu_gather8), factored there in registers
-// (lu_panel8), written back with its swaps applied across the panel and its
-// block row solved (lu_subpanel_post), and the rest of the panel updated by
-// an FP32 mfg_gemm (K = 8, L21 read from W): the same elimination, with the
-// panel's updates blocked.  Panels taller than lu_panel8 holds go column by
-// column (lu_panel).
+// sub-panels: each held in a contiguous copy (the panel's first gathered by
+// lu_gather8, the others written by the previous sub-panel's update; the two
+// halves of W alternate), factored there in registers (lu_panel8), written
+// back with its swaps applied across the panel and its block row solved
+// (lu_subpanel_post), and the rest of the panel updated with K = 8
+// (lu_subpanel_update, L21 read from the copy): the same elimination, with
+// the panel's updates blocked.  Panels taller than lu_panel8 holds go column
+// by column (lu_panel).
 
 int lu_factor_impl(int64_t n, float* A, int64_t lda, int32_t* ipiv, int32_t* info, float* W, int mode,
                    hipStream_t s) {
@@ -523,24 +651,37 @@ int lu_factor_impl(int64_t n, float* A, int64_t lda, int32_t* ipiv, int32_t* inf
     for (int64_t j = 0; j < n; j += kNb) {
         const int w = (int)std::min<int64_t>(kNb, n - j);
         if (n - j <= (int64_t)kP8Threads * kP8Rows) {
+            const bool aligned = lda % 4 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0;
+            float* const copies[2] = {W, W + lu_copy_floats(n)};
+            int cur = 0;
+            bool held = false;  // copies[cur] already holds this sub-panel
             for (int64_t jj = j; jj < j + w; jj += kP8) {
                 const int wi = (int)std::min<int64_t>(kP8, j + w - jj);
-                const int vec = wi == kP8 && lda % 4 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0;
+                const int vec = wi == kP8 && aligned;
                 const int rows = (int)(n - jj);
-                hipLaunchKernelGGL(lu_gather8, dim3(blocks(rows, 256)), dim3(256), 0, s, A, lda, jj, rows, wi, vec, W);
-                MFG_LAUNCH_CHECK();
-                hipLaunchKernelGGL(lu_panel8, dim3(1), dim3(kP8Threads), 0, s, rows, W, jj, wi, ipiv, info);
+                float* const Wc = copies[cur];
+                if (!held) {
+                    hipLaunchKernelGGL(lu_gather8, dim3(blocks(rows, 256)), dim3(256), 0, s, A, lda, jj, rows, wi, vec,
+                                       Wc);
+                    MFG_LAUNCH_CHECK();
+                }
+                hipLaunchKernelGGL(lu_panel8, dim3(1), dim3(kP8Threads), 0, s, rows, Wc, jj, wi, ipiv, info);
                 MFG_LAUNCH_CHECK();
                 const unsigned nb = blocks(rows, 256);
-                hipLaunchKernelGGL(lu_subpanel_post, dim3(nb + 1), dim3(256), 0, s, A, lda, jj, rows, wi, vec, W, ipiv,
-                                   j, j + w, (int)nb);
+                hipLaunchKernelGGL(lu_subpanel_post, dim3(nb + 1), dim3(256), 0, s, A, lda, jj, rows, wi, vec, Wc,
+                                   ipiv, j, j + w, (int)nb);
                 MFG_LAUNCH_CHECK();
                 const int64_t right = j + w - (jj + wi);  // columns of the panel right of the sub-panel
-                const int64_t below = n - jj - wi;
-                if (right > 0 && below > 0) {  // wi == kP8; L21 read from W's rows below the diagonal block
-                    const int st = mfg_gemm(below, right, wi, W + (int64_t)wi * kP8, kP8, A + jj * lda + jj + wi, lda,
-                                            A + (jj + wi) * lda + jj + wi, lda, -1.0f, 1.0f, MFG_F32, (void*)s);
-                    if (st != MFG_OK) return st;
+                const int below = rows - wi;              // > 0 whenever right > 0 (then wi == kP8)
+                held = false;
+                if (right > 0 && below > 0) {
+                    const int wn = (int)std::min<int64_t>(kP8, right);
+                    const int64_t threads = (int64_t)below * ((right + kP8 - 1) / kP8);
+                    hipLaunchKernelGGL(lu_subpanel_update, dim3(blocks(threads, 256)), dim3(256), 0, s, A, lda, jj,
+                                       below, j + w, Wc, copies[cur ^ 1], wn, (int)aligned);
+                    MFG_LAUNCH_CHECK();
+                    cur ^= 1;
+                    held = true;
                 }
             }
         } else {
@@ -578,8 +719,31 @@ static int permutation(int64_t n, const int32_t* ipiv, std::vector<int32_t>& per
 }
 
 // V = U^-1 L^-1 V (V: n x nrhs FP32, already permuted), FP32.
-static int lu_substitute(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, float* V, int64_t ldv,
-                         hipStream_t s) {
+// Forward and backward substitution by blocks of kNb rows, in place in V
+// (n x nrhs).  Y (n x nrhs, ldy) is scratch: each block step reads its
+// right-hand sides from one of V and Y and writes its solution to the other
+// (forward V -> Y, backward Y -> V), with the remaining rows updated in the
+// same launch (lu_subst_step).  More right-hand sides than a grid dimension
+// holds go block by block instead: the diagonal block (lu_trsv_block), then
+// the rest of V by an FP32 mfg_gemm.
+static int lu_substitute(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, float* V, int64_t ldv, float* Y,
+                         int64_t ldy, hipStream_t s) {
+    if (nrhs <= 65535) {
+        const int vec = ldlu % 4 == 0 && reinterpret_cast<uintptr_t>(LU) % 16 == 0;
+        for (int64_t b = 0; b < n; b += kNb) {  // forward, unit lower: V -> Y
+            const int w = (int)std::min<int64_t>(kNb, n - b);
+            const dim3 g(blocks(n - b - w, 256), (unsigned)nrhs);
+            hipLaunchKernelGGL(lu_subst_step<true>, g, dim3(256), 0, s, LU, ldlu, n, b, w, V, ldv, Y, ldy, vec);
+            MFG_LAUNCH_CHECK();
+        }
+        for (int64_t b = ((n - 1) / kNb) * kNb; b >= 0; b -= kNb) {  // backward, upper: Y -> V
+            const int w = (int)std::min<int64_t>(kNb, n - b);
+            const dim3 g(blocks(b, 256), (unsigned)nrhs);
+            hipLaunchKernelGGL(lu_subst_step<false>, g, dim3(256), 0, s, LU, ldlu, n, b, w, Y, ldy, V, ldv, vec);
+            MFG_LAUNCH_CHECK();
+        }
+        return MFG_OK;
+    }
     const dim3 g((unsigned)nrhs);
     for (int64_t b = 0; b < n; b += kNb) {  // forward, unit lower
         const int w = (int)std::min<int64_t>(kNb, n - b);
@@ -604,12 +768,14 @@ static int lu_substitute(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu,
     return MFG_OK;
 }
 
-// X = (LU)^-1 P B with B, X n x nrhs FP32 (X may not alias B).
-static int lu_solve_impl(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, const int32_t* dperm, const float* B,
+// X = (LU)^-1 P B with B, X n x nrhs FP32 (X may not alias B).  B is
+// overwritten: once its rows are gathered into X it is the substitution's
+// scratch.
+static int lu_solve_impl(int64_t n, int64_t nrhs, const float* LU, int64_t ldlu, const int32_t* dperm, float* B,
                          int64_t ldb, float* X, int64_t ldx, hipStream_t s) {
     hipLaunchKernelGGL(gather_rows, dim3(blocks(n * nrhs, 256)), dim3(256), 0, s, n, nrhs, dperm, B, ldb, X, ldx);
     MFG_LAUNCH_CHECK();
-    return lu_substitute(n, nrhs, LU, ldlu, X, ldx, s);
+    return lu_substitute(n, nrhs, LU, ldlu, X, ldx, B, ldb, s);
 }
 
 }  // namespace mfg

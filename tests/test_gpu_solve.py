@@ -77,7 +77,8 @@ def test_lu_pivot_takes_first_of_equal_maxima_and_skips_nan():
     assert int(host(ipiv)[0]) == 530
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (64, 3), (130, 1), (500, 2)])
+# (70, 65539): more right-hand sides than a grid dimension holds, solved block by block
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (64, 3), (130, 1), (500, 2), (70, 65539)])
 def test_lu_solve_fp32_accuracy(n, nrhs):
     A = workloads.conditioned(900 + n, n, 100.0)
     B = workloads.normal(901 + n, [(n, nrhs)])[0].astype(np.float64)
