@@ -423,10 +423,25 @@ __global__ __launch_bounds__(256) void lu_laswp(int64_t n, float* A, int64_t lda
 }
 
 // U12 = L11^-1 A12 for the block row A[j:j+kNb, j+kNb:n] (L11 unit lower,
-// kept in LDS), one thread per column, the column in registers.
+// kept in LDS), one thread per column, the column in registers.  L11 comes
+// in as 16 loads per thread issued together, then 16 LDS stores (stored as
+// each arrived, the loads went out one latency at a time); every lane reads
+// the same entries, four per LDS read, and the multiply-adds run in the same
+// order as one entry at a time.
 __global__ __launch_bounds__(256) void lu_trsm(int64_t n, float* A, int64_t lda, int64_t j) {
-    __shared__ float L[kNb][kNb + 1];
-    for (int e = threadIdx.x; e < kNb * kNb; e += 256) L[e / kNb][e % kNb] = A[(j + e / kNb) * lda + j + e % kNb];
+    __shared__ __attribute__((aligned(16))) float L[kNb][kNb];
+    constexpr int kPer = kNb * kNb / 256;
+    float lv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        lv[u] = A[(j + e / kNb) * lda + j + e % kNb];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        L[e / kNb][e % kNb] = lv[u];
+    }
     __syncthreads();
     const int64_t col = j + kNb + (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (col >= n) return;
@@ -436,7 +451,12 @@ __global__ __launch_bounds__(256) void lu_trsm(int64_t n, float* A, int64_t lda,
 #pragma unroll
     for (int i = 1; i < kNb; ++i)
 #pragma unroll
-        for (int k = 0; k < i; ++k) x[i] = __builtin_fmaf(-L[i][k], x[k], x[i]);
+        for (int k4 = 0; k4 < i; k4 += 4) {
+            const float4 l = *reinterpret_cast<const float4*>(&L[i][k4]);
+            const float lk[4] = {l.x, l.y, l.z, l.w};
+#pragma unroll
+            for (int k = k4; k < k4 + 4 && k < i; ++k) x[i] = __builtin_fmaf(-lk[k - k4], x[k], x[i]);
+        }
 #pragma unroll
     for (int i = 0; i < kNb; ++i) A[(j + i) * lda + col] = x[i];
 }
