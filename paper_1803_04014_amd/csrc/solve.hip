@@ -271,11 +271,12 @@ __global__ __launch_bounds__(kP8Threads) void lu_panel8(int rows, float* W, int6
 }
 
 // The sub-panel A[j:j+rows, j:j+w] (w <= kP8) copied into W (rows x kP8,
-// row-major, 16-byte aligned; columns from w on zero) and back, one thread
-// per row over as many workgroups as it takes: A's rows are lda apart, and
-// one workgroup fetching them all (each row a separate line and page) took
-// most of the panel kernel's time.  vec: w == kP8 and A's rows 16-byte
-// aligned at column j (two 16-byte pieces per row), else element by element.
+// row-major, 16-byte aligned; columns from w on zero), one thread per row
+// over as many workgroups as it takes (lu_subpanel_post writes it back the
+// same way): A's rows are lda apart, and one workgroup fetching them all
+// (each row a separate line and page) took most of the panel kernel's time.
+// vec: w == kP8 and A's rows 16-byte aligned at column j (two 16-byte pieces
+// per row), else element by element.
 __global__ __launch_bounds__(256) void lu_gather8(const float* A, int64_t lda, int64_t j, int rows, int w, int vec,
                                                   float* W) {
     const int i = blockIdx.x * 256 + threadIdx.x;
