@@ -62,3 +62,23 @@ def test_fp32_input_modes(inputs, mode):
     dA, dB, dC = dev(A), dev(B), dev(C0)
     mfg.gemm(dA, dB, dC, 1.0, 1.0, mode=mode)
     _check(mode, host(dC), A, B, C0, rows)
+
+
+NR = 8000  # a multiple of 64 but not of the tiles: partial edge tiles at full scale
+
+
+@pytest.mark.parametrize("mode", ["f16", "split3"])
+def test_ragged_edges_at_scale(mode):
+    """M = N = K = 8000: the pipelined kernels (K a multiple of 64) with
+    partial tiles on the M and N edges (the last 256-row tile row holds 64
+    rows, the last 192-row one of the split kinds 128), alpha = 1.25,
+    beta = -0.5; rows from both edges and the tile boundaries before them."""
+    need_gpu()
+    A, B, C0 = workloads.uniform(3, [(NR, NR), (NR, NR), (NR, NR)])
+    rows = np.union1d(oracle.sample_rows(NR, n=12, seed=4), np.array([7679, 7680, 7871, 7872, 7935, 7936, 7999]))
+    dA, dB, dC = dev(A), dev(B), dev(C0)
+    mfg.gemm(dA, dB, dC, 1.25, -0.5, mode=mode)
+    C = host(dC)
+    print(f"ragged parity: {mode}, N = {NR}, {rows.size} sampled rows", flush=True)
+    ref = oracle.reference(mode, A, B, 1.25, -0.5, C0, rows=rows)
+    assert_parity(C[rows], ref, f"{mode} N={NR}", mode)
