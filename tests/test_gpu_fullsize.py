@@ -8,7 +8,9 @@ every launch with the library's default configuration:
   on the device (untimed there), then the GEMM on the preconverted operands;
 * the refined modes (Sec. V, Eq. 1 and Eq. 2) and BF16 from the FP32 inputs,
   split by the library; at this size the two-plane kinds run on the 192 x 128
-  tile, whose last tile row (rows 8064 .. 8191) is partial.
+  tile, whose last tile row (rows 8064 .. 8191) is partial;
+* FP8 from the FP32 inputs (128 x 128 tile quantisation on the device);
+* M = N = K = 8000, partial tiles on both edges, in F16 and SPLIT3.
 
 The oracle computes each mode's FP64 reference on sampled rows (first and last
 rows, tile edges, rows of the partial last tile row, random rows), and every
@@ -62,6 +64,28 @@ def test_fp32_input_modes(inputs, mode):
     dA, dB, dC = dev(A), dev(B), dev(C0)
     mfg.gemm(dA, dB, dC, 1.0, 1.0, mode=mode)
     _check(mode, host(dC), A, B, C0, rows)
+
+
+def test_fp8_from_fp32(inputs):
+    """FP8 from the FP32 inputs (tile quantisation on the device, the scaled
+    FP8 GEMM): the oracle quantises B and the 128-row tile rows of A that hold
+    the sampled rows (tiles are independent, so these equal the full
+    quantisation's), and the sampled rows are compared at the FP8 bar."""
+    A, B, C0, rows = inputs
+    dA, dB, dC = dev(A), dev(B), dev(C0)
+    mfg.gemm(dA, dB, dC, 1.0, 1.0, mode="fp8")
+    C = host(dC)
+    T = oracle.FP8_TILE
+    tiles = {}
+    for r in rows:
+        t = int(r) // T
+        if t not in tiles:
+            tiles[t] = oracle.fp8_quantize(A[t * T:(t + 1) * T]).deq
+    arows = np.stack([tiles[int(r) // T][int(r) % T] for r in rows])
+    bq = oracle.fp8_quantize(B).deq
+    print(f"full-size parity: fp8, N = {N}, {rows.size} sampled rows", flush=True)
+    ref = oracle.reference("fp8", arows, bq, 1.0, 1.0, C0[rows], terms=[(1.0, arows, bq)])
+    assert_parity(C[rows], ref, f"fp8 N={N}", "fp8")
 
 
 NR = 8000  # a multiple of 64 but not of the tiles: partial edge tiles at full scale
