@@ -56,6 +56,28 @@ def test_batched_equals_solo_and_oracle(mode, shape, count):
             assert_parity(got[b], ref, f"{mode} problem {b}")
 
 
+@pytest.mark.parametrize("count,size", [(65536, 16), (16384, 64), (1 << 18, 16)])
+def test_batched_bench_workloads(count, size):
+    """The benchmark's strided batches at their sizes (65536 x 16^3, 16384 x
+    64^3, and the largest 16^3 batch of its sweep, 2^18), FP16 in, FP32 out,
+    alpha = 1, beta = 0 over C filled with NaN (never read at beta = 0):
+    every output finite, every 1024th problem and the last bitwise equal to
+    its solo GEMM, every 8192nd and the last within the parity bar of the
+    oracle."""
+    A32, B32 = workloads.uniform(40 + size, [(count, size, size), (count, size, size)])
+    dA, dB = dev(A32).half(), dev(B32).half()
+    dC = torch.full((count, size, size), float("nan"), dtype=torch.float32, device=DEV)
+    mfg.gemm_batched(dA, dB, dC, 1.0, 0.0, mode="f16")
+    assert bool(torch.isfinite(dC).all())
+    got = host(dC)
+    for b in sorted(set(range(0, count, 1024)) | {count - 1}):
+        solo = host(_solo("f16", dA[b], dB[b], torch.zeros_like(dC[b]), 1.0, 0.0, True))
+        assert np.array_equal(got[b].view(np.uint32), solo.view(np.uint32)), f"problem {b} differs from solo"
+    for b in sorted(set(range(0, count, 8192)) | {count - 1}):
+        ref = oracle.reference("f16", A32[b], B32[b])
+        assert_parity(got[b], ref, f"f16 batch {count}x{size}^3 problem {b}")
+
+
 @pytest.mark.parametrize("mode,shape", [("split3", (16, 16, 40)), ("refine_a", (16, 16, 40)), ("split4", (16, 16, 40)),
                                         ("split3", (48, 64, 40)), ("split4", (64, 40, 72)),
                                         ("bf16_split3", (16, 16, 40)), ("bf16_split3", (48, 64, 40))])
@@ -215,6 +237,39 @@ def test_grouped_refined_equals_solo_and_oracle(mode):
         torch.cuda.synchronize()
         for i in range(0, count, 7):
             assert np.array_equal(host(probs[i][2]).view(np.uint32), first[i].view(np.uint32)), f"replay {rep} {i}"
+    plan.close()
+
+
+@pytest.mark.parametrize("mode", ["f16", "split3"])
+def test_grouped_bench_workload_4096(mode):
+    """The benchmark's grouped workload at its size: 4096 problems with M, N, K
+    log-uniform in [16, 512] (dimension seed 6, ld rounded up to 8), one graph
+    launch of the plan, alpha = 1, beta = 0 over C filled with NaN (never read
+    at beta = 0).  Every 16th problem bitwise equal to its solo GEMM; every
+    128th and the largest within the parity bar of the oracle's reference."""
+    count = 4096
+    dims = workloads.loguniform_dims(6, count, 16, 512)
+    two = mode != "f16"
+    probs, ops = [], []
+    for i, (m, n, k) in enumerate(dims):
+        m, n, k = int(m), int(n), int(k)
+        A, B = workloads.uniform(7000 + i, [(m, k), (k, n)])
+        dA, dB = _planes(A, -(-k // 8) * 8, two), _planes(B, -(-n // 8) * 8, two)
+        probs.append((dA, dB, torch.full((m, n), float("nan"), dtype=torch.float32, device=DEV)))
+        ops.append((A, B))
+    plan = mfg.GroupedPlan(probs, mode)
+    plan.graph_launch(1.0, 0.0)
+    torch.cuda.synchronize()
+    print(f"grouped {mode}: {count} problems, {plan.info()['work_items']} work items", flush=True)
+    for i in range(0, count, 16):
+        dA, dB, dC = probs[i]
+        solo = torch.zeros_like(dC)
+        mfg.gemm(dA, dB, solo, 1.0, 0.0, mode=mode, preconverted=True)
+        assert np.array_equal(host(dC).view(np.uint32), host(solo).view(np.uint32)), f"{mode} problem {i}"
+    sizes = [a.shape[0] * a.shape[1] * b.shape[1] for a, b in ops]
+    for i in sorted(set(range(0, count, 128)) | {int(np.argmax(sizes))}):
+        A, B = ops[i]
+        assert_parity(host(probs[i][2]), oracle.reference(mode, A, B), f"{mode} grouped problem {i}")
     plan.close()
 
 
