@@ -50,12 +50,13 @@ int pick_config_f8(int64_t M, int64_t N, int64_t K, bool vec_ok) {
     return 0;
 }
 
-// FP32: the 256 x 128 tiled kernel for large problems, 128 x 128 from
-// 128 x 128 up, the simple kernel otherwise (or for unaligned rows).
+// FP32: the 128 x 128 tiled kernel from 128 x 128 up (two wavefronts per
+// SIMD; alternating timings against 256 x 128 at N = 4096 / 8192 / 16384:
+// 122.6 / 125.1 / 126.1 against 120.8 / 122.0 / 121.7 TFLOP/s), the simple
+// kernel otherwise (or for unaligned rows).
 int pick_config_f32(int64_t M, int64_t N, int64_t K, bool vec_ok) {
     (void)K;
     if (!vec_ok) return 0;
-    if (M >= 4096 && N >= 4096) return 2;
     if (M >= 128 && N >= 128) return 1;
     return 0;
 }
