@@ -302,9 +302,9 @@ int mfg_grouped_autotune(int64_t count, const mfg_problem* problems, int mode, i
  * row i was swapped with row ipiv[i] (0-based, in order i = 0 .. n-1).
  * info (host, may be NULL): 0, or the 1-based index of the first exactly
  * zero pivot (the factorisation is then complete but U is singular).  The
- * call allocates (and frees) a status word and a min(n, 8192) x 8 FP32
- * copy of the current 8-column sub-panel, and synchronises `stream` before
- * it returns.
+ * call allocates (and frees) a status word and two min(n, 8192) x 8 FP32
+ * copies of 8-column sub-panels (they alternate), and synchronises `stream`
+ * before it returns.
  * Errors: MFG_ERR_INVALID_ARG (n < 0, lda < max(1, n), NULL pointers with
  * n > 0, a mode with flags); MFG_ERR_NO_MEMORY if those allocations fail;
  * MFG_ERR_UNSUPPORTED for n > 2^31 - 1; those of mfg_gemm. */
